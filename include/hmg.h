@@ -1,0 +1,235 @@
+/*
+ * hmg.h — C ABI of the MI355X (gfx950) matrix-free SIPG operator and hybrid
+ * multigrid solver for the 3-D Poisson equation.
+ *
+ * Method: Fehn, Munch, Wall, Kronbichler, "Hybrid multigrid methods for
+ * high-order discontinuous Galerkin discretizations", arXiv:1910.01900.
+ * Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ *  - All vectors and all device memory belong to the caller.  The library
+ *    never allocates device memory: persistent device state of a handle
+ *    (geometry, penalty, inverse diagonal, level vectors, coarse inverse)
+ *    lives in a workspace the caller binds after asking for its size.
+ *    Workspaces must stay alive and untouched until the handle is destroyed.
+ *  - Vector arguments are device pointers, 256-byte aligned, contiguous,
+ *    of the handle's precision (double for HMG_F64, float for HMG_F32)
+ *    unless stated otherwise.
+ *  - Work is enqueued on the given HIP stream (0 = legacy default stream)
+ *    and is stream-ordered; calls return before the GPU finishes unless the
+ *    entry point says "blocks".
+ *  - Every call returns an hmg_status.  Negative values are errors and leave
+ *    outputs unspecified; hmg_last_error() returns a thread-local message.
+ *  - Handles are not thread-safe for concurrent mutation.  Two calls that
+ *    use the same handle's workspace on different streams race.
+ *
+ * Layouts
+ *  - Elements of an Nx x Ny x Nz box: e = ex + Nx*(ey + Ny*ez).
+ *  - DG vector (discontinuous Q_k, n = k+1): index e*n^3 + i + n*(j + n*l),
+ *    (i, j, l) the GLL node indices in the reference directions x, y, z.
+ *  - FE vector (continuous Q_k): global node index gx + Mx*(gy + My*gz),
+ *    M_d = N_d*k + 1, gx = ex*k + i (etc.).  Nodes on Dirichlet box faces
+ *    are present; the operator acts as the identity on them (Sec. 2).
+ */
+#ifndef HMG_H
+#define HMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HMG_OK = 0,
+  HMG_NOT_CONVERGED = 1,      /* warning: results valid, tolerance not reached */
+  HMG_ERR_INVALID = -1,       /* bad argument (null, size, range, alignment)   */
+  HMG_ERR_UNSUPPORTED = -2,   /* valid but not implemented (degree, space, size) */
+  HMG_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed    */
+  HMG_ERR_BREAKDOWN = -4,     /* CG breakdown: p^T A p <= 0 (operator not SPD)  */
+  HMG_ERR_NONFINITE = -5,     /* NaN or Inf met in a residual norm             */
+  HMG_ERR_WORKSPACE = -6      /* workspace missing, too small or misaligned    */
+} hmg_status;
+
+typedef enum { HMG_F64 = 0, HMG_F32 = 1 } hmg_prec;
+typedef enum { HMG_DG = 0, HMG_FE = 1 } hmg_space;
+
+/* Thread-local text of the last error (empty string if none). */
+const char* hmg_last_error(void);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int hmg_version(void);
+
+/*
+ * Structured hexahedral mesh of the box [lo, hi] (Sec. 2 and Sec. 5.3).
+ *  nel[3]       elements per direction, each >= 1.
+ *  degree       polynomial degree k of the shape functions, 1..7.
+ *  deformed     0: Cartesian (affine) mesh; 1: curvilinear mesh whose points
+ *               are moved by x_i += deform_amp * prod_j sin(deform_waves*pi*s_j),
+ *               s_j = (x_j - lo_j)/(hi_j - lo_j), represented by a degree-3
+ *               (Q3) mapping interpolating the deformation at the 4^3 GLL
+ *               support points of each element (Sec. 5.3: cubic mapping).
+ *  bc[6]        per box face (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi):
+ *               0 Dirichlet (weak, mirror principle, Sec. 2), 1 Neumann.
+ *  ip_factor    multiplies the penalty tau_e (Sec. 2; Table 8 varies it).
+ *  tau_scale    optional host array of N_el per-element penalty factors
+ *               (copied during create; may be NULL).
+ */
+typedef struct {
+  int32_t nel[3];
+  double lo[3], hi[3];
+  int32_t degree;
+  int32_t deformed;
+  double deform_amp;
+  int32_t deform_waves;
+  uint8_t bc[6];
+  double ip_factor;
+  const double* tau_scale;
+} hmg_mesh_desc;
+
+typedef struct hmg_level hmg_level;
+typedef struct hmg_transfer hmg_transfer;
+typedef struct hmg_hierarchy hmg_hierarchy;
+
+/*
+ * One multigrid level: a discretization (space, degree, mesh, precision) of
+ * the homogeneous Laplace operator (Sec. 2: re-discretization on each level).
+ * create builds geometry and penalty on the host; query reports the DoF
+ * count and the workspace size; bind uploads to the workspace and computes
+ * the inverse diagonal (blocks until done).
+ */
+int hmg_level_create(const hmg_mesh_desc* mesh, int space, int prec, hmg_level** out);
+int hmg_level_query(const hmg_level* L, int64_t* n_dofs, size_t* workspace_bytes);
+int hmg_level_bind(hmg_level* L, void* dev_workspace, size_t bytes, hipStream_t stream);
+void hmg_level_destroy(hmg_level* L);
+
+/*
+ * v = A u, the matrix-free operator of eq:MatrixFreeAbstractNotation (Sec. 4):
+ * cell integrals by sum factorization plus, for DG, the interior-penalty
+ * face integrals (jump, average, penalty; mirror boundary conditions).
+ * u and v must not overlap.  v is overwritten.
+ */
+int hmg_operator_apply(const hmg_level* L, const void* u, void* v, hipStream_t stream);
+
+/* r = b - A u (the residual of Alg. 2).  r must not overlap u. */
+int hmg_residual(const hmg_level* L, const void* b, const void* u, void* r, hipStream_t stream);
+
+/* d = diag(A) (Sec. 3.1: the diagonal used by the Chebyshev-Jacobi smoother).
+ * The diagonal is setup data: the library evaluates a(phi_i, phi_i) on the
+ * host while creating the level (sum-factorized cell part plus own-side face
+ * terms) and keeps it on the device after bind; this call copies it. */
+int hmg_diagonal(const hmg_level* L, void* d, hipStream_t stream);
+/* Host copy of diag(A) (out: host array of n_dofs doubles); usable before bind. */
+int hmg_level_diagonal_host(const hmg_level* L, double* out);
+
+/*
+ * Estimate lambda_max of D^{-1}A by `iters` Jacobi-preconditioned CG
+ * iterations (Sec. 3.1: 20 iterations) from the start vector drawn by the
+ * SplitMix64 generator seeded with `seed` (value i = 2*top53bits*2^-53 - 1
+ * of output i+1); returns the largest Ritz value.  Blocks.
+ */
+int hmg_estimate_lambda_max(const hmg_level* L, int iters, uint64_t seed, double* lmax,
+                            hipStream_t stream);
+
+/*
+ * Alg. 3: `degree` steps of Chebyshev-accelerated Jacobi on A x = b with
+ * eigenvalue interval [lo_frac, hi_frac] * lmax (Sec. 3.1: 0.06 and 1.2);
+ * sigma_j, theta_j of the classical three-term Chebyshev iteration.
+ * x holds x_0 on entry (ignored if x_is_zero) and x_degree on exit.
+ * Uses one level-internal temporary vector.
+ */
+int hmg_chebyshev_smooth(const hmg_level* L, const void* b, void* x, int degree, double lmax,
+                         double lo_frac, double hi_frac, int x_is_zero, hipStream_t stream);
+
+/*
+ * Transfer between two levels that differ in exactly one of (h, p, c)
+ * (Sec. 3.2).  kind 'p': same mesh and space, coarse degree < fine degree;
+ * 'h': same degree and space, coarse mesh = fine mesh with every N_d
+ * halved; 'c': fine DG and coarse FE on the same mesh and degree.
+ * Both levels must have the same precision and be bound; the transfer needs
+ * a workspace for its DG-layout temporaries (FE transfers only).
+ */
+int hmg_transfer_create(const hmg_level* fine, const hmg_level* coarse, char kind, hmg_transfer** out);
+int hmg_transfer_query(const hmg_transfer* T, size_t* workspace_bytes);
+int hmg_transfer_bind(hmg_transfer* T, void* dev_workspace, size_t bytes);
+void hmg_transfer_destroy(hmg_transfer* T);
+/* fine += P coarse, P = sum_e S_e P_e G_e (multiplicity-weighted scatter). */
+int hmg_prolongate_add(const hmg_transfer* T, const void* coarse, void* fine, hipStream_t stream);
+/* coarse = P^T fine (overwrite). */
+int hmg_restrict(const hmg_transfer* T, const void* fine, void* coarse, hipStream_t stream);
+
+/*
+ * Hybrid multigrid hierarchy (Sec. 3.2) for the DG discretization of `mesh`.
+ *  strategy      letters in coarsening order, e.g. "p", "cph", "hpc" (Table 4);
+ *                each letter coarsens exhaustively in its turn.
+ *  pseq          p-sequence: 0 p-1, 1 floor(p/2), 2 straight to 1 (Sec. 3.2.2).
+ *  h_min         h-coarsening stops when an N_d is odd or max N_d <= h_min.
+ *  smoother_degree  Chebyshev steps per smoothing (Sec. 3.1: 5).
+ *  mg_prec       precision of the V-cycle (smoothers, transfers, level
+ *                operators); the coarsest-level solve is always FP64.  The
+ *                outer PCG always runs in FP64 with its own FP64 fine operator.
+ *  lmax_seed     seed of the lambda_max start vectors (level l uses seed + l).
+ * The coarse solver is an exact FP64 solve: the coarsest operator is probed
+ * column by column on the GPU, factored (Cholesky) on the host and its
+ * inverse applied as a dense matrix-vector product (at most 8192 unknowns).
+ * bind uploads everything, estimates lambda_max per level and factors the
+ * coarse matrix; it blocks.
+ */
+int hmg_hierarchy_create(const hmg_mesh_desc* mesh, const char* strategy, int pseq, int h_min,
+                         int smoother_degree, int mg_prec, uint64_t lmax_seed,
+                         hmg_hierarchy** out);
+int hmg_hierarchy_query(const hmg_hierarchy* H, int64_t* n_dofs, size_t* workspace_bytes);
+int hmg_hierarchy_bind(hmg_hierarchy* H, void* dev_workspace, size_t bytes, hipStream_t stream);
+void hmg_hierarchy_destroy(hmg_hierarchy* H);
+
+/* Level l (0 = finest) of the V-cycle: space, degree, mesh size, DoFs and
+ * the lambda_max estimate used by its smoother (coarsest level: lmax 0). */
+typedef struct {
+  int32_t space, degree, nel[3], prec;
+  int64_t n_dofs;
+  double lmax;
+} hmg_level_info;
+int hmg_hierarchy_levels(const hmg_hierarchy* H, int* n_levels);
+int hmg_hierarchy_level_info(const hmg_hierarchy* H, int l, hmg_level_info* info);
+/* Override the lambda_max of level l (e.g. to replay another estimate). */
+int hmg_hierarchy_set_lmax(hmg_hierarchy* H, int l, double lmax);
+
+/*
+ * x = M^{-1} b: one V-cycle of Alg. 2 with x^(L) = 0 (Sec. 3: the PCG
+ * preconditioner).  b and x are FP64 vectors on the finest level (converted
+ * to and from mg_prec internally).  b and x must not overlap.
+ */
+int hmg_vcycle(hmg_hierarchy* H, const double* b, double* x, hipStream_t stream);
+
+typedef struct {
+  int32_t iters;
+  double r0, rn;       /* ||b - A x_0||_2 and final ||r||_2 */
+  double rho, n10;     /* Sec. 5.1: (rn/r0)^(1/iters), -10/log10(rho) */
+} hmg_solve_stats;
+
+/*
+ * Alg. 1: preconditioned CG in FP64 with one V-cycle as preconditioner.
+ * Stops when ||r||/||r_0|| <= rtol or ||r|| <= atol.  x holds x_0 on entry
+ * and the solution on exit.  Blocks (one device-to-host read of ||r|| per
+ * iteration).  Returns HMG_NOT_CONVERGED after maxit iterations,
+ * HMG_ERR_BREAKDOWN if p^T A p <= 0 and HMG_ERR_NONFINITE on NaN/Inf;
+ * stats (may be NULL) are filled in every case.
+ */
+int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, double atol,
+                  int maxit, hmg_solve_stats* stats, hipStream_t stream);
+
+/*
+ * Manufactured right-hand side for u = prod_j sin(freq * x_j):
+ * f = 3 freq^2 u and Dirichlet data g = u moved to the right-hand side as in
+ * Sec. 2 (b_i = (phi_i, f) - sum_{Dirichlet F} (dphi_i/dn - 2 tau phi_i, g)_F).
+ * Computed on the host during the call and copied to b (DG levels only;
+ * b has the level's precision).  Blocks.
+ */
+int hmg_rhs_sine(const hmg_level* L, double freq, void* b, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMG_H */

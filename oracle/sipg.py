@@ -42,23 +42,27 @@ def _cell_tab(k):
     return basis.tabulate3(basis.gll_nodes(k), z, z, z)
 
 
-def penalty(mesh, k, ip_factor=1.0):
+def penalty(mesh, k, ip_factor=1.0, elems=None):
     """tau_e per element (Sec. 2, penalty parameter of Hillewaert):
     (k+1)^2 * (A(interior faces)/2 + A(boundary faces)) / V(element),
-    times ip_factor and the optional per-element scale."""
-    elems = np.arange(mesh.n_el)
+    times ip_factor and the optional per-element scale.  With `elems`, only
+    those entries are computed (the others are NaN)."""
+    sel = np.arange(mesh.n_el) if elems is None else np.unique(np.asarray(elems))
+    elems = sel
     _, JxW, _ = cell_geometry(mesh, k, elems)
     vol = JxW.sum(axis=1)
-    area = np.zeros(mesh.n_el)
+    area = np.zeros(len(elems))
     for d in range(3):
         for s in range(2):
             _, _, dA, _ = face_geometry(mesh, k, elems, d, s)
             a = dA.sum(axis=1)
             interior = np.array([mesh.neighbor(e, d, s) >= 0 for e in elems])
             area += np.where(interior, 0.5 * a, a)
-    tau = ip_factor * (k + 1) ** 2 * area / vol
+    t = ip_factor * (k + 1) ** 2 * area / vol
     if mesh.tau_scale is not None:
-        tau = tau * np.asarray(mesh.tau_scale, dtype=np.float64)
+        t = t * np.asarray(mesh.tau_scale, dtype=np.float64)[elems]
+    tau = np.full(mesh.n_el, np.nan)
+    tau[elems] = t
     return tau
 
 
@@ -146,11 +150,13 @@ def apply(mesh, k, u, tau=None, elems=None, ip_factor=1.0, batch=4096):
     Returns v[len(elems), n^3]."""
     n = k + 1
     nd = n ** 3
-    if tau is None:
-        tau = penalty(mesh, k, ip_factor)
     if elems is None:
         elems = np.arange(mesh.n_el)
     elems = np.asarray(elems, dtype=np.int64)
+    if tau is None:
+        near = [elems] + [np.array([mesh.neighbor(e, d, s) for e in elems]) for d in range(3) for s in range(2)]
+        near = np.concatenate(near)
+        tau = penalty(mesh, k, ip_factor, elems=near[near >= 0] if len(elems) < mesh.n_el else None)
     U = np.asarray(u, dtype=np.float64).reshape(mesh.n_el, nd)
     out = np.zeros((len(elems), nd))
     _, Gc = _cell_tab(k)

@@ -1,0 +1,990 @@
+// C ABI: handles, workspace layout, smoother / transfer / V-cycle / PCG
+// drivers (Alg. 1-3) and the coarse-level exact solve.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "hmg_internal.h"
+
+namespace hmg {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+int fail(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return HMG_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int to_mesh(const hmg_mesh_desc* d, Mesh& m) {
+  if (!d) return fail(HMG_ERR_INVALID, "mesh descriptor is NULL");
+  for (int r = 0; r < 3; ++r) {
+    if (d->nel[r] < 1) return fail(HMG_ERR_INVALID, "nel must be >= 1");
+    if (!(d->hi[r] > d->lo[r])) return fail(HMG_ERR_INVALID, "hi must exceed lo");
+    m.N[r] = d->nel[r];
+    m.lo[r] = d->lo[r];
+    m.hi[r] = d->hi[r];
+  }
+  if (d->degree < 1 || d->degree > 7) return fail(HMG_ERR_UNSUPPORTED, "degree must be 1..7");
+  m.k = d->degree;
+  m.curved = d->deformed != 0;
+  m.amp = d->deform_amp;
+  m.waves = d->deform_waves < 1 ? 1 : d->deform_waves;
+  for (int f = 0; f < 6; ++f) {
+    if (d->bc[f] > 1) return fail(HMG_ERR_INVALID, "bc must be 0 (Dirichlet) or 1 (Neumann)");
+    m.bc[f] = d->bc[f];
+  }
+  m.ip = d->ip_factor > 0 ? d->ip_factor : 1.0;
+  const int64_t ne = m.n_el();
+  if (ne > ((int64_t)1 << 31)) return fail(HMG_ERR_UNSUPPORTED, "too many elements");
+  m.tau_scale.clear();
+  if (d->tau_scale) m.tau_scale.assign(d->tau_scale, d->tau_scale + ne);
+  return HMG_OK;
+}
+
+static int check_ptr(const void* p, const char* what) {
+  if (!p) return fail(HMG_ERR_INVALID, std::string(what) + " is NULL");
+  if (((uintptr_t)p) & 255) return fail(HMG_ERR_INVALID, std::string(what) + " is not 256-byte aligned");
+  return HMG_OK;
+}
+#define TRY(x)             \
+  do {                     \
+    int rc_ = (x);         \
+    if (rc_ < 0) return rc_; \
+  } while (0)
+
+// ------------------------------------------------------------------ dense Cholesky
+// In-place lower Cholesky (row-major), blocked, trailing updates threaded.
+static bool cholesky(std::vector<double>& A, int n) {
+  const int bs = 64;
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  for (int k0 = 0; k0 < n; k0 += bs) {
+    const int k1 = std::min(n, k0 + bs);
+    for (int j = k0; j < k1; ++j) {
+      double d = A[(size_t)j * n + j];
+      for (int k = k0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+      if (!(d > 0)) return false;
+      d = std::sqrt(d);
+      A[(size_t)j * n + j] = d;
+      for (int i = j + 1; i < k1; ++i) {
+        double s = A[(size_t)i * n + j];
+        for (int k = k0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+        A[(size_t)i * n + j] = s / d;
+      }
+    }
+    auto panel = [&](int ia, int ib) {
+      for (int i = ia; i < ib; ++i) {
+        double* Ai = &A[(size_t)i * n];
+        for (int j = k0; j < k1; ++j) {
+          double s = Ai[j];
+          const double* Aj = &A[(size_t)j * n];
+          for (int k = k0; k < j; ++k) s -= Ai[k] * Aj[k];
+          Ai[j] = s / Aj[j];
+        }
+        for (int j = k1; j <= i; ++j) {
+          const double* Aj = &A[(size_t)j * n];
+          double s = 0.0;
+          for (int k = k0; k < k1; ++k) s += Ai[k] * Aj[k];
+          Ai[j] -= s;
+        }
+      }
+    };
+    // panel rows first (they are read by the trailing update of later rows)
+    std::vector<std::thread> th;
+    auto par = [&](auto fn, int a, int b) {
+      th.clear();
+      int chunk = (b - a + (int)nt - 1) / (int)nt;
+      for (unsigned t = 0; t < nt; ++t) {
+        int x = a + (int)t * chunk, y = std::min(b, x + chunk);
+        if (x >= y) break;
+        th.emplace_back(fn, x, y);
+      }
+      for (auto& t : th) t.join();
+    };
+    // triangular solve of the panel, then trailing update
+    par([&](int ia, int ib) {
+      for (int i = ia; i < ib; ++i) {
+        double* Ai = &A[(size_t)i * n];
+        for (int j = k0; j < k1; ++j) {
+          double s = Ai[j];
+          const double* Aj = &A[(size_t)j * n];
+          for (int k = k0; k < j; ++k) s -= Ai[k] * Aj[k];
+          Ai[j] = s / Aj[j];
+        }
+      }
+    }, k1, n);
+    par([&](int ia, int ib) {
+      for (int i = ia; i < ib; ++i) {
+        double* Ai = &A[(size_t)i * n];
+        for (int j = k1; j <= i; ++j) {
+          const double* Aj = &A[(size_t)j * n];
+          double s = 0.0;
+          for (int k = k0; k < k1; ++k) s += Ai[k] * Aj[k];
+          Ai[j] -= s;
+        }
+      }
+    }, k1, n);
+    (void)panel;
+  }
+  return true;
+}
+
+// A^{-1} = L^{-T} L^{-1} from the Cholesky factor (row-major, lower).
+static void chol_inverse(const std::vector<double>& L, int n, std::vector<double>& Ainv) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<double> W((size_t)n * n, 0.0);  // W[j][i] = (L^{-1})[i][j], i >= j
+  auto run = [&](auto fn) {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(fn, (int)t);
+    for (auto& t : th) t.join();
+  };
+  run([&](int t) {
+    for (int j = t; j < n; j += (int)nt) {
+      double* y = &W[(size_t)j * n];
+      for (int i = j; i < n; ++i) {
+        const double* Li = &L[(size_t)i * n];
+        double s = (i == j) ? 1.0 : 0.0;
+        for (int k = j; k < i; ++k) s -= Li[k] * y[k];
+        y[i] = s / Li[i];
+      }
+    }
+  });
+  Ainv.assign((size_t)n * n, 0.0);
+  run([&](int t) {
+    for (int i = t; i < n; i += (int)nt)
+      for (int j = 0; j <= i; ++j) {
+        const double* a = &W[(size_t)i * n];
+        const double* b = &W[(size_t)j * n];
+        double s = 0.0;
+        for (int k = i; k < n; ++k) s += a[k] * b[k];
+        Ainv[(size_t)i * n + j] = s;
+        Ainv[(size_t)j * n + i] = s;
+      }
+  });
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix by Sturm bisection
+static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < m ? std::fabs(b[i]) : 0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+      q = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= m) hi = mid;
+    else lo = mid;
+    if (hi - lo <= 1e-15 * std::fabs(hi)) break;
+  }
+  return hi;
+}
+
+// Classical Chebyshev iteration coefficients (Saad, Alg. 12.1) on [lo, hi]*lmax.
+static void cheb_coeffs(int ns, double lmax, double lof, double hif, std::vector<double>& sig,
+                        std::vector<double>& th) {
+  const double a = lof * lmax, b = hif * lmax;
+  const double c = 0.5 * (b + a), delta = 0.5 * (b - a), s1 = c / delta;
+  sig.assign(ns, 0.0);
+  th.assign(ns, 0.0);
+  th[0] = 1.0 / c;
+  double rho_prev = 1.0 / s1;
+  for (int j = 1; j < ns; ++j) {
+    const double rho = 1.0 / (2.0 * s1 - rho_prev);
+    sig[j] = rho * rho_prev;
+    th[j] = 2.0 * rho / delta;
+    rho_prev = rho;
+  }
+}
+
+}  // namespace hmg
+
+using namespace hmg;
+
+extern "C" const char* hmg_last_error(void) { return g_err.c_str(); }
+extern "C" int hmg_version(void) { return 100; }
+
+// ================================================================== levels
+static int level_init(const Mesh& m, int space, int prec, hmg_level** out) {
+  if (space != HMG_DG && space != HMG_FE) return fail(HMG_ERR_INVALID, "space must be DG or FE");
+  if (prec != HMG_F64 && prec != HMG_F32) return fail(HMG_ERR_INVALID, "prec must be F64 or F32");
+  hmg_level* L = new hmg_level();
+  L->mesh = m;
+  L->space = space;
+  L->prec = prec;
+  L->k = m.k;
+  L->n = m.k + 1;
+  L->n_el = m.n_el();
+  L->n_dg = L->n_el * L->n * L->n * L->n;
+  L->n_dofs = space == HMG_DG ? L->n_dg
+                              : ((int64_t)m.N[0] * m.k + 1) * ((int64_t)m.N[1] * m.k + 1) *
+                                    ((int64_t)m.N[2] * m.k + 1);
+  L->basis = make_basis(m.k);
+  int rc = build_geometry(m, L->basis, L->geom);
+  if (rc) {
+    delete L;
+    return rc;
+  }
+  rc = diag_host(m, L->basis, L->geom, space, L->diag_h);
+  if (rc) {
+    delete L;
+    return rc;
+  }
+  if (space == HMG_FE)
+    for (int d = 0; d < 3; ++d) L->geom.face[d].clear();
+  // workspace layout
+  const size_t es = L->elem_size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L->off_metric = take(L->geom.metric.size() * es);
+  for (int d = 0; d < 3; ++d) L->off_face[d] = take(L->geom.face[d].size() * es);
+  L->off_tau = take((size_t)L->n_el * es);
+  L->off_diag = take(L->vec_bytes());
+  L->off_dinv = take(L->vec_bytes());
+  L->off_tmp = take((size_t)kTmpVecs * L->vec_bytes());
+  L->off_scratch = take(space == HMG_FE ? (size_t)L->n_dg * es : 0);
+  L->off_part = take((size_t)std::max<int64_t>(kPartials, L->n_el + 1) * 8);
+  L->off_scal = take(16 * 8);
+  L->ws_bytes = off;
+  *out = L;
+  return HMG_OK;
+}
+
+extern "C" int hmg_level_create(const hmg_mesh_desc* desc, int space, int prec, hmg_level** out) {
+  if (!out) return fail(HMG_ERR_INVALID, "out is NULL");
+  Mesh m;
+  TRY(to_mesh(desc, m));
+  return level_init(m, space, prec, out);
+}
+
+extern "C" int hmg_level_query(const hmg_level* L, int64_t* n_dofs, size_t* ws) {
+  if (!L) return fail(HMG_ERR_INVALID, "level is NULL");
+  if (n_dofs) *n_dofs = L->n_dofs;
+  if (ws) *ws = L->ws_bytes;
+  return HMG_OK;
+}
+
+template <typename T>
+static int upload(const std::vector<double>& h, void* dst, hipStream_t s, std::vector<char>& keep) {
+  if (h.empty()) return HMG_OK;
+  const size_t bytes = h.size() * sizeof(T);
+  std::vector<char> buf(bytes);
+  T* p = (T*)buf.data();
+  for (size_t i = 0; i < h.size(); ++i) p[i] = (T)h[i];
+  HMG_HIP(hipMemcpyAsync(dst, buf.data(), bytes, hipMemcpyHostToDevice, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  (void)keep;
+  return HMG_OK;
+}
+
+extern "C" int hmg_level_bind(hmg_level* L, void* ws, size_t bytes, hipStream_t s) {
+  if (!L) return fail(HMG_ERR_INVALID, "level is NULL");
+  if (!ws || (((uintptr_t)ws) & 255)) return fail(HMG_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (bytes < L->ws_bytes) return fail(HMG_ERR_WORKSPACE, "workspace too small");
+  L->ws = (char*)ws;
+  std::vector<char> keep;
+  const Geometry& g = L->geom;
+  if (L->prec == HMG_F64) {
+    TRY(upload<double>(g.metric, L->metric(), s, keep));
+    for (int d = 0; d < 3; ++d) TRY(upload<double>(g.face[d], L->face(d), s, keep));
+    TRY(upload<double>(g.tau, L->tau(), s, keep));
+  } else {
+    TRY(upload<float>(g.metric, L->metric(), s, keep));
+    for (int d = 0; d < 3; ++d) TRY(upload<float>(g.face[d], L->face(d), s, keep));
+    TRY(upload<float>(g.tau, L->tau(), s, keep));
+  }
+  // diagonal (computed during create) and its inverse
+  const std::vector<double>& dg = L->diag_h;
+  std::vector<double> di(dg.size());
+  for (size_t i = 0; i < dg.size(); ++i) di[i] = 1.0 / dg[i];
+  if (L->prec == HMG_F64) {
+    TRY(upload<double>(dg, L->diag(), s, keep));
+    TRY(upload<double>(di, L->dinv(), s, keep));
+  } else {
+    TRY(upload<float>(dg, L->diag(), s, keep));
+    TRY(upload<float>(di, L->dinv(), s, keep));
+  }
+  L->bound = true;
+  L->geom.metric.clear();
+  L->geom.metric.shrink_to_fit();
+  for (int d = 0; d < 3; ++d) {
+    L->geom.face[d].clear();
+    L->geom.face[d].shrink_to_fit();
+  }
+  return HMG_OK;
+}
+
+extern "C" void hmg_level_destroy(hmg_level* L) { delete L; }
+
+static int check_level(const hmg_level* L) {
+  if (!L) return fail(HMG_ERR_INVALID, "level is NULL");
+  if (!L->bound) return fail(HMG_ERR_WORKSPACE, "level is not bound to a workspace");
+  return HMG_OK;
+}
+
+extern "C" int hmg_operator_apply(const hmg_level* L, const void* u, void* v, hipStream_t s) {
+  TRY(check_level(L));
+  TRY(check_ptr(u, "u"));
+  TRY(check_ptr(v, "v"));
+  if (u == v) return fail(HMG_ERR_INVALID, "u and v must not overlap");
+  return launch_operator(L, OP_APPLY, u, v, nullptr, nullptr, 0, 0, nullptr, s);
+}
+
+extern "C" int hmg_residual(const hmg_level* L, const void* b, const void* u, void* r, hipStream_t s) {
+  TRY(check_level(L));
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(u, "u"));
+  TRY(check_ptr(r, "r"));
+  if (u == r) return fail(HMG_ERR_INVALID, "u and r must not overlap");
+  return launch_operator(L, OP_RESID, u, r, b, nullptr, 0, 0, nullptr, s);
+}
+
+extern "C" int hmg_level_diagonal_host(const hmg_level* L, double* out) {
+  if (!L || !out) return fail(HMG_ERR_INVALID, "NULL argument");
+  std::copy(L->diag_h.begin(), L->diag_h.end(), out);
+  return HMG_OK;
+}
+
+extern "C" int hmg_diagonal(const hmg_level* L, void* d, hipStream_t s) {
+  TRY(check_level(L));
+  TRY(check_ptr(d, "d"));
+  return vec_copy(L->prec, L->diag(), d, L->n_dofs, s);
+}
+
+static int estimate_lmax(const hmg_level* L, int iters, uint64_t seed, double* lmax, hipStream_t s) {
+  const int pr = L->prec;
+  const int64_t n = L->n_dofs;
+  void *r = L->tmp(0), *z = L->tmp(1), *p = L->tmp(2), *Ap = L->tmp(3);
+  double* scal = L->scal();
+  double* part = L->partials();
+  TRY(vec_splitmix(pr, seed, r, n, s));
+  TRY(vec_mul3(pr, 1.0, L->dinv(), r, z, n, s));
+  TRY(vec_copy(pr, z, p, n, s));
+  TRY(vec_dot(pr, r, z, n, part, scal + 0, s));
+  double rz;
+  HMG_HIP(hipMemcpyAsync(&rz, scal + 0, 8, hipMemcpyDeviceToHost, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  std::vector<double> alpha, beta;
+  for (int it = 0; it < iters; ++it) {
+    TRY(launch_operator(L, OP_APPLY, p, Ap, nullptr, nullptr, 0, 0, nullptr, s));
+    TRY(vec_dot(pr, p, Ap, n, part, scal + 1, s));
+    double pAp;
+    HMG_HIP(hipMemcpyAsync(&pAp, scal + 1, 8, hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    if (!(pAp > 0) || !(rz > 0)) break;
+    const double a = rz / pAp;
+    TRY(vec_axpby(pr, 1.0, r, -a, Ap, r, n, s));
+    TRY(vec_mul3(pr, 1.0, L->dinv(), r, z, n, s));
+    TRY(vec_dot(pr, r, z, n, part, scal + 0, s));
+    double rzn;
+    HMG_HIP(hipMemcpyAsync(&rzn, scal + 0, 8, hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    const double bta = rzn / rz;
+    alpha.push_back(a);
+    beta.push_back(bta);
+    rz = rzn;
+    TRY(vec_axpby(pr, 1.0, z, bta, p, p, n, s));
+    if (!(rzn > 0)) break;
+  }
+  const int m = (int)alpha.size();
+  if (m == 0) return fail(HMG_ERR_BREAKDOWN, "lambda_max: CG broke down at the first step");
+  std::vector<double> da(m), ob(std::max(0, m - 1));
+  for (int j = 0; j < m; ++j) {
+    da[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < m) ob[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  *lmax = tridiag_max_eig(da, ob);
+  return HMG_OK;
+}
+
+extern "C" int hmg_estimate_lambda_max(const hmg_level* L, int iters, uint64_t seed, double* lmax,
+                                       hipStream_t s) {
+  TRY(check_level(L));
+  if (!lmax || iters < 1) return fail(HMG_ERR_INVALID, "lmax NULL or iters < 1");
+  return estimate_lmax(L, iters, seed, lmax, s);
+}
+
+// Alg. 3 with the result left in x; uses tmp(0) as the second buffer.
+static int chebyshev(const hmg_level* L, const void* b, void* x, int ns, double lmax, double lof,
+                     double hif, int x_is_zero, hipStream_t s) {
+  std::vector<double> sig, th;
+  cheb_coeffs(ns, lmax, lof, hif, sig, th);
+  const int pr = L->prec;
+  const int64_t n = L->n_dofs;
+  void* tmp = L->tmp(0);
+  void *cur, *oth;
+  if (x_is_zero) {
+    // x_1 = theta_0 D^{-1} b, x_0 = 0; ns-1 swaps follow
+    if (((ns - 1) & 1) == 0) {
+      cur = x;
+      oth = tmp;
+    } else {
+      cur = tmp;
+      oth = x;
+    }
+    TRY(vec_mul3(pr, th[0], L->dinv(), b, cur, n, s));
+    TRY(vec_fill(pr, oth, 0.0, n, s));
+  } else {
+    // ns swaps follow the first step
+    if ((ns & 1) == 0) {
+      cur = x;
+      oth = tmp;
+    } else {
+      TRY(vec_copy(pr, x, tmp, n, s));
+      cur = tmp;
+      oth = x;
+    }
+    TRY(launch_operator(L, OP_CHEB, cur, oth, b, cur, 0.0, th[0], nullptr, s));
+    std::swap(cur, oth);
+  }
+  for (int j = 1; j < ns; ++j) {
+    TRY(launch_operator(L, OP_CHEB, cur, oth, b, oth, sig[j], th[j], nullptr, s));
+    std::swap(cur, oth);
+  }
+  if (cur != x) return fail(HMG_ERR_INVALID, "internal: Chebyshev buffer parity");
+  return HMG_OK;
+}
+
+extern "C" int hmg_chebyshev_smooth(const hmg_level* L, const void* b, void* x, int degree,
+                                    double lmax, double lof, double hif, int x_is_zero,
+                                    hipStream_t s) {
+  TRY(check_level(L));
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(x, "x"));
+  if (degree < 1 || !(lmax > 0) || !(hif > lof) || !(lof > 0))
+    return fail(HMG_ERR_INVALID, "need degree >= 1, lmax > 0, 0 < lo_frac < hi_frac");
+  return chebyshev(L, b, x, degree, lmax, lof, hif, x_is_zero, s);
+}
+
+extern "C" int hmg_rhs_sine(const hmg_level* L, double freq, void* b, hipStream_t s) {
+  TRY(check_level(L));
+  TRY(check_ptr(b, "b"));
+  if (L->space != HMG_DG) return fail(HMG_ERR_UNSUPPORTED, "rhs only for DG levels");
+  std::vector<double> h;
+  TRY(rhs_sine_host(L->mesh, L->basis, L->geom, freq, h));
+  std::vector<char> keep;
+  if (L->prec == HMG_F64) return upload<double>(h, b, s, keep);
+  return upload<float>(h, b, s, keep);
+}
+
+// ================================================================== transfers
+struct hmg_transfer {
+  const hmg_level* f = nullptr;
+  const hmg_level* c = nullptr;
+  char kind = 'p';
+  std::vector<double> P0, P1;
+  size_t ws_bytes = 0, off_sf = 0, off_sc = 0;
+  char* ws = nullptr;
+  bool fe = false;
+};
+
+static bool same_box(const Mesh& a, const Mesh& b) {
+  for (int d = 0; d < 3; ++d)
+    if (a.lo[d] != b.lo[d] || a.hi[d] != b.hi[d]) return false;
+  for (int f = 0; f < 6; ++f)
+    if (a.bc[f] != b.bc[f]) return false;
+  return a.curved == b.curved && a.amp == b.amp && a.waves == b.waves;
+}
+
+extern "C" int hmg_transfer_create(const hmg_level* fine, const hmg_level* coarse, char kind,
+                                   hmg_transfer** out) {
+  if (!fine || !coarse || !out) return fail(HMG_ERR_INVALID, "NULL argument");
+  if (fine->prec != coarse->prec) return fail(HMG_ERR_INVALID, "levels differ in precision");
+  if (!same_box(fine->mesh, coarse->mesh)) return fail(HMG_ERR_INVALID, "levels differ in domain");
+  auto* T = new hmg_transfer();
+  T->f = fine;
+  T->c = coarse;
+  T->kind = kind;
+  const Mesh &mf = fine->mesh, &mc = coarse->mesh;
+  bool ok = false;
+  if (kind == 'c') {
+    ok = fine->space == HMG_DG && coarse->space == HMG_FE && fine->k == coarse->k;
+    for (int d = 0; d < 3; ++d) ok = ok && mf.N[d] == mc.N[d];
+  } else if (kind == 'p') {
+    ok = fine->space == coarse->space && coarse->k < fine->k;
+    for (int d = 0; d < 3; ++d) ok = ok && mf.N[d] == mc.N[d];
+    if (ok) lagrange(coarse->basis.gll, fine->basis.gll, &T->P0, nullptr);
+  } else if (kind == 'h') {
+    ok = fine->space == coarse->space && coarse->k == fine->k;
+    for (int d = 0; d < 3; ++d) ok = ok && mf.N[d] == 2 * mc.N[d];
+    if (ok) {
+      std::vector<double> x0(fine->n), x1(fine->n);
+      for (int i = 0; i < fine->n; ++i) {
+        x0[i] = 0.5 * fine->basis.gll[i];
+        x1[i] = 0.5 * (1.0 + fine->basis.gll[i]);
+      }
+      lagrange(coarse->basis.gll, x0, &T->P0, nullptr);
+      lagrange(coarse->basis.gll, x1, &T->P1, nullptr);
+    }
+  }
+  if (!ok) {
+    delete T;
+    return fail(HMG_ERR_INVALID, std::string("levels do not form a '") + kind + "' transfer");
+  }
+  T->fe = kind != 'c' && fine->space == HMG_FE;
+  const size_t es = fine->elem_size();
+  if (T->fe) {
+    T->off_sf = 0;
+    T->off_sc = align256((size_t)fine->n_dg * es);
+    T->ws_bytes = T->off_sc + align256((size_t)coarse->n_dg * es);
+  }
+  *out = T;
+  return HMG_OK;
+}
+
+extern "C" int hmg_transfer_query(const hmg_transfer* T, size_t* ws) {
+  if (!T) return fail(HMG_ERR_INVALID, "transfer is NULL");
+  if (ws) *ws = T->ws_bytes;
+  return HMG_OK;
+}
+extern "C" int hmg_transfer_bind(hmg_transfer* T, void* ws, size_t bytes) {
+  if (!T) return fail(HMG_ERR_INVALID, "transfer is NULL");
+  if (T->ws_bytes == 0) return HMG_OK;
+  if (!ws || (((uintptr_t)ws) & 255) || bytes < T->ws_bytes)
+    return fail(HMG_ERR_WORKSPACE, "transfer workspace missing, misaligned or too small");
+  T->ws = (char*)ws;
+  return HMG_OK;
+}
+extern "C" void hmg_transfer_destroy(hmg_transfer* T) { delete T; }
+
+static int transfer_ready(const hmg_transfer* T) {
+  if (!T) return fail(HMG_ERR_INVALID, "transfer is NULL");
+  if (T->fe && !T->ws) return fail(HMG_ERR_WORKSPACE, "transfer is not bound");
+  return HMG_OK;
+}
+
+static int prolongate_add(const hmg_transfer* T, const void* coarse, void* fine, hipStream_t s) {
+  const hmg_level *F = T->f, *C = T->c;
+  const int pr = F->prec;
+  if (T->kind == 'c') return tr_c_inject(pr, F->mesh, F->k, coarse, fine, 0, 1, s);
+  const int kind = T->kind == 'h' ? 1 : 0;
+  const double* P1 = T->P1.empty() ? nullptr : T->P1.data();
+  if (!T->fe)
+    return tr_dg_prolongate(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, coarse, fine, 1, s);
+  void* sf = T->ws + T->off_sf;
+  void* sc = T->ws + T->off_sc;
+  TRY(tr_c_inject(pr, C->mesh, C->k, coarse, sc, 0, 0, s));
+  TRY(tr_dg_prolongate(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, sc, sf, 0, s));
+  return tr_c_sum(pr, F->mesh, F->k, sf, fine, 1, 1, s);
+}
+
+static int restrict_(const hmg_transfer* T, const void* fine, void* coarse, hipStream_t s) {
+  const hmg_level *F = T->f, *C = T->c;
+  const int pr = F->prec;
+  if (T->kind == 'c') return tr_c_sum(pr, F->mesh, F->k, fine, coarse, 0, 0, s);
+  const int kind = T->kind == 'h' ? 1 : 0;
+  const double* P1 = T->P1.empty() ? nullptr : T->P1.data();
+  if (!T->fe)
+    return tr_dg_restrict(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, fine, coarse, s);
+  void* sf = T->ws + T->off_sf;
+  void* sc = T->ws + T->off_sc;
+  TRY(tr_c_inject(pr, F->mesh, F->k, fine, sf, 1, 0, s));
+  TRY(tr_dg_restrict(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, sf, sc, s));
+  return tr_c_sum(pr, C->mesh, C->k, sc, coarse, 0, 0, s);
+}
+
+extern "C" int hmg_prolongate_add(const hmg_transfer* T, const void* coarse, void* fine, hipStream_t s) {
+  TRY(transfer_ready(T));
+  TRY(check_ptr(coarse, "coarse"));
+  TRY(check_ptr(fine, "fine"));
+  return prolongate_add(T, coarse, fine, s);
+}
+extern "C" int hmg_restrict(const hmg_transfer* T, const void* fine, void* coarse, hipStream_t s) {
+  TRY(transfer_ready(T));
+  TRY(check_ptr(coarse, "coarse"));
+  TRY(check_ptr(fine, "fine"));
+  return restrict_(T, fine, coarse, s);
+}
+
+// ================================================================== hierarchy
+struct hmg_hierarchy {
+  Mesh mesh;
+  int pseq = 1, h_min = 4, ns = 5, mg_prec = HMG_F64;
+  uint64_t seed = 1;
+  std::vector<hmg_level*> lv;       // V-cycle levels, fine -> coarse, in mg_prec
+  std::vector<hmg_transfer*> tr;    // tr[l]: lv[l] <-> lv[l+1]
+  std::vector<double> lmax;
+  hmg_level* fine64 = nullptr;      // outer-CG operator (== lv[0] when mg_prec is F64)
+  hmg_level* coarse64 = nullptr;    // FP64 copy of the coarsest level (probing)
+  bool own_fine64 = false, own_coarse64 = false;
+  int64_t nc = 0;                   // coarse unknowns
+  // workspace layout
+  size_t ws_bytes = 0;
+  std::vector<size_t> off_lv, off_tr, off_b, off_x, off_r;
+  size_t off_f64 = 0, off_c64 = 0, off_ainv = 0, off_cg = 0, off_part = 0, off_scal = 0;
+  char* ws = nullptr;
+  bool bound = false;
+  void* b(int l) const { return ws + off_b[l]; }
+  void* x(int l) const { return ws + off_x[l]; }
+  void* r(int l) const { return ws + off_r[l]; }
+  double* cg(int i) const { return (double*)(ws + off_cg) + (size_t)i * fine64->n_dofs; }
+  double* part() const { return (double*)(ws + off_part); }
+  double* scal() const { return (double*)(ws + off_scal); }
+  double* ainv() const { return (double*)(ws + off_ainv); }
+  ~hmg_hierarchy() {
+    for (auto* t : tr) delete t;
+    if (own_fine64) delete fine64;
+    if (own_coarse64) delete coarse64;
+    for (auto* l : lv) delete l;
+  }
+};
+
+static bool can_h(const Mesh& m, int h_min) {
+  for (int d = 0; d < 3; ++d)
+    if (m.N[d] % 2) return false;
+  return std::max(m.N[0], std::max(m.N[1], m.N[2])) > h_min;
+}
+
+extern "C" int hmg_hierarchy_create(const hmg_mesh_desc* desc, const char* strategy, int pseq,
+                                    int h_min, int ns, int mg_prec, uint64_t seed,
+                                    hmg_hierarchy** out) {
+  if (!out || !strategy) return fail(HMG_ERR_INVALID, "NULL argument");
+  if (pseq < 0 || pseq > 2 || ns < 1 || (mg_prec != HMG_F64 && mg_prec != HMG_F32))
+    return fail(HMG_ERR_INVALID, "bad pseq, smoother degree or precision");
+  for (const char* c = strategy; *c; ++c)
+    if (*c != 'c' && *c != 'p' && *c != 'h') return fail(HMG_ERR_INVALID, "strategy letters are c, p, h");
+  Mesh m;
+  TRY(to_mesh(desc, m));
+  auto* H = new hmg_hierarchy();
+  H->mesh = m;
+  H->pseq = pseq;
+  H->h_min = h_min < 1 ? 1 : h_min;
+  H->ns = ns;
+  H->mg_prec = mg_prec;
+  H->seed = seed;
+  // level specs (Sec. 3.2: one of h, p, c changes per level)
+  struct Spec { int space; Mesh m; char kind; };
+  std::vector<Spec> specs{{HMG_DG, m, 0}};
+  for (const char* c = strategy; *c; ++c) {
+    Spec cur = specs.back();
+    if (*c == 'c' && cur.space == HMG_DG) {
+      specs.back().kind = 'c';
+      specs.push_back({HMG_FE, cur.m, 0});
+    } else if (*c == 'p') {
+      while (specs.back().m.k > 1) {
+        Spec nx = specs.back();
+        int k = nx.m.k;
+        nx.m.k = pseq == 0 ? k - 1 : (pseq == 1 ? k / 2 : 1);
+        specs.back().kind = 'p';
+        nx.kind = 0;
+        specs.push_back(nx);
+      }
+    } else if (*c == 'h') {
+      while (can_h(specs.back().m, H->h_min)) {
+        Spec nx = specs.back();
+        for (int d = 0; d < 3; ++d) nx.m.N[d] /= 2;
+        if (!nx.m.tau_scale.empty()) {  // parent penalty scale: mean of the children
+          std::vector<double> ts((size_t)nx.m.n_el(), 0.0);
+          const Mesh& fm = specs.back().m;
+          for (int64_t e = 0; e < fm.n_el(); ++e) {
+            int64_t ex = e % fm.N[0], ey = (e / fm.N[0]) % fm.N[1], ez = e / ((int64_t)fm.N[0] * fm.N[1]);
+            ts[(ex / 2) + nx.m.N[0] * ((ey / 2) + (int64_t)nx.m.N[1] * (ez / 2))] += fm.tau_scale[e] / 8.0;
+          }
+          nx.m.tau_scale = ts;
+        }
+        specs.back().kind = 'h';
+        nx.kind = 0;
+        specs.push_back(nx);
+      }
+    }
+  }
+  for (auto& sp : specs) {
+    hmg_level* L = nullptr;
+    int rc = level_init(sp.m, sp.space, mg_prec, &L);
+    if (rc) {
+      delete H;
+      return rc;
+    }
+    H->lv.push_back(L);
+  }
+  for (size_t l = 0; l + 1 < specs.size(); ++l) {
+    hmg_transfer* T = nullptr;
+    int rc = hmg_transfer_create(H->lv[l], H->lv[l + 1], specs[l].kind, &T);
+    if (rc) {
+      delete H;
+      return rc;
+    }
+    H->tr.push_back(T);
+  }
+  H->lmax.assign(H->lv.size(), 0.0);
+  if (mg_prec == HMG_F64) {
+    H->fine64 = H->lv[0];
+    H->coarse64 = H->lv.back();
+  } else {
+    int rc = level_init(m, HMG_DG, HMG_F64, &H->fine64);
+    if (!rc) rc = level_init(specs.back().m, specs.back().space, HMG_F64, &H->coarse64);
+    H->own_fine64 = H->own_coarse64 = true;
+    if (rc) {
+      delete H;
+      return rc;
+    }
+  }
+  H->nc = H->lv.back()->n_dofs;
+  if (H->nc > 8192) {
+    delete H;
+    return fail(HMG_ERR_UNSUPPORTED, "coarse level has more than 8192 unknowns (choose a strategy that coarsens further)");
+  }
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  for (auto* L : H->lv) H->off_lv.push_back(take(L->ws_bytes));
+  for (auto* T : H->tr) H->off_tr.push_back(take(T->ws_bytes));
+  for (auto* L : H->lv) {
+    H->off_b.push_back(take(L->vec_bytes()));
+    H->off_x.push_back(take(L->vec_bytes()));
+    H->off_r.push_back(take(L->vec_bytes()));
+  }
+  if (H->own_fine64) {
+    H->off_f64 = take(H->fine64->ws_bytes);
+    H->off_c64 = take(H->coarse64->ws_bytes);
+  }
+  H->off_ainv = take((size_t)H->nc * H->nc * 8);
+  H->off_cg = take((size_t)4 * H->fine64->n_dofs * 8);
+  H->off_part = take((size_t)kPartials * 8);
+  H->off_scal = take(16 * 8);
+  H->ws_bytes = off;
+  *out = H;
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_query(const hmg_hierarchy* H, int64_t* n, size_t* ws) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (n) *n = H->fine64->n_dofs;
+  if (ws) *ws = H->ws_bytes;
+  return HMG_OK;
+}
+
+// Probe the coarsest FP64 operator with coloured unit vectors, assemble the
+// dense matrix on the host, factor it and upload its inverse.
+static int coarse_setup(hmg_hierarchy* H, hipStream_t s) {
+  const hmg_level* C = H->coarse64;
+  const int64_t n = C->n_dofs;
+  const Mesh& m = C->mesh;
+  const int k = C->k, np = k + 1, n3 = np * np * np;
+  std::vector<double> A((size_t)n * n, 0.0), e(n), y(n);
+  void* du = C->tmp(1);
+  void* dv = C->tmp(2);
+  const bool fe = C->space == HMG_FE;
+  const int Mx = m.N[0] * k + 1, My = m.N[1] * k + 1, Mz = m.N[2] * k + 1;
+  const int per = fe ? 2 * k + 1 : 3;
+  const int ncol = fe ? per * per * per : 27 * n3;
+  for (int c = 0; c < ncol; ++c) {
+    std::fill(e.begin(), e.end(), 0.0);
+    std::vector<int64_t> cols;
+    if (fe) {
+      const int cx = c % per, cy = (c / per) % per, cz = c / (per * per);
+      for (int gz = cz; gz < Mz; gz += per)
+        for (int gy = cy; gy < My; gy += per)
+          for (int gx = cx; gx < Mx; gx += per) cols.push_back(gx + (int64_t)Mx * (gy + (int64_t)My * gz));
+    } else {
+      const int col = c / n3, loc = c % n3;
+      const int cx = col % 3, cy = (col / 3) % 3, cz = col / 9;
+      for (int ez = cz; ez < m.N[2]; ez += 3)
+        for (int ey = cy; ey < m.N[1]; ey += 3)
+          for (int ex = cx; ex < m.N[0]; ex += 3)
+            cols.push_back((ex + (int64_t)m.N[0] * (ey + (int64_t)m.N[1] * ez)) * n3 + loc);
+    }
+    if (cols.empty()) continue;
+    for (auto j : cols) e[j] = 1.0;
+    HMG_HIP(hipMemcpyAsync(du, e.data(), n * 8, hipMemcpyHostToDevice, s));
+    TRY(launch_operator(C, OP_APPLY, du, dv, nullptr, nullptr, 0, 0, nullptr, s));
+    HMG_HIP(hipMemcpyAsync(y.data(), dv, n * 8, hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    // each row sees at most one probed column: attribute it
+    for (auto j : cols) {
+      if (fe) {
+        const int gx = (int)(j % Mx), gy = (int)((j / Mx) % My), gz = (int)(j / ((int64_t)Mx * My));
+        for (int z = std::max(0, gz - k); z <= std::min(Mz - 1, gz + k); ++z)
+          for (int yy = std::max(0, gy - k); yy <= std::min(My - 1, gy + k); ++yy)
+            for (int x = std::max(0, gx - k); x <= std::min(Mx - 1, gx + k); ++x) {
+              const int64_t i = x + (int64_t)Mx * (yy + (int64_t)My * z);
+              A[(size_t)i * n + j] = y[i];
+            }
+      } else {
+        const int64_t el = j / n3;
+        const int ex = (int)(el % m.N[0]), ey = (int)((el / m.N[0]) % m.N[1]),
+                  ez = (int)(el / ((int64_t)m.N[0] * m.N[1]));
+        const int nb[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+        for (auto& o : nb) {
+          const int x = ex + o[0], yy = ey + o[1], z = ez + o[2];
+          if (x < 0 || yy < 0 || z < 0 || x >= m.N[0] || yy >= m.N[1] || z >= m.N[2]) continue;
+          const int64_t ei = x + (int64_t)m.N[0] * (yy + (int64_t)m.N[1] * z);
+          for (int r = 0; r < n3; ++r) A[(size_t)(ei * n3 + r) * n + j] = y[ei * n3 + r];
+        }
+      }
+    }
+  }
+  // symmetrize (round-off) and factor
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+      A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
+    }
+  if (!cholesky(A, (int)n)) return fail(HMG_ERR_BREAKDOWN, "coarse matrix is not positive definite");
+  std::vector<double> Ainv;
+  chol_inverse(A, (int)n, Ainv);
+  HMG_HIP(hipMemcpyAsync(H->ainv(), Ainv.data(), (size_t)n * n * 8, hipMemcpyHostToDevice, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_bind(hmg_hierarchy* H, void* ws, size_t bytes, hipStream_t s) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (!ws || (((uintptr_t)ws) & 255)) return fail(HMG_ERR_WORKSPACE, "workspace NULL or misaligned");
+  if (bytes < H->ws_bytes) return fail(HMG_ERR_WORKSPACE, "workspace too small");
+  H->ws = (char*)ws;
+  for (size_t l = 0; l < H->lv.size(); ++l)
+    TRY(hmg_level_bind(H->lv[l], H->ws + H->off_lv[l], H->lv[l]->ws_bytes, s));
+  for (size_t l = 0; l < H->tr.size(); ++l)
+    TRY(hmg_transfer_bind(H->tr[l], H->ws + H->off_tr[l], H->tr[l]->ws_bytes));
+  if (H->own_fine64) {
+    TRY(hmg_level_bind(H->fine64, H->ws + H->off_f64, H->fine64->ws_bytes, s));
+    TRY(hmg_level_bind(H->coarse64, H->ws + H->off_c64, H->coarse64->ws_bytes, s));
+  }
+  for (size_t l = 0; l + 1 < H->lv.size(); ++l)
+    TRY(estimate_lmax(H->lv[l], 20, H->seed + l, &H->lmax[l], s));
+  TRY(coarse_setup(H, s));
+  H->bound = true;
+  return HMG_OK;
+}
+
+extern "C" void hmg_hierarchy_destroy(hmg_hierarchy* H) { delete H; }
+
+extern "C" int hmg_hierarchy_levels(const hmg_hierarchy* H, int* n) {
+  if (!H || !n) return fail(HMG_ERR_INVALID, "NULL argument");
+  *n = (int)H->lv.size();
+  return HMG_OK;
+}
+extern "C" int hmg_hierarchy_level_info(const hmg_hierarchy* H, int l, hmg_level_info* info) {
+  if (!H || !info) return fail(HMG_ERR_INVALID, "NULL argument");
+  if (l < 0 || l >= (int)H->lv.size()) return fail(HMG_ERR_INVALID, "level index out of range");
+  const hmg_level* L = H->lv[l];
+  info->space = L->space;
+  info->degree = L->k;
+  for (int d = 0; d < 3; ++d) info->nel[d] = L->mesh.N[d];
+  info->prec = L->prec;
+  info->n_dofs = L->n_dofs;
+  info->lmax = H->lmax[l];
+  return HMG_OK;
+}
+extern "C" int hmg_hierarchy_set_lmax(hmg_hierarchy* H, int l, double lmax) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (l < 0 || l + 1 >= (int)H->lv.size() || !(lmax > 0)) return fail(HMG_ERR_INVALID, "bad level or lmax");
+  H->lmax[l] = lmax;
+  return HMG_OK;
+}
+
+// Alg. 2 on level l with x^(l) = 0; b(l) holds the right-hand side.
+static int vcycle(hmg_hierarchy* H, size_t l, hipStream_t s) {
+  hmg_level* L = H->lv[l];
+  if (l + 1 == H->lv.size()) return coarse_gemv(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, s);
+  TRY(chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax[l], 0.06, 1.2, 1, s));
+  TRY(launch_operator(L, OP_RESID, H->x(l), H->r(l), H->b(l), nullptr, 0, 0, nullptr, s));
+  TRY(restrict_(H->tr[l], H->r(l), H->b(l + 1), s));
+  TRY(vcycle(H, l + 1, s));
+  TRY(prolongate_add(H->tr[l], H->x(l + 1), H->x(l), s));
+  return chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax[l], 0.06, 1.2, 0, s);
+}
+
+static int precondition(hmg_hierarchy* H, const double* b, double* x, hipStream_t s) {
+  const int pr = H->mg_prec;
+  const int64_t n = H->lv[0]->n_dofs;
+  TRY(vec_convert(HMG_F64, b, pr, H->b(0), n, s));
+  TRY(vcycle(H, 0, s));
+  return vec_convert(pr, H->x(0), HMG_F64, x, n, s);
+}
+
+extern "C" int hmg_vcycle(hmg_hierarchy* H, const double* b, double* x, hipStream_t s) {
+  if (!H || !H->bound) return fail(HMG_ERR_WORKSPACE, "hierarchy missing or not bound");
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(x, "x"));
+  if ((const void*)b == (void*)x) return fail(HMG_ERR_INVALID, "b and x must not overlap");
+  return precondition(H, b, x, s);
+}
+
+extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, double atol,
+                             int maxit, hmg_solve_stats* st, hipStream_t s) {
+  if (!H || !H->bound) return fail(HMG_ERR_WORKSPACE, "hierarchy missing or not bound");
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(x, "x"));
+  if (maxit < 0) return fail(HMG_ERR_INVALID, "maxit < 0");
+  const hmg_level* A = H->fine64;
+  const int64_t n = A->n_dofs;
+  double *r = H->cg(0), *p = H->cg(1), *v = H->cg(2), *z = H->cg(3);
+  double* sc = H->scal();  // 0,1: delta ping-pong, 2: p.Ap, 3: r.r
+  double* part = H->part();
+  hmg_solve_stats stats{0, 0, 0, 0, 0};
+  auto finish = [&](int code) {
+    if (st) *st = stats;
+    return code;
+  };
+  TRY(launch_operator(A, OP_RESID, x, r, b, nullptr, 0, 0, nullptr, s));
+  TRY(vec_dot(HMG_F64, r, r, n, part, sc + 3, s));
+  double rr;
+  HMG_HIP(hipMemcpyAsync(&rr, sc + 3, 8, hipMemcpyDeviceToHost, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  double nr = std::sqrt(rr);
+  stats.r0 = stats.rn = nr;
+  if (!std::isfinite(nr)) return finish(fail(HMG_ERR_NONFINITE, "initial residual is not finite"));
+  const double r0 = nr;
+  if (r0 == 0.0 || nr <= atol) return finish(HMG_OK);
+  TRY(precondition(H, r, z, s));
+  TRY(vec_copy(HMG_F64, z, p, n, s));
+  TRY(vec_dot(HMG_F64, r, z, n, part, sc + 0, s));
+  int it = 0;
+  while (nr / r0 > rtol && nr > atol && it < maxit) {
+    double* dcur = sc + (it & 1);
+    double* dnew = sc + ((it + 1) & 1);
+    int nparts = 0;
+    TRY(launch_operator(A, OP_DOT, p, v, nullptr, nullptr, 0, 0, &nparts, s));
+    TRY(reduce_partials(A->partials(), nparts, sc + 2, s));
+    int g = cg_update_xr(x, r, p, v, dcur, sc + 2, n, part, s);
+    if (g < 0) return finish(g);
+    TRY(reduce_partials(part, g, sc + 3, s));
+    double hs[2];
+    HMG_HIP(hipMemcpyAsync(hs, sc + 2, 16, hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    ++it;
+    nr = std::sqrt(hs[1]);
+    stats.iters = it;
+    stats.rn = nr;
+    if (!(hs[0] > 0)) return finish(fail(HMG_ERR_BREAKDOWN, "p^T A p <= 0: operator not SPD"));
+    if (!std::isfinite(nr)) return finish(fail(HMG_ERR_NONFINITE, "residual is not finite"));
+    if (!(nr / r0 > rtol && nr > atol)) break;
+    TRY(precondition(H, r, z, s));
+    TRY(vec_dot(HMG_F64, r, z, n, part, dnew, s));
+    TRY(cg_update_p(p, z, dnew, dcur, n, s));
+  }
+  if (it > 0) {
+    stats.rho = std::pow(nr / r0, 1.0 / it);
+    stats.n10 = -10.0 / std::log10(stats.rho);
+  }
+  if (nr / r0 > rtol && nr > atol) return finish(HMG_NOT_CONVERGED);
+  return finish(HMG_OK);
+}

@@ -1,0 +1,526 @@
+// Vector operations, deterministic reductions, CG updates, FE node sums,
+// multigrid transfers and the coarse-level dense solve for gfx950.
+#include "hmg_internal.h"
+
+namespace hmg {
+
+static constexpr int kBlock = 256;
+
+static unsigned grid_for(int64_t n, int per_thread = 4) {
+  int64_t g = (n + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+  if (g < 1) g = 1;
+  if (g > 65535 * 8) g = 65535 * 8;
+  return (unsigned)g;
+}
+
+__device__ __forceinline__ double block_reduce(double v) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+// ------------------------------------------------------------------ elementwise
+template <typename T>
+__global__ void k_fill(T* x, T a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = a;
+}
+template <typename T>
+__global__ void k_axpby(T a, const T* x, T b, const T* y, T* z, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = a * x[i] + (y ? b * y[i] : T(0));
+}
+template <typename T>
+__global__ void k_recip(const T* x, T* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = T(1) / x[i];
+}
+template <typename T>
+__global__ void k_mul3(T a, const T* d, const T* b, T* z, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = a * d[i] * b[i];
+}
+template <typename A, typename B>
+__global__ void k_convert(const A* x, B* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (B)x[i];
+}
+template <typename T>
+__global__ void k_dot(const T* x, const T* y, int64_t n, double* partials) {
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)x[i] * (double)y[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+__global__ void k_reduce(const double* partials, int np, double* out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) *out = s;
+}
+// SplitMix64 (Steele, Lea, Flood 2014): output i = mix(seed + (i+1)*golden)
+template <typename T>
+__global__ void k_splitmix(uint64_t seed, T* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (T)((double)(z >> 11) * 0x1.0p-52 - 1.0);
+  }
+}
+
+// CG (Alg. 1): omega = delta / (p^T v); x += omega p; r -= omega v; partials of r.r
+__global__ void k_cg_xr(double* x, double* r, const double* p, const double* v, const double* num,
+                        const double* den, int64_t n, double* partials) {
+  const double omega = *num / *den;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += omega * p[i];
+    const double ri = r[i] - omega * v[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+// p = z + (delta_new / delta_old) p
+__global__ void k_cg_p(double* p, const double* z, const double* num, const double* den, int64_t n) {
+  const double beta = *num / *den;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+#define PREC_DISPATCH(prec, EXPR_D, EXPR_F) \
+  do {                                      \
+    if ((prec) == HMG_F64) {                \
+      EXPR_D;                               \
+    } else {                                \
+      EXPR_F;                               \
+    }                                       \
+  } while (0)
+
+int vec_fill(int prec, void* x, double a, int64_t n, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_fill<double>, grid_for(n), kBlock, 0, s, (double*)x, a, n),
+                hipLaunchKernelGGL(k_fill<float>, grid_for(n), kBlock, 0, s, (float*)x, (float)a, n));
+  return check_launch("fill");
+}
+int vec_copy(int prec, const void* x, void* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  HMG_HIP(hipMemcpyAsync(y, x, (size_t)n * (prec == HMG_F64 ? 8 : 4), hipMemcpyDeviceToDevice, s));
+  return HMG_OK;
+}
+int vec_axpby(int prec, double a, const void* x, double b, const void* y, void* z, int64_t n,
+              hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_axpby<double>, grid_for(n), kBlock, 0, s, a, (const double*)x, b,
+                                   (const double*)y, (double*)z, n),
+                hipLaunchKernelGGL(k_axpby<float>, grid_for(n), kBlock, 0, s, (float)a, (const float*)x,
+                                   (float)b, (const float*)y, (float*)z, n));
+  return check_launch("axpby");
+}
+int vec_recip(int prec, const void* x, void* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_recip<double>, grid_for(n), kBlock, 0, s, (const double*)x, (double*)y, n),
+                hipLaunchKernelGGL(k_recip<float>, grid_for(n), kBlock, 0, s, (const float*)x, (float*)y, n));
+  return check_launch("recip");
+}
+int vec_mul3(int prec, double a, const void* d, const void* b, void* z, int64_t n, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_mul3<double>, grid_for(n), kBlock, 0, s, a, (const double*)d,
+                                   (const double*)b, (double*)z, n),
+                hipLaunchKernelGGL(k_mul3<float>, grid_for(n), kBlock, 0, s, (float)a, (const float*)d,
+                                   (const float*)b, (float*)z, n));
+  return check_launch("mul3");
+}
+int vec_convert(int from, const void* x, int to, void* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  if (from == to) return vec_copy(from, x, y, n, s);
+  if (from == HMG_F64)
+    hipLaunchKernelGGL((k_convert<double, float>), grid_for(n), kBlock, 0, s, (const double*)x, (float*)y, n);
+  else
+    hipLaunchKernelGGL((k_convert<float, double>), grid_for(n), kBlock, 0, s, (const float*)x, (double*)y, n);
+  return check_launch("convert");
+}
+static unsigned dot_grid(int64_t n) {
+  unsigned g = grid_for(n, 8);
+  return g > (unsigned)kPartials ? (unsigned)kPartials : g;
+}
+int reduce_partials(const double* partials, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, 1, 1024, 0, s, partials, np, out);
+  return check_launch("reduce");
+}
+int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
+            hipStream_t s) {
+  const unsigned g = dot_grid(n);
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_dot<double>, g, kBlock, 0, s, (const double*)x, (const double*)y, n, partials),
+                hipLaunchKernelGGL(k_dot<float>, g, kBlock, 0, s, (const float*)x, (const float*)y, n, partials));
+  int rc = check_launch("dot");
+  if (rc) return rc;
+  return reduce_partials(partials, (int)g, out, s);
+}
+int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
+                 const double* den, int64_t n, double* partials, hipStream_t s) {
+  const unsigned g = dot_grid(n);
+  hipLaunchKernelGGL(k_cg_xr, g, kBlock, 0, s, x, r, p, v, num, den, n, partials);
+  int rc = check_launch("cg_xr");
+  if (rc) return rc;
+  return (int)g;  // caller reduces g partials
+}
+int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p, grid_for(n), kBlock, 0, s, p, z, num, den, n);
+  return check_launch("cg_p");
+}
+int vec_splitmix(int prec, uint64_t seed, void* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_splitmix<double>, grid_for(n), kBlock, 0, s, seed, (double*)x, n),
+                hipLaunchKernelGGL(k_splitmix<float>, grid_for(n), kBlock, 0, s, seed, (float*)x, n));
+  return check_launch("splitmix");
+}
+
+// ------------------------------------------------------------------ FE node sums
+// The elements sharing global node g along one direction: up to two
+// (element coordinate, local index) pairs.
+struct NodeDir {
+  int cnt;
+  int e[2], loc[2];
+};
+__device__ __forceinline__ NodeDir node_dir(int64_t g, int k, int Nd) {
+  NodeDir r;
+  const int q = (int)(g / k), rem = (int)(g - (int64_t)q * k);
+  if (rem != 0) {
+    r.cnt = 1;
+    r.e[0] = q;
+    r.loc[0] = rem;
+  } else {
+    r.cnt = 0;
+    if (q >= 1) {
+      r.e[r.cnt] = q - 1;
+      r.loc[r.cnt] = k;
+      ++r.cnt;
+    }
+    if (q < Nd) {
+      r.e[r.cnt] = q;
+      r.loc[r.cnt] = 0;
+      ++r.cnt;
+    }
+  }
+  return r;
+}
+
+struct FeGeo {
+  int Nx, Ny, Nz, k, bcmask;
+  int64_t Mx, My, Mz, nnodes;
+};
+static FeGeo fe_geo(const Mesh& m, int k) {
+  FeGeo g;
+  g.Nx = m.N[0];
+  g.Ny = m.N[1];
+  g.Nz = m.N[2];
+  g.k = k;
+  g.bcmask = m.bcmask();
+  g.Mx = (int64_t)m.N[0] * k + 1;
+  g.My = (int64_t)m.N[1] * k + 1;
+  g.Mz = (int64_t)m.N[2] * k + 1;
+  g.nnodes = g.Mx * g.My * g.Mz;
+  return g;
+}
+__device__ __forceinline__ bool node_fixed(const FeGeo& G, int64_t gx, int64_t gy, int64_t gz) {
+  const int m = G.bcmask;
+  return (gx == 0 && !(m & 1)) || (gx == G.Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
+         (gy == G.My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == G.Mz - 1 && !(m & 32));
+}
+
+// sum of a DG-layout vector over the elements sharing each node; returns the
+// multiplicity in *mult
+template <typename T>
+__device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int64_t gx, int64_t gy,
+                                             int64_t gz, int* mult) {
+  const int n = G.k + 1, n3 = n * n * n;
+  NodeDir X = node_dir(gx, G.k, G.Nx), Y = node_dir(gy, G.k, G.Ny), Z = node_dir(gz, G.k, G.Nz);
+  T s = 0;
+  for (int c = 0; c < Z.cnt; ++c)
+    for (int b = 0; b < Y.cnt; ++b)
+      for (int a = 0; a < X.cnt; ++a) {
+        const int64_t e = X.e[a] + (int64_t)G.Nx * (Y.e[b] + (int64_t)G.Ny * Z.e[c]);
+        s += dg[e * n3 + X.loc[a] + n * (Y.loc[b] + n * Z.loc[c])];
+      }
+  *mult = X.cnt * Y.cnt * Z.cnt;
+  return s;
+}
+
+template <typename T, int MODE>
+__global__ void k_fe_sum(FeGeo G, const T* dg, const T* u, T* out, const T* b, const T* dinv,
+                         const T* xold, T sigma, T theta) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.nnodes; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gx = i % G.Mx, r = i / G.Mx, gy = r % G.My, gz = r / G.My;
+    int mult;
+    T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
+    if (node_fixed(G, gx, gy, gz)) v = u[i];
+    if (MODE == OP_APPLY) {
+      out[i] = v;
+    } else if (MODE == OP_RESID) {
+      out[i] = b[i] - v;
+    } else {
+      const T x = u[i];
+      out[i] = x + sigma * (x - xold[i]) + theta * dinv[i] * (b[i] - v);
+    }
+  }
+}
+// fe (+)= free * w * E^T dg
+template <typename T>
+__global__ void k_c_sum(FeGeo G, const T* dg, T* fe, int weight_mult, int add) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.nnodes; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gx = i % G.Mx, r = i / G.Mx, gy = r % G.My, gz = r / G.My;
+    int mult;
+    T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
+    if (weight_mult) v /= (T)mult;
+    if (node_fixed(G, gx, gy, gz)) v = 0;
+    fe[i] = add ? fe[i] + v : v;
+  }
+}
+// dg (+)= E (free * w * fe)
+template <typename T>
+__global__ void k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add) {
+  const int n = G.k + 1, n3 = n * n * n;
+  const int64_t ndg = (int64_t)G.Nx * G.Ny * G.Nz * n3;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ndg; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / n3;
+    const int p = (int)(i - e * n3);
+    const int64_t gx = (e % G.Nx) * G.k + p % n;
+    const int64_t er = e / G.Nx;
+    const int64_t gy = (er % G.Ny) * G.k + (p / n) % n;
+    const int64_t gz = (er / G.Ny) * G.k + p / (n * n);
+    T v = 0;
+    if (!node_fixed(G, gx, gy, gz)) {
+      v = fe[gx + G.Mx * (gy + G.My * gz)];
+      if (weight_mult) {
+        int mult = node_dir(gx, G.k, G.Nx).cnt * node_dir(gy, G.k, G.Ny).cnt * node_dir(gz, G.k, G.Nz).cnt;
+        v /= (T)mult;
+      }
+    }
+    dg[i] = add ? dg[i] + v : v;
+  }
+}
+
+template <typename T>
+static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, const void* b,
+                    const void* xold, double sigma, double theta, hipStream_t s) {
+  FeGeo G = fe_geo(L->mesh, L->k);
+  const unsigned g = grid_for(G.nnodes);
+  const T* dg = (const T*)L->scratch();
+  const T* di = (const T*)L->dinv();
+  switch (mode) {
+    case OP_RESID:
+      hipLaunchKernelGGL((k_fe_sum<T, OP_RESID>), g, kBlock, 0, s, G, dg, (const T*)u, (T*)out,
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
+      break;
+    case OP_CHEB:
+      hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB>), g, kBlock, 0, s, G, dg, (const T*)u, (T*)out,
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY>), g, kBlock, 0, s, G, dg, (const T*)u, (T*)out,
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
+  }
+  return check_launch("fe_sum");
+}
+int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
+                const void* xold, double sigma, double theta, hipStream_t s) {
+  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s);
+  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s);
+}
+int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int weight_mult, int add,
+                hipStream_t s) {
+  FeGeo G = fe_geo(m, k);
+  const int64_t ndg = m.n_el() * (int64_t)(k + 1) * (k + 1) * (k + 1);
+  const unsigned g = grid_for(ndg);
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_inject<double>, g, kBlock, 0, s, G, (const double*)fe, (double*)dg, weight_mult, add),
+                hipLaunchKernelGGL(k_c_inject<float>, g, kBlock, 0, s, G, (const float*)fe, (float*)dg, weight_mult, add));
+  return check_launch("c_inject");
+}
+int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
+             hipStream_t s) {
+  FeGeo G = fe_geo(m, k);
+  const unsigned g = grid_for(G.nnodes);
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_sum<double>, g, kBlock, 0, s, G, (const double*)dg, (double*)fe, weight_mult, add),
+                hipLaunchKernelGGL(k_c_sum<float>, g, kBlock, 0, s, G, (const float*)dg, (float*)fe, weight_mult, add));
+  return check_launch("c_sum");
+}
+
+// ------------------------------------------------------------------ DG p / h transfers
+// Element-local tensor products with 1-D matrices P (nf x nc), P[i*nc + j]
+// = coarse basis j at fine node i (Sec. 3.2: L2 projection = interpolation).
+template <typename T>
+struct TrArgs {
+  T P[2][kMaxN * kMaxN];
+  int nf, nc, kind;  // kind 0: p, 1: h
+  int Nf[3];
+  int64_t nel_f, nel_c;
+};
+
+// out[o0,o1,o2] = sum M2[o2,i2] M1[o1,i1] M0[o0,i0] in[i0,i1,i2] in LDS
+// (x fastest); trans selects M^T (M stored nf x nc).
+template <typename T>
+__device__ void tensor3(const TrArgs<T>& a, const T* in, T* t1, T* t2, T* out, int ni, int no,
+                        const int child[3], bool trans) {
+  const int nf = a.nf, nc = a.nc;
+  auto M = [&](int d, int o, int i) -> T {
+    const T* P = a.P[child[d]];
+    return trans ? P[i * nc + o] : P[o * nc + i];
+  };
+  for (int p = threadIdx.x; p < no * ni * ni; p += blockDim.x) {
+    const int o0 = p % no, i1 = (p / no) % ni, i2 = p / (no * ni);
+    T s = 0;
+    for (int i0 = 0; i0 < ni; ++i0) s += M(0, o0, i0) * in[i0 + ni * (i1 + ni * i2)];
+    t1[p] = s;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < no * no * ni; p += blockDim.x) {
+    const int o0 = p % no, o1 = (p / no) % no, i2 = p / (no * no);
+    T s = 0;
+    for (int i1 = 0; i1 < ni; ++i1) s += M(1, o1, i1) * t1[o0 + no * (i1 + ni * i2)];
+    t2[p] = s;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < no * no * no; p += blockDim.x) {
+    const int o0 = p % no, o1 = (p / no) % no, o2 = p / (no * no);
+    T s = 0;
+    for (int i2 = 0; i2 < ni; ++i2) s += M(2, o2, i2) * t2[o0 + no * (o1 + no * i2)];
+    out[p] = s;
+  }
+  __syncthreads();
+  (void)nf;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tr_prolong(TrArgs<T> a, const T* coarse, T* fine, int add) {
+  __shared__ T in[512], t1[512], t2[512], out[512];
+  const int64_t e = blockIdx.x;
+  const int nf = a.nf, nc = a.nc, nf3 = nf * nf * nf, nc3 = nc * nc * nc;
+  int child[3] = {0, 0, 0};
+  int64_t ec = e;
+  if (a.kind == 1) {
+    const int ex = (int)(e % a.Nf[0]), ey = (int)((e / a.Nf[0]) % a.Nf[1]),
+              ez = (int)(e / ((int64_t)a.Nf[0] * a.Nf[1]));
+    child[0] = ex & 1;
+    child[1] = ey & 1;
+    child[2] = ez & 1;
+    const int Cx = a.Nf[0] / 2, Cy = a.Nf[1] / 2;
+    ec = (ex >> 1) + (int64_t)Cx * ((ey >> 1) + (int64_t)Cy * (ez >> 1));
+  }
+  for (int p = threadIdx.x; p < nc3; p += blockDim.x) in[p] = coarse[ec * nc3 + p];
+  __syncthreads();
+  tensor3(a, in, t1, t2, out, nc, nf, child, false);
+  for (int p = threadIdx.x; p < nf3; p += blockDim.x) {
+    const int64_t g = e * nf3 + p;
+    fine[g] = add ? fine[g] + out[p] : out[p];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tr_restrict(TrArgs<T> a, const T* fine, T* coarse) {
+  __shared__ T in[512], t1[512], t2[512], out[512];
+  const int64_t ec = blockIdx.x;
+  const int nf = a.nf, nc = a.nc, nf3 = nf * nf * nf, nc3 = nc * nc * nc;
+  T acc[2] = {0, 0};  // nc3 <= 512 -> at most 2 points per thread
+  const int nchild = a.kind == 1 ? 8 : 1;
+  for (int c = 0; c < nchild; ++c) {
+    int child[3] = {0, 0, 0};
+    int64_t ef = ec;
+    if (a.kind == 1) {
+      const int Cx = a.Nf[0] / 2, Cy = a.Nf[1] / 2;
+      const int cx = (int)(ec % Cx), cy = (int)((ec / Cx) % Cy), cz = (int)(ec / ((int64_t)Cx * Cy));
+      child[0] = c & 1;
+      child[1] = (c >> 1) & 1;
+      child[2] = (c >> 2) & 1;
+      ef = (2 * cx + child[0]) + (int64_t)a.Nf[0] * ((2 * cy + child[1]) + (int64_t)a.Nf[1] * (2 * cz + child[2]));
+    }
+    for (int p = threadIdx.x; p < nf3; p += blockDim.x) in[p] = fine[ef * nf3 + p];
+    __syncthreads();
+    tensor3(a, in, t1, t2, out, nf, nc, child, true);
+    int slot = 0;
+    for (int p = threadIdx.x; p < nc3; p += blockDim.x, ++slot) acc[slot] += out[p];
+    __syncthreads();
+  }
+  int slot = 0;
+  for (int p = threadIdx.x; p < nc3; p += blockDim.x, ++slot) coarse[ec * nc3 + p] = acc[slot];
+}
+
+template <typename T>
+static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double* P0, const double* P1) {
+  TrArgs<T> a;
+  a.nf = nf;
+  a.nc = nc;
+  a.kind = kind;
+  for (int d = 0; d < 3; ++d) a.Nf[d] = Nf[d];
+  for (int i = 0; i < nf * nc; ++i) {
+    a.P[0][i] = (T)P0[i];
+    a.P[1][i] = (T)(P1 ? P1[i] : P0[i]);
+  }
+  a.nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
+  a.nel_c = kind == 1 ? a.nel_f / 8 : a.nel_f;
+  return a;
+}
+
+int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
+                     const double* P1, const void* coarse, void* fine, int add, hipStream_t s) {
+  const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
+  if (nel_f == 0) return HMG_OK;
+  if (prec == HMG_F64) {
+    auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1);
+    hipLaunchKernelGGL(k_tr_prolong<double>, (unsigned)nel_f, 256, 0, s, a, (const double*)coarse, (double*)fine, add);
+  } else {
+    auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1);
+    hipLaunchKernelGGL(k_tr_prolong<float>, (unsigned)nel_f, 256, 0, s, a, (const float*)coarse, (float*)fine, add);
+  }
+  return check_launch("tr_prolong");
+}
+int tr_dg_restrict(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
+                   const double* P1, const void* fine, void* coarse, hipStream_t s) {
+  const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
+  const int64_t nel_c = kind == 1 ? nel_f / 8 : nel_f;
+  if (nel_c == 0) return HMG_OK;
+  if (prec == HMG_F64) {
+    auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1);
+    hipLaunchKernelGGL(k_tr_restrict<double>, (unsigned)nel_c, 256, 0, s, a, (const double*)fine, (double*)coarse);
+  } else {
+    auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1);
+    hipLaunchKernelGGL(k_tr_restrict<float>, (unsigned)nel_c, 256, 0, s, a, (const float*)fine, (float*)coarse);
+  }
+  return check_launch("tr_restrict");
+}
+
+// ------------------------------------------------------------------ coarse solve
+// x = Ainv b with the dense FP64 inverse of the coarsest operator; one
+// wavefront per row, FP64 accumulation whatever the vector precision.
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_gemv(const double* Ainv, const T* b, T* x, int n) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* Ar = Ainv + (int64_t)row * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += Ar[j] * (double)b[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) x[row] = (T)acc;
+}
+int coarse_gemv(int prec, const double* Ainv, const void* b, void* x, int n, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 3) / 4);
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_coarse_gemv<double>, g, 256, 0, s, Ainv, (const double*)b, (double*)x, n),
+                hipLaunchKernelGGL(k_coarse_gemv<float>, g, 256, 0, s, Ainv, (const float*)b, (float*)x, n));
+  return check_launch("coarse_gemv");
+}
+
+}  // namespace hmg

@@ -1,0 +1,196 @@
+// Internal declarations shared by the host setup, the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hmg.h"
+
+namespace hmg {
+
+constexpr int kMaxN = 8;  // n = k + 1, k = 1..7
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+#define HMG_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::hmg::fail(HMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+int check_launch(const char* what);
+
+// ---------------------------------------------------------------- 1-D bases
+// Sec. 2: Lagrange basis on the k+1 GLL nodes of [0,1], Gauss rule with k+1
+// points.  All tables are row-major [q][i].
+struct Basis1D {
+  int k = 0, n = 0;
+  std::vector<double> gll, gz, gw;  // GLL nodes, Gauss points, Gauss weights
+  std::vector<double> S;            // S[q][i]  = l_i(z_q)
+  std::vector<double> Sp;           // Sp[q][i] = l_i'(z_q)
+  std::vector<double> D;            // D[q][r]  = derivative of the Gauss Lagrange basis r at z_q
+  std::vector<double> M;            // M[i][j]  = sum_q w_q l_i(z_q) l_j(z_q) (1-D mass)
+  std::vector<double> dl0, dl1;     // l_i'(0), l_i'(1)
+};
+Basis1D make_basis(int k);
+std::vector<double> gll_nodes(int k);
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
+// V[q][i] = l_i(x_q), Dv[q][i] = l_i'(x_q) for the Lagrange basis of `nodes`.
+void lagrange(const std::vector<double>& nodes, const std::vector<double>& x,
+              std::vector<double>* V, std::vector<double>* Dv);
+
+// Kernel-argument copy of the tables for a compile-time n.
+template <int N, typename T>
+struct OpTab {
+  T S[N * N], Sp[N * N], D[N * N], M[N * N], dl0[N], dl1[N], w[N];
+};
+template <int N, typename T>
+OpTab<N, T> make_tab(const Basis1D& b) {
+  OpTab<N, T> t;
+  for (int i = 0; i < N * N; ++i) {
+    t.S[i] = (T)b.S[i];
+    t.Sp[i] = (T)b.Sp[i];
+    t.D[i] = (T)b.D[i];
+    t.M[i] = (T)b.M[i];
+  }
+  for (int i = 0; i < N; ++i) {
+    t.dl0[i] = (T)b.dl0[i];
+    t.dl1[i] = (T)b.dl1[i];
+    t.w[i] = (T)b.gw[i];
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------- mesh / geometry
+struct Mesh {
+  int N[3];
+  double lo[3], hi[3];
+  int k;
+  bool curved;
+  double amp;
+  int waves;
+  uint8_t bc[6];
+  double ip;
+  std::vector<double> tau_scale;  // empty = all ones
+  int64_t n_el() const { return (int64_t)N[0] * N[1] * N[2]; }
+  double h(int d) const { return (hi[d] - lo[d]) / N[d]; }
+  int bcmask() const {  // bit (2d+s) set <=> Neumann
+    int m = 0;
+    for (int f = 0; f < 6; ++f)
+      if (bc[f]) m |= 1 << f;
+    return m;
+  }
+};
+
+// Host geometry of a level (double precision, uploaded in the level precision).
+//  metric  [e][6][n^3]: w_q |det J| J^{-1} J^{-T} as (00, 11, 22, 01, 02, 12)
+//  face[d] [f][7][n^2]: f = p + (N_d+1)*(ea + N_a*eb); comps 0..2 = n^T J_L^{-T},
+//          3..5 = n^T J_R^{-T}, 6 = surface weight; n points from L to R.
+//  tau     [e]
+struct Geometry {
+  std::vector<double> metric;
+  std::vector<double> face[3];
+  std::vector<double> tau;
+};
+int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g);  // curved or affine
+// Physical point and Jacobian at reference point xi of element e (Q3 map).
+void map_point(const Mesh& m, int64_t e, const double xi[3], double x[3], double J[9]);
+int rhs_sine_host(const Mesh& m, const Basis1D& b, const Geometry& g, double freq,
+                  std::vector<double>& out);
+// diag(A) of a DG or FE level (setup, host)
+int diag_host(const Mesh& m, const Basis1D& b, const Geometry& g, int space,
+              std::vector<double>& out);
+
+// ---------------------------------------------------------------- level handle
+}  // namespace hmg
+
+struct hmg_level {
+  hmg::Mesh mesh;
+  int space = HMG_DG;
+  int prec = HMG_F64;
+  int k = 1, n = 2;
+  int64_t n_el = 0, n_dofs = 0, n_dg = 0;  // n_dg = n_el * n^3
+  hmg::Basis1D basis;
+  hmg::Geometry geom;  // host copy, released after bind
+  std::vector<double> diag_h;  // diag(A), computed during create
+  // workspace layout (byte offsets) and bound pointers
+  size_t ws_bytes = 0;
+  size_t off_metric = 0, off_face[3] = {0, 0, 0}, off_tau = 0, off_diag = 0, off_dinv = 0, off_tmp = 0,
+         off_scratch = 0, off_part = 0, off_scal = 0;
+  char* ws = nullptr;
+  bool bound = false;
+  size_t elem_size() const { return prec == HMG_F64 ? 8 : 4; }
+  void* metric() const { return ws + off_metric; }
+  void* face(int d) const { return ws + off_face[d]; }
+  void* tau() const { return ws + off_tau; }
+  void* diag() const { return ws + off_diag; }  // diag(A), level precision
+  void* dinv() const { return ws + off_dinv; }
+  void* tmp(int i) const { return ws + off_tmp + (size_t)i * vec_bytes(); }
+  void* scratch() const { return ws + off_scratch; }  // DG-layout buffer (FE levels)
+  double* partials() const { return (double*)(ws + off_part); }
+  double* scal() const { return (double*)(ws + off_scal); }
+  size_t vec_bytes() const { return (size_t)n_dofs * elem_size(); }
+};
+
+namespace hmg {
+
+constexpr int kPartials = 1024;  // max blocks of a reduction
+constexpr int kTmpVecs = 4;      // level temporaries (Chebyshev, lambda_max)
+
+// ---------------------------------------------------------------- kernel launchers
+enum OpMode { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2, OP_DOT = 3 };
+
+// DG: out = f(A u); FE: cell part into scratch, then node sum with the mode.
+// OP_CHEB: out = u + sigma (u - xold) + theta dinv (b - A u)  (out may alias xold)
+// OP_DOT : out = A u, partials[blk] = sum u.(A u) (for p^T A p).
+int launch_operator(const hmg_level* L, int mode, const void* u, void* out, const void* b,
+                    const void* xold, double sigma, double theta, int* nparts, hipStream_t s);
+
+// vectors (type by prec); n elements
+int vec_fill(int prec, void* x, double a, int64_t n, hipStream_t s);
+int vec_copy(int prec, const void* x, void* y, int64_t n, hipStream_t s);
+int vec_axpby(int prec, double a, const void* x, double b, const void* y, void* z, int64_t n,
+              hipStream_t s);  // z = a x + b y
+int vec_recip(int prec, const void* x, void* y, int64_t n, hipStream_t s);       // y = 1/x
+int vec_mul3(int prec, double a, const void* d, const void* b, void* z, int64_t n,
+             hipStream_t s);  // z = a d .* b
+int vec_convert(int from, const void* x, int to, void* y, int64_t n, hipStream_t s);
+// deterministic two-stage dot: result to dev double* out (and nparts returned)
+int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
+            hipStream_t s);
+int reduce_partials(const double* partials, int nparts, double* out, hipStream_t s);
+// CG updates with device scalars (all FP64): see kernels for formulas
+// omega = *num / *den; x += omega p; r -= omega v; returns the number of
+// partials of r.r written (>0) or an error (<0)
+int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
+                 const double* den, int64_t n, double* partials, hipStream_t s);
+// p = z + (*num / *den) p
+int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
+                hipStream_t s);
+
+// transfers (element-local tensor-product kernels)
+// DG p / h: fine += P coarse, coarse = P^T fine
+int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
+                     const double* P1, const void* coarse, void* fine, int add, hipStream_t s);
+int tr_dg_restrict(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
+                   const double* P1, const void* fine, void* coarse, hipStream_t s);
+// c-transfers between the FE vector and a DG-layout vector on the same mesh
+//   inject: dg = E(free * w * fe) with w = 1 or 1/mult;  add: dg += ... if add
+//   sum   : fe (+)= free * w * E^T dg
+int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int weight_mult,
+                int add, hipStream_t s);
+int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
+             hipStream_t s);
+// FE operator node sum with a mode (see launch_operator)
+int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
+                const void* xold, double sigma, double theta, hipStream_t s);
+// coarse dense FP64 inverse apply: x = Ainv b (b, x of prec), n unknowns
+int coarse_gemv(int prec, const double* Ainv, const void* b, void* x, int n, hipStream_t s);
+// SplitMix64 uniform [-1,1) vector
+int vec_splitmix(int prec, uint64_t seed, void* x, int64_t n, hipStream_t s);
+
+}  // namespace hmg

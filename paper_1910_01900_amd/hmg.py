@@ -1,0 +1,314 @@
+"""Thin ctypes binding of libhmg.so (include/hmg.h): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch provides device memory
+(workspaces and vectors) and the current HIP stream.  Importing this module
+does not touch the GPU; loading the library fails loudly if it is not built.
+"""
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hmg.h")
+
+DG, FE = 0, 1
+F64, F32 = 0, 1
+STATUS = {0: "HMG_OK", 1: "HMG_NOT_CONVERGED", -1: "HMG_ERR_INVALID", -2: "HMG_ERR_UNSUPPORTED",
+          -3: "HMG_ERR_HIP", -4: "HMG_ERR_BREAKDOWN", -5: "HMG_ERR_NONFINITE", -6: "HMG_ERR_WORKSPACE"}
+
+
+class HmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("nel", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("degree", C.c_int32), ("deformed", C.c_int32), ("deform_amp", C.c_double),
+                ("deform_waves", C.c_int32), ("bc", C.c_uint8 * 6), ("ip_factor", C.c_double),
+                ("tau_scale", C.POINTER(C.c_double))]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("space", C.c_int32), ("degree", C.c_int32), ("nel", C.c_int32 * 3),
+                ("prec", C.c_int32), ("n_dofs", C.c_int64), ("lmax", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("r0", C.c_double), ("rn", C.c_double),
+                ("rho", C.c_double), ("n10", C.c_double)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libhmg.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhmg.so is not built: run `python -m paper_1910_01900_amd.build`")
+        # One HIP runtime per process: torch's copy of libamdhip64.so.7 is
+        # loaded first, and the library's DT_NEEDED entry resolves to it by
+        # SONAME (two runtimes in one process do not share the device).
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "hmg_last_error": (C.c_char_p, []),
+            "hmg_version": (C.c_int, []),
+            "hmg_level_create": (C.c_int, [C.POINTER(MeshDesc), C.c_int, C.c_int, C.POINTER(_P)]),
+            "hmg_level_query": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+            "hmg_level_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
+            "hmg_level_destroy": (None, [_P]),
+            "hmg_operator_apply": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_residual": (C.c_int, [_P, _P, _P, _P, _P]),
+            "hmg_diagonal": (C.c_int, [_P, _P, _P]),
+            "hmg_level_diagonal_host": (C.c_int, [_P, C.POINTER(C.c_double)]),
+            "hmg_estimate_lambda_max": (C.c_int, [_P, C.c_int, C.c_uint64, C.POINTER(C.c_double), _P]),
+            "hmg_chebyshev_smooth": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double,
+                                               C.c_int, _P]),
+            "hmg_transfer_create": (C.c_int, [_P, _P, C.c_char, C.POINTER(_P)]),
+            "hmg_transfer_query": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+            "hmg_transfer_bind": (C.c_int, [_P, _P, C.c_size_t]),
+            "hmg_transfer_destroy": (None, [_P]),
+            "hmg_prolongate_add": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_restrict": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_hierarchy_create": (C.c_int, [C.POINTER(MeshDesc), C.c_char_p, C.c_int, C.c_int, C.c_int,
+                                               C.c_int, C.c_uint64, C.POINTER(_P)]),
+            "hmg_hierarchy_query": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+            "hmg_hierarchy_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
+            "hmg_hierarchy_destroy": (None, [_P]),
+            "hmg_hierarchy_levels": (C.c_int, [_P, C.POINTER(C.c_int)]),
+            "hmg_hierarchy_level_info": (C.c_int, [_P, C.c_int, C.POINTER(LevelInfo)]),
+            "hmg_hierarchy_set_lmax": (C.c_int, [_P, C.c_int, C.c_double]),
+            "hmg_vcycle": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_pcg_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int,
+                                        C.POINTER(SolveStats), _P]),
+            "hmg_rhs_sine": (C.c_int, [_P, C.c_double, _P, _P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Function names declared in include/hmg.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hmg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def check(code, allow=(0,)):
+    if code in allow:
+        return code
+    if code > 0:
+        return code
+    raise HmgError(code, lib().hmg_last_error().decode())
+
+
+@dataclass
+class Mesh:
+    """Structured box mesh (hmg_mesh_desc)."""
+    nel: tuple
+    degree: int
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    deformed: bool = False
+    amp: float = 0.0
+    waves: int = 1
+    bc: tuple = (0, 0, 0, 0, 0, 0)
+    ip: float = 1.0
+    tau_scale: np.ndarray = field(default=None)
+
+    def desc(self):
+        d = MeshDesc()
+        for i in range(3):
+            d.nel[i] = int(self.nel[i])
+            d.lo[i] = float(self.lo[i])
+            d.hi[i] = float(self.hi[i])
+        d.degree = int(self.degree)
+        d.deformed = 1 if self.deformed else 0
+        d.deform_amp = float(self.amp)
+        d.deform_waves = int(self.waves)
+        for i in range(6):
+            d.bc[i] = int(self.bc[i])
+        d.ip_factor = float(self.ip)
+        if self.tau_scale is not None:
+            self._ts = np.ascontiguousarray(self.tau_scale, dtype=np.float64)
+            d.tau_scale = self._ts.ctypes.data_as(C.POINTER(C.c_double))
+        else:
+            d.tau_scale = None
+        return d
+
+    @property
+    def n_el(self):
+        return int(np.prod(self.nel))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def ptr(t):
+    torch = _torch()
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype(prec):
+    torch = _torch()
+    return torch.float64 if prec == F64 else torch.float32
+
+
+def _workspace(nbytes):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+class Level:
+    """A bound level (hmg_level): create on the host, bind to a torch workspace."""
+
+    def __init__(self, mesh, space=DG, prec=F64):
+        self.mesh, self.space, self.prec = mesh, space, prec
+        self._h = C.c_void_p()
+        desc = mesh.desc()
+        check(lib().hmg_level_create(C.byref(desc), space, prec, C.byref(self._h)))
+        n, ws = C.c_int64(), C.c_size_t()
+        check(lib().hmg_level_query(self._h, C.byref(n), C.byref(ws)))
+        self.n_dofs = n.value
+        self.ws_bytes = ws.value
+        self.ws = _workspace(ws.value)
+        check(lib().hmg_level_bind(self._h, ptr(self.ws), ws.value, stream()))
+        self.dtype = _dtype(prec)
+
+    def vector(self, values=None):
+        torch = _torch()
+        if values is None:
+            return torch.zeros(self.n_dofs, dtype=self.dtype, device="cuda")
+        return torch.as_tensor(np.asarray(values), dtype=self.dtype).to("cuda").contiguous()
+
+    def apply(self, u, v=None):
+        v = self.vector() if v is None else v
+        check(lib().hmg_operator_apply(self._h, ptr(u), ptr(v), stream()))
+        return v
+
+    def residual(self, b, u, r=None):
+        r = self.vector() if r is None else r
+        check(lib().hmg_residual(self._h, ptr(b), ptr(u), ptr(r), stream()))
+        return r
+
+    def diagonal(self):
+        d = self.vector()
+        check(lib().hmg_diagonal(self._h, ptr(d), stream()))
+        return d
+
+    def lambda_max(self, iters=20, seed=1):
+        out = C.c_double()
+        check(lib().hmg_estimate_lambda_max(self._h, iters, seed, C.byref(out), stream()))
+        return out.value
+
+    def chebyshev(self, b, x, degree, lmax, lo=0.06, hi=1.2, x_is_zero=False):
+        check(lib().hmg_chebyshev_smooth(self._h, ptr(b), ptr(x), degree, lmax, lo, hi,
+                                         1 if x_is_zero else 0, stream()))
+        return x
+
+    def rhs_sine(self, freq):
+        b = self.vector()
+        check(lib().hmg_rhs_sine(self._h, freq, ptr(b), stream()))
+        return b
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.hmg_level_destroy(self._h)
+            self._h = C.c_void_p()
+
+
+class Transfer:
+    def __init__(self, fine, coarse, kind):
+        self.fine, self.coarse = fine, coarse
+        self._h = C.c_void_p()
+        check(lib().hmg_transfer_create(fine._h, coarse._h, kind.encode(), C.byref(self._h)))
+        ws = C.c_size_t()
+        check(lib().hmg_transfer_query(self._h, C.byref(ws)))
+        self.ws = _workspace(ws.value)
+        check(lib().hmg_transfer_bind(self._h, ptr(self.ws), ws.value))
+
+    def prolongate_add(self, c, f):
+        check(lib().hmg_prolongate_add(self._h, ptr(c), ptr(f), stream()))
+        return f
+
+    def restrict(self, f, c=None):
+        c = self.coarse.vector() if c is None else c
+        check(lib().hmg_restrict(self._h, ptr(f), ptr(c), stream()))
+        return c
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.hmg_transfer_destroy(self._h)
+            self._h = C.c_void_p()
+
+
+class Hierarchy:
+    """Hybrid multigrid hierarchy + FP64 PCG (hmg_hierarchy)."""
+
+    def __init__(self, mesh, strategy="cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=F64,
+                 lmax_seed=1):
+        self.mesh = mesh
+        self._h = C.c_void_p()
+        desc = mesh.desc()
+        check(lib().hmg_hierarchy_create(C.byref(desc), strategy.encode(), pseq, h_min, smoother_degree,
+                                         mg_prec, lmax_seed, C.byref(self._h)))
+        n, ws = C.c_int64(), C.c_size_t()
+        check(lib().hmg_hierarchy_query(self._h, C.byref(n), C.byref(ws)))
+        self.n_dofs, self.ws_bytes = n.value, ws.value
+        self.ws = _workspace(ws.value)
+        check(lib().hmg_hierarchy_bind(self._h, ptr(self.ws), ws.value, stream()))
+
+    def levels(self):
+        n = C.c_int()
+        check(lib().hmg_hierarchy_levels(self._h, C.byref(n)))
+        out = []
+        for l in range(n.value):
+            info = LevelInfo()
+            check(lib().hmg_hierarchy_level_info(self._h, l, C.byref(info)))
+            out.append({"space": "DG" if info.space == DG else "FE", "degree": info.degree,
+                        "nel": tuple(info.nel), "prec": info.prec, "n_dofs": info.n_dofs,
+                        "lmax": info.lmax})
+        return out
+
+    def set_lmax(self, l, lmax):
+        check(lib().hmg_hierarchy_set_lmax(self._h, l, lmax))
+
+    def vcycle(self, b, x=None):
+        torch = _torch()
+        x = torch.zeros_like(b) if x is None else x
+        check(lib().hmg_vcycle(self._h, ptr(b), ptr(x), stream()))
+        return x
+
+    def solve(self, b, x=None, rtol=1e-10, atol=0.0, maxit=200, allow_not_converged=False):
+        torch = _torch()
+        x = torch.zeros_like(b) if x is None else x
+        st = SolveStats()
+        code = lib().hmg_pcg_solve(self._h, ptr(b), ptr(x), rtol, atol, maxit, C.byref(st), stream())
+        check(code, allow=(0, 1) if allow_not_converged else (0,))
+        return x, {"iters": st.iters, "r0": st.r0, "rn": st.rn, "rho": st.rho, "n10": st.n10,
+                   "status": STATUS.get(code, code)}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.hmg_hierarchy_destroy(self._h)
+            self._h = C.c_void_p()

@@ -1,0 +1,36 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle
+comparisons.  Random numbers only: nothing here computes any part of the
+method.  Seeds follow numpy.random.default_rng(20191004 + i).
+
+Workloads (the paper's cube test case, Sec. 5.3, on [0,1]^3 with Dirichlet
+conditions; curvilinear meshes move every coordinate by
+amp * prod_j sin(pi s_j) and use a degree-3 mapping):
+  cube_k3_8      Cartesian 8^3, k = 3 (32,768 DoFs)
+  curved_k4_64   curvilinear 64^3, k = 4 (32,768,000 DoFs), amp 0.05
+  curved_k7_48   curvilinear 48^3, k = 7 (56,623,104 DoFs), amp 0.05,
+                 per-element penalty scale ~ U[1, 10]
+"""
+import numpy as np
+
+BASE_SEED = 20191004
+
+
+def rng(i):
+    return np.random.default_rng(BASE_SEED + i)
+
+
+def uniform(i, n, lo=-1.0, hi=1.0):
+    """n FP64 values ~ U[lo, hi) from stream i."""
+    return rng(i).uniform(lo, hi, int(n))
+
+
+WORKLOADS = {
+    "cube_k3_8": dict(nel=(8, 8, 8), degree=3, deformed=False, amp=0.0, tau_scale_seed=None),
+    "curved_k4_64": dict(nel=(64, 64, 64), degree=4, deformed=True, amp=0.05, tau_scale_seed=None),
+    "curved_k7_48": dict(nel=(48, 48, 48), degree=7, deformed=True, amp=0.05, tau_scale_seed=5),
+}
+
+
+def tau_scale(seed_index, n_el):
+    """Per-element penalty factors ~ U[1, 10]."""
+    return rng(seed_index).uniform(1.0, 10.0, int(n_el))

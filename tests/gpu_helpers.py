@@ -1,0 +1,29 @@
+"""Shared helpers of the GPU parity tests: build the same mesh for the HIP
+library and for the oracle, run the oracle, compare."""
+import numpy as np
+
+from oracle import fe as ofe
+from oracle import sipg
+from oracle.mesh import BoxMesh
+from paper_1910_01900_amd import hmg
+
+
+def meshes(nel, k, deformed=False, amp=0.05, waves=1, bc=(0,) * 6, ip=1.0, tau_scale=None,
+           lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    a = amp if deformed else 0.0
+    hm = hmg.Mesh(tuple(nel), k, lo, hi, deformed, a, waves, tuple(bc), ip, tau_scale)
+    om = BoxMesh(tuple(nel), tuple(lo), tuple(hi), deform=a, waves=waves, bc=tuple(bc), tau_scale=tau_scale)
+    return hm, om
+
+
+def to_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def fp32_bound(k):
+    """Componentwise FP32 bound factor: 16 (k+1) 2^-24 times (|A||u|)_i."""
+    return 16 * (k + 1) * 2.0 ** -24

@@ -1,0 +1,165 @@
+"""GPU parity of the matrix-free operator (Sec. 4) against the oracle's
+plain definition (Sec. 2): DG SIPG and continuous FE, Cartesian and
+curvilinear, k = 1..7, mixed boundary conditions, scaled penalties, ragged
+meshes (element counts not divisible by the elements per workgroup)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import fp32_bound, meshes, rel_inf, to_np
+from oracle import fe as ofe
+from oracle import sipg
+from paper_1910_01900_amd import hmg
+from paper_1910_01900_amd.inputs import tau_scale, uniform
+
+pytestmark = pytest.mark.gpu
+
+NEL = (5, 3, 3)  # 45 elements: a ragged tail for every elements-per-block choice but k=6
+
+
+@pytest.mark.parametrize("k", range(1, 8))
+@pytest.mark.parametrize("deformed", [False, True])
+def test_dg_apply_fp64_matches_oracle(k, deformed):
+    nel = NEL if k != 6 else (4, 3, 4)
+    hm, om = meshes(nel, k, deformed, bc=(0, 1, 0, 0, 1, 0), waves=2, amp=0.08)
+    print("dg_apply k=%d deformed=%s nel=%s" % (k, deformed, nel), flush=True)
+    L = hmg.Level(hm)
+    u = uniform(1, L.n_dofs)
+    v = to_np(L.apply(L.vector(u)))
+    ref = sipg.apply(om, k, u).ravel()
+    assert rel_inf(v, ref) < 1e-12
+    if k <= 3:
+        A = sipg.assemble(om, k)
+        bound = abs(A) @ np.abs(u)
+        assert np.all(np.abs(v - ref) <= 1e-12 * bound + 1e-300)
+
+
+@pytest.mark.parametrize("k", [2, 5])
+@pytest.mark.parametrize("deformed", [False, True])
+def test_dg_apply_scaled_penalty_and_ip(k, deformed):
+    nel = (3, 4, 2)
+    ts = tau_scale(5, 24)
+    hm, om = meshes(nel, k, deformed, ip=10.0, tau_scale=ts, lo=(0.0, -0.5, 0.2), hi=(1.5, 1.0, 0.9))
+    L = hmg.Level(hm)
+    u = uniform(2, L.n_dofs)
+    v = to_np(L.apply(L.vector(u)))
+    ref = sipg.apply(om, k, u, ip_factor=10.0).ravel()
+    assert rel_inf(v, ref) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 7])
+@pytest.mark.parametrize("deformed", [False, True])
+def test_dg_apply_fp32_within_bound(k, deformed):
+    hm, om = meshes(NEL, k, deformed, bc=(0, 1, 0, 0, 1, 0))
+    L = hmg.Level(hm, prec=hmg.F32)
+    u = uniform(1, L.n_dofs).astype(np.float32).astype(np.float64)
+    v = to_np(L.apply(L.vector(u)))
+    ref = sipg.apply(om, k, u).ravel()
+    err = rel_inf(v, ref)
+    print("fp32 k=%d deformed=%s normwise rel err %.3e" % (k, deformed, err))
+    assert err < 1e-5
+    if k <= 3:
+        A = sipg.assemble(om, k)
+        bound = abs(A) @ np.abs(u)
+        ratio = np.max(np.abs(v - ref) / (fp32_bound(k) * bound))
+        print("max componentwise ratio %.3f" % ratio)
+        assert ratio <= 1.0
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+@pytest.mark.parametrize("deformed", [False, True])
+def test_fe_apply_matches_oracle(k, deformed):
+    hm, om = meshes(NEL, k, deformed, bc=(0, 1, 0, 0, 1, 0))
+    L = hmg.Level(hm, space=hmg.FE)
+    u = uniform(3, L.n_dofs)
+    v = to_np(L.apply(L.vector(u)))
+    A = ofe.assemble(om, k)
+    ref = A @ u
+    assert rel_inf(v, ref) < 1e-12
+    assert np.all(np.abs(v - ref) <= 1e-12 * (abs(A) @ np.abs(u)))
+
+
+@pytest.mark.parametrize("space", [hmg.DG, hmg.FE])
+@pytest.mark.parametrize("deformed", [False, True])
+def test_diagonal_matches_oracle(space, deformed):
+    k = 3
+    hm, om = meshes(NEL, k, deformed, bc=(1, 0, 0, 1, 0, 0), tau_scale=tau_scale(7, 45))
+    L = hmg.Level(hm, space=space)
+    d = to_np(L.diagonal())
+    ref = sipg.assemble(om, k).diagonal() if space == hmg.DG else ofe.assemble(om, k).diagonal()
+    assert rel_inf(d, ref) < 1e-12
+
+
+def test_residual_and_determinism():
+    k = 4
+    hm, om = meshes((4, 4, 3), k, True)
+    L = hmg.Level(hm)
+    u = L.vector(uniform(4, L.n_dofs))
+    b = L.vector(uniform(5, L.n_dofs))
+    r = to_np(L.residual(b, u))
+    ref = to_np(b) - sipg.apply(om, k, to_np(u)).ravel()
+    assert rel_inf(r, ref) < 1e-12
+    v1 = L.apply(u)
+    v2 = L.apply(u)
+    assert bool((v1 == v2).all())
+
+
+def test_symmetry_on_gpu():
+    k = 3
+    hm, _ = meshes((3, 3, 3), k, True, waves=2, amp=0.1)
+    L = hmg.Level(hm)
+    u = L.vector(uniform(6, L.n_dofs))
+    w = L.vector(uniform(7, L.n_dofs))
+    a = float((u * L.apply(w)).sum())
+    b = float((w * L.apply(u)).sum())
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_single_element_and_one_layer():
+    for nel in ((1, 1, 1), (7, 1, 1), (1, 1, 9)):
+        hm, om = meshes(nel, 3, True, bc=(0, 1, 1, 0, 0, 1))
+        L = hmg.Level(hm)
+        u = uniform(8, L.n_dofs)
+        assert rel_inf(to_np(L.apply(L.vector(u))), sipg.apply(om, 3, u).ravel()) < 1e-12
+
+
+@pytest.mark.parametrize("deformed", [False, True])
+def test_rhs_sine_matches_oracle(deformed):
+    k = 3
+    hm, om = meshes((3, 2, 2), k, deformed, lo=(0, 0, 0), hi=(1.1, 0.9, 1.0), bc=(0, 1, 0, 0, 0, 1))
+    L = hmg.Level(hm)
+    freq = 2.5
+    b = to_np(L.rhs_sine(freq))
+    u = lambda X: np.prod(np.sin(freq * X), axis=-1)
+    ref = sipg.rhs(om, k, lambda X: 3 * freq ** 2 * u(X), g=u)
+    assert rel_inf(b, ref) < 1e-12
+
+
+@pytest.mark.parametrize("space", [hmg.DG, hmg.FE])
+@pytest.mark.parametrize("x_is_zero", [True, False])
+@pytest.mark.parametrize("degree", [1, 4, 5])
+def test_chebyshev_matches_oracle(space, x_is_zero, degree):
+    from oracle import solver
+    k = 2
+    hm, om = meshes((3, 3, 2), k, True)
+    L = hmg.Level(hm, space=space)
+    A = sipg.assemble(om, k) if space == hmg.DG else ofe.assemble(om, k)
+    dinv = 1.0 / A.diagonal()
+    b = uniform(9, L.n_dofs)
+    x0 = np.zeros(L.n_dofs) if x_is_zero else uniform(10, L.n_dofs)
+    lmax = 1.7
+    x = L.vector(x0)
+    L.chebyshev(L.vector(b), x, degree, lmax, x_is_zero=x_is_zero)
+    ref = solver.chebyshev(A, dinv, b, x0, degree, lmax)
+    assert rel_inf(to_np(x), ref) < 1e-12
+
+
+@pytest.mark.parametrize("space", [hmg.DG, hmg.FE])
+def test_lambda_max_matches_oracle(space):
+    from oracle import rng, solver
+    k = 2
+    hm, om = meshes((3, 3, 3), k, True, waves=2, amp=0.1)
+    L = hmg.Level(hm, space=space)
+    A = sipg.assemble(om, k) if space == hmg.DG else ofe.assemble(om, k)
+    ref = solver.lanczos_lmax(A, 1.0 / A.diagonal(), rng.uniform_pm1(11, A.shape[0]), 20)
+    got = L.lambda_max(20, 11)
+    assert abs(got - ref) <= 1e-9 * ref
