@@ -1,0 +1,198 @@
+"""Benchmark: PCG + hybrid multigrid solve on one MI355X.
+
+Workload (default): the curvilinear cube of 64^3 elements, degree k = 4
+(32,768,000 DoFs, x_i += 0.05 prod sin(pi x_j), cubic mapping), Dirichlet
+boundary, seeded U[-1,1] right-hand side.  One step = one full solve from
+x_0 = 0 to ||r||/||r_0|| <= 1e-10: FP64 preconditioned CG (Alg. 1) with one
+V-cycle per iteration (Alg. 2) over the hybrid hierarchy cph (DG4 -> FE4 ->
+FE2 -> FE1 -> h-coarsening to 4^3) in FP32, Chebyshev(5) smoothing (Alg. 3)
+and an exact FP64 coarse solve.  `value` is DoFs solved per second
+(N * steps / time).  The FP64 and FP32 operator applies are timed on their
+own with HIP events on the launch stream (operator_apply, roofline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoF/s of SIPG operator apply (FP64/FP32); solve time per DoF at 1e-10 rel. residual"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def apply_bytes(nel, k, prec_bytes, curved):
+    """Algorithmic HBM bytes of one DG operator apply: read u, write v, the
+    stored geometry (6 metric values per cell quadrature point, 7 values
+    per face quadrature point on every face once) and tau per element."""
+    Nx, Ny, Nz = nel
+    n = k + 1
+    ne = Nx * Ny * Nz
+    dofs = ne * n ** 3
+    b = 2 * dofs * prec_bytes + ne * prec_bytes
+    if curved:
+        faces = (Nx + 1) * Ny * Nz + Nx * (Ny + 1) * Nz + Nx * Ny * (Nz + 1)
+        b += ne * 6 * n ** 3 * prec_bytes + faces * 7 * n * n * prec_bytes
+    return b
+
+
+def time_applies(L, u, v, reps):
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        L.apply(u, v)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        L.apply(u, v)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps  # ms per apply
+
+
+def cpu_baseline(w, u_host, budget_s=20.0):
+    """The oracle's element-wise apply (O(n^6) dense tabulations) on a
+    bounded sample of elements of the same mesh, timed on the host."""
+    from threadpoolctl import threadpool_info
+    from oracle import sipg
+    from oracle.mesh import BoxMesh
+    k = w["degree"]
+    om = BoxMesh(tuple(w["nel"]), deform=w["amp"] if w["deformed"] else 0.0)
+    n_el = int(np.prod(w["nel"]))
+    count, elapsed = 64, 0.0
+    sel = None
+    while True:
+        sel = np.arange(count) * (n_el // count)
+        t0 = time.perf_counter()
+        sipg.apply(om, k, u_host, elems=sel)
+        elapsed = time.perf_counter() - t0
+        if elapsed > budget_s / 4 or count >= n_el:
+            break
+        count *= 4
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    dofs = len(sel) * (k + 1) ** 3
+    return {"value": dofs / elapsed, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
+            "sample": "FP64 operator apply of %d elements spread over the %s mesh (%d DoFs), %.1f s"
+                      % (len(sel), "x".join(map(str, w["nel"])), dofs, elapsed)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="curved_k4_64")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (a.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_01900_amd import hmg
+    from paper_1910_01900_amd.inputs import WORKLOADS, tau_scale, uniform
+
+    w = WORKLOADS[a.workload]
+    k = w["degree"]
+    n_el = int(np.prod(w["nel"]))
+    ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
+    mesh = hmg.Mesh(tuple(w["nel"]), k, deformed=w["deformed"], amp=w["amp"], tau_scale=ts)
+    torch.cuda.set_device(0)
+
+    t0 = time.time()
+    log("setup: hierarchy cph (FP32 V-cycle) for", a.workload)
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32)
+    log("setup done in %.1f s; levels:" % (time.time() - t0),
+        [(l["space"], l["degree"], l["nel"][0]) for l in H.levels()])
+    N = H.n_dofs
+    b = torch.as_tensor(uniform(3, N), device="cuda")
+    x = torch.zeros_like(b)
+
+    for i in range(a.warmup):
+        x.zero_()
+        _, st = H.solve(b, x, rtol=1e-10, maxit=100)
+        log("warmup solve %d: %d iterations, n10 %.2f" % (i, st["iters"], st["n10"]))
+    torch.cuda.synchronize()
+    times, stats = [], None
+    t_start = time.perf_counter()
+    for i in range(a.steps):
+        x.zero_()
+        t1 = time.perf_counter()
+        _, stats = H.solve(b, x, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        log("step %d: %.1f ms, %d iterations" % (i, times[-1] * 1e3, stats["iters"]))
+    total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * total / a.steps
+
+    # final residual recomputed with the FP64 operator
+    L64 = hmg.Level(mesh, prec=hmg.F64)
+    r = L64.residual(b, x)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    log("final relative residual %.3e" % rel)
+
+    # operator applies, timed with HIP events on the launch stream
+    u = L64.vector(uniform(1, L64.n_dofs))
+    v = L64.vector()
+    ms64 = time_applies(L64, u, v, a.apply_reps)
+    u_host = u.cpu().numpy() if not a.no_cpu_baseline else None
+    del u, v, r
+    L32 = hmg.Level(mesh, prec=hmg.F32)
+    u32 = L32.vector(uniform(1, L32.n_dofs))
+    v32 = L32.vector()
+    ms32 = time_applies(L32, u32, v32, a.apply_reps)
+    del u32, v32
+    bytes64 = apply_bytes(w["nel"], k, 8, w["deformed"])
+    achieved = bytes64 / (ms64 * 1e-3) / 1e9
+    log("apply FP64 %.3f ms (%.2f GDoF/s, %.0f GB/s), FP32 %.3f ms (%.2f GDoF/s)"
+        % (ms64, N / ms64 / 1e6, achieved, ms32, N / ms32 / 1e6))
+
+    out = {
+        "metric": METRIC,
+        "value": N * a.steps / total,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (outer CG) / f32 (V-cycle)",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "mesh": "x".join(map(str, w["nel"])), "degree": k,
+                   "curved": w["deformed"], "dofs": N, "strategy": "cph", "p_sequence": "floor(p/2)",
+                   "smoother": "Chebyshev(5)", "coarse": "exact FP64, FE1 4^3", "rtol": 1e-10,
+                   "parallelism": "single GPU"},
+        "solve": {"ns_per_dof": 1e9 * (total / a.steps) / N, "iterations": stats["iters"],
+                  "n10": stats["n10"], "rho": stats["rho"], "final_rel_residual": rel},
+        "operator_apply": {"fp64_dofs_per_s": N / (ms64 * 1e-3), "fp32_dofs_per_s": N / (ms32 * 1e-3),
+                           "fp64_ms": ms64, "fp32_ms": ms32},
+        "roofline": {"kernel": "op_kernel<5,double,curved,DG,APPLY>", "bound": "hbm",
+                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes64},
+    }
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w, u_host)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -238,7 +238,7 @@ static int level_init(const Mesh& m, int space, int prec, hmg_level** out) {
                               : ((int64_t)m.N[0] * m.k + 1) * ((int64_t)m.N[1] * m.k + 1) *
                                     ((int64_t)m.N[2] * m.k + 1);
   L->basis = make_basis(m.k);
-  int rc = build_geometry(m, L->basis, L->geom);
+  int rc = build_geometry(m, L->basis, L->geom, space == HMG_DG);
   if (rc) {
     delete L;
     return rc;

@@ -96,7 +96,7 @@ struct Geometry {
   std::vector<double> face[3];
   std::vector<double> tau;
 };
-int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g);  // curved or affine
+int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g, bool faces);  // curved or affine
 // Physical point and Jacobian at reference point xi of element e (Q3 map).
 void map_point(const Mesh& m, int64_t e, const double xi[3], double x[3], double J[9]);
 int rhs_sine_host(const Mesh& m, const Basis1D& b, const Geometry& g, double freq,

@@ -303,7 +303,7 @@ static void face_normals(const std::vector<double>& J, const Basis1D& b, int d, 
   }
 }
 
-int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g) {
+int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g, bool faces) {
   const int n = b.n, n3 = n * n * n, nf = n * n;
   const int64_t ne = m.n_el();
   g.tau.assign(ne, 0.0);
@@ -352,7 +352,7 @@ int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g) {
     double sc = m.tau_scale.empty() ? 1.0 : m.tau_scale[e];
     g.tau[e] = m.ip * sc * (double)(n * n) * area / vol;
   });
-  if (!m.curved) return HMG_OK;
+  if (!m.curved || !faces) return HMG_OK;
   // face data: 3 directions, (N_d + 1) * N_a * N_b faces each
   for (int d = 0; d < 3; ++d) {
     int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
