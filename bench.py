@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--workload", default="curved_k4_64")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
+                    help="only time the operator apply (and a 1 GiB copy used to calibrate "
+                         "HBM counters); for profiling")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -113,6 +116,22 @@ def main():
     ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
     mesh = hmg.Mesh(tuple(w["nel"]), k, deformed=w["deformed"], amp=w["amp"], tau_scale=ts)
     torch.cuda.set_device(0)
+
+    if a.apply_only:
+        prec = hmg.F64 if a.apply_only == "f64" else hmg.F32
+        L = hmg.Level(mesh, prec=prec)
+        u = L.vector(uniform(1, L.n_dofs))
+        v = L.vector()
+        ms = time_applies(L, u, v, a.apply_reps)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        nb = apply_bytes(w["nel"], k, 8 if prec == hmg.F64 else 4, w["deformed"])
+        print(json.dumps({"workload": a.workload, "prec": a.apply_only, "ms_per_apply": ms,
+                          "dofs_per_s": L.n_dofs / (ms * 1e-3), "algorithmic_bytes": nb,
+                          "achieved_GBs": nb / (ms * 1e-3) / 1e9, "calibration_copy_bytes": 1 << 30}))
+        return
 
     t0 = time.time()
     log("setup: hierarchy cph (FP32 V-cycle) for", a.workload)
