@@ -34,7 +34,9 @@ struct Basis1D {
   std::vector<double> Sp;           // Sp[q][i] = l_i'(z_q)
   std::vector<double> D;            // D[q][r]  = derivative of the Gauss Lagrange basis r at z_q
   std::vector<double> M;            // M[i][j]  = sum_q w_q l_i(z_q) l_j(z_q) (1-D mass)
+  std::vector<double> K;            // K[i][j]  = sum_q w_q l_i'(z_q) l_j'(z_q) (1-D stiffness)
   std::vector<double> dl0, dl1;     // l_i'(0), l_i'(1)
+  std::vector<double> lg0, lg1;     // Gauss-point Lagrange basis at 0 and 1
 };
 Basis1D make_basis(int k);
 std::vector<double> gll_nodes(int k);
@@ -46,7 +48,7 @@ void lagrange(const std::vector<double>& nodes, const std::vector<double>& x,
 // Kernel-argument copy of the tables for a compile-time n.
 template <int N, typename T>
 struct OpTab {
-  T S[N * N], Sp[N * N], D[N * N], M[N * N], dl0[N], dl1[N], w[N];
+  T S[N * N], Sp[N * N], D[N * N], M[N * N], K[N * N], dl0[N], dl1[N], lg0[N], lg1[N], w[N];
 };
 template <int N, typename T>
 OpTab<N, T> make_tab(const Basis1D& b) {
@@ -56,10 +58,13 @@ OpTab<N, T> make_tab(const Basis1D& b) {
     t.Sp[i] = (T)b.Sp[i];
     t.D[i] = (T)b.D[i];
     t.M[i] = (T)b.M[i];
+    t.K[i] = (T)b.K[i];
   }
   for (int i = 0; i < N; ++i) {
     t.dl0[i] = (T)b.dl0[i];
     t.dl1[i] = (T)b.dl1[i];
+    t.lg0[i] = (T)b.lg0[i];
+    t.lg1[i] = (T)b.lg1[i];
     t.w[i] = (T)b.gw[i];
   }
   return t;
@@ -120,7 +125,7 @@ struct hmg_level {
   // workspace layout (byte offsets) and bound pointers
   size_t ws_bytes = 0;
   size_t off_metric = 0, off_face[3] = {0, 0, 0}, off_tau = 0, off_diag = 0, off_dinv = 0, off_tmp = 0,
-         off_scratch = 0, off_part = 0, off_scal = 0;
+         off_scratch = 0, off_part = 0, off_scal = 0, off_ltab = 0;
   char* ws = nullptr;
   bool bound = false;
   size_t elem_size() const { return prec == HMG_F64 ? 8 : 4; }
@@ -133,6 +138,8 @@ struct hmg_level {
   void* scratch() const { return ws + off_scratch; }  // DG-layout buffer (FE levels)
   double* partials() const { return (double*)(ws + off_part); }
   double* scal() const { return (double*)(ws + off_scal); }
+  // 1-D tables the operator kernel indexes per lane: S, Sp, M (n x n), l'(0), l'(1)
+  void* ltab() const { return ws + off_ltab; }
   size_t vec_bytes() const { return (size_t)n_dofs * elem_size(); }
 };
 

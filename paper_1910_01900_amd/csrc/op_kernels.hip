@@ -1,41 +1,50 @@
 // Matrix-free SIPG / continuous-FE Laplace operator for gfx950 (Sec. 4,
 // eq:MatrixFreeAbstractNotation) and its launchers.
 //
-// Work decomposition: one workgroup owns E consecutive elements (x-fastest
-// numbering), n^2 threads per element.  Thread t of an element owns one
-// line of n points along a direction that changes from phase to phase
-// (x-lines: t = j + n*l, y-lines: t = i + n*l, z-lines: t = i + n*j), so
-// every 1-D contraction is a register-only loop with the n x n table in
-// scalar registers (kernel arguments), and only the change of direction
-// goes through LDS.
+// Work decomposition: every wavefront owns EW = 64 / n^2 elements outright
+// (n^2 lanes per element) and a private LDS region; all exchanges between
+// lanes stay inside the wavefront, so phases are separated by wavefront
+// fences instead of workgroup barriers and the four wavefronts of a
+// workgroup progress independently (the latency of one hides behind the
+// others).  Lane t of an element owns one line of n points along the
+// direction of the current phase (x-lines: t = j + n*l, y-lines:
+// t = i + n*l, z-lines: t = i + n*j), so every 1-D contraction is a
+// register-only loop with the n x n tables in scalar registers; LDS only
+// changes the direction.
 //
-// Cell integral (Sec. 4): interpolate to Gauss points (3 sweeps with S),
-// collocation gradient at the Gauss points (3 sweeps with D), quadrature-
-// point operator (stored w|det J| J^{-1} J^{-T} for curved cells, constant
-// diagonal for affine ones), integration with the transposed sweeps.
-//
-// Face integrals (cell-based loop, Sec. 2 fluxes): each element evaluates
-// all six faces from its own side; the neighbour trace is gathered from
-// global memory (L2).  Traces are formed on the nodal face (GLL: the face
-// value is the end node, the normal derivative a dot product along the
-// line), taken to the face Gauss points with 2-D sweeps, the flux is
-// applied pointwise, and the test side returns to the nodal face with the
-// transposed sweeps and is added to the element result.  No element writes
-// to another element's output: deterministic, no atomics.
+// Curvilinear cells (Sec. 4): interpolation to the Gauss points (3 sweeps
+// with S), collocation gradient (3 sweeps with D), the stored metric
+// w |det J| J^{-1} J^{-T}, integration (transposed sweeps).  Faces (Sec. 2
+// fluxes, cell-based loop): the own trace and reference gradient at a face
+// point are extrapolated along the normal line from the cell's Gauss-point
+// values (Gauss Lagrange basis at 0 or 1; exact, both are polynomials of
+// degree <= k along that line); the neighbour's trace comes from its nodal
+// face data (global memory / L2) with 2-D face sweeps; the face test
+// functions go back into the cell integration arrays along the same normal
+// line, so the face integrals share the cell's integration sweeps.  Affine
+// cells use the nodal form sum_d c_d K_d (x) M (x) M (7 sweeps) and their
+// faces collapse to face mass-matrix products in nodal space.  No element
+// writes another element's output: deterministic, no atomics.
 #include "hmg_internal.h"
 
 namespace hmg {
 
 #ifndef HMG_DISPATCH_ONLY
-template <int N>
+template <int N, bool CURVED, bool FE>
 struct Cfg {
   static constexpr int NT = N * N;
   static constexpr int N3 = N * N * N;
-  static constexpr int E = (256 / NT) >= 1 ? 256 / NT : 1;
-  static constexpr int THREADS = ((E * NT + 63) / 64) * 64;
-  static constexpr int FACE = 12 * NT;
-  static constexpr int WORK = (2 * N3 > FACE) ? 2 * N3 : FACE;
-  static constexpr int PER = N3 + WORK;
+  static constexpr int EW = 64 / NT >= 1 ? 64 / NT : 1;  // elements per wavefront
+  static constexpr int WAVES = 4;
+  static constexpr int EB = EW * WAVES;  // elements per workgroup
+  // LDS values per element: curved uses 4 arrays (value/flux x, y, z) and,
+  // for DG, 18 n^2 neighbour face values; affine uses 3 arrays and 4 n^2
+  // face values.
+  static constexpr int PER = CURVED ? (FE ? 4 * N3 : (4 * N3 > 18 * NT ? 4 * N3 : 18 * NT))
+                                    : (FE ? 3 * N3 : (3 * N3 > N3 + 4 * NT ? 3 * N3 : N3 + 4 * NT));
+  // per-wavefront copy of the tables indexed by lane: S, Sp, M, l'(0), l'(1)
+  static constexpr int LT = 3 * NT + 2 * N;
+  static constexpr int LT_S = 0, LT_SP = NT, LT_M = 2 * NT, LT_DL0 = 3 * NT, LT_DL1 = 3 * NT + N;
 };
 
 template <int N, typename T>
@@ -50,6 +59,7 @@ struct OpArgs {
   const T* metric;
   const T* face[3];
   const T* tau;
+  const T* ltab;  // S, Sp, M, l'(0), l'(1) in device memory (indexed per lane)
   int64_t nel;
   int Nx, Ny, Nz, bcmask;
   T h[3];
@@ -64,263 +74,305 @@ __device__ __forceinline__ int xcd_block() {
   return x * per + min(x, rem) + y;
 }
 
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  }
-  return s;
+// Order LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ------------------------------------------------------------------ faces
-template <int N, typename T, bool CURVED, int d>
-__device__ __forceinline__ void face_pass(const OpArgs<N, T>& a, const T* A, T* F, bool act, int t,
-                                          int64_t e, const int ec[3], T vacc[N]) {
-  constexpr int NT = N * N, N3 = N * N * N;
-  constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
-  const auto& tb = a.tab;
-  const int ta = t % N, tbb = t / N;
-  auto lidx = [&](int m) -> int {
-    if (d == 0) return m + N * t;
-    if (d == 1) return ta + N * m + NT * tbb;
-    return t + NT * m;
-  };
-  const int Nd = d == 0 ? a.Nx : (d == 1 ? a.Ny : a.Nz);
-  const int64_t stride = d == 0 ? 1 : (d == 1 ? (int64_t)a.Nx : (int64_t)a.Nx * a.Ny);
-  T Po[2] = {0, 0}, Qo[2] = {0, 0}, Pn[2] = {0, 0}, Qn[2] = {0, 0};
-  bool has[2] = {false, false};
-  T taue = 0, taun[2] = {0, 0};
-  if (act) {
-    T line[N];
+// Index of point m on the line of lane t along direction d (x-fastest n^3).
+template <int N, int d>
+__device__ __forceinline__ int lidx(int t, int m) {
+  constexpr int NT = N * N;
+  if (d == 0) return m + N * t;
+  if (d == 1) return (t % N) + N * m + NT * (t / N);
+  return t + NT * m;
+}
+
+template <int N, typename T, int d>
+__device__ __forceinline__ void read_line(const T* A, int t, T (&x)[N]) {
 #pragma unroll
-    for (int m = 0; m < N; ++m) line[m] = A[lidx(m)];
-    Po[0] = line[0];
-    Po[1] = line[N - 1];
+  for (int m = 0; m < N; ++m) x[m] = A[lidx<N, d>(t, m)];
+}
+template <int N, typename T, int d>
+__device__ __forceinline__ void write_line(T* A, int t, const T (&x)[N]) {
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      Qo[0] += tb.dl0[m] * line[m];
-      Qo[1] += tb.dl1[m] * line[m];
-    }
-    taue = a.tau[e];
+  for (int m = 0; m < N; ++m) A[lidx<N, d>(t, m)] = x[m];
+}
+// y[q] = sum_m M[q][m] x[m]  (M row-major n x n)
+template <int N, typename T>
+__device__ __forceinline__ void mat(const T* M, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      has[s] = s ? (ec[d] + 1 < Nd) : (ec[d] > 0);
-      if (has[s]) {
-        const int64_t en = e + (s ? stride : -stride);
-        const T* un = a.u + en * N3;
-        T nl[N];
+  for (int q = 0; q < N; ++q) {
+    T s = 0;
 #pragma unroll
-        for (int m = 0; m < N; ++m) nl[m] = un[lidx(m)];
-        Pn[s] = s ? nl[0] : nl[N - 1];
-        T q = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) q += (s ? tb.dl0[m] : tb.dl1[m]) * nl[m];
-        Qn[s] = q;
-        taun[s] = a.tau[en];
-      }
-    }
+    for (int m = 0; m < N; ++m) s += M[q * N + m] * x[m];
+    y[q] = s;
   }
-  bool dir[2], neu[2];
+}
+// y[i] = sum_q M[q][i] x[q]  (transpose)
+template <int N, typename T>
+__device__ __forceinline__ void matT(const T* M, const T (&x)[N], T (&y)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) s += M[q * N + i] * x[q];
+    y[i] = s;
+  }
+}
+
+template <int d>
+__device__ __forceinline__ int64_t dstride(int Nx, int Ny) {
+  return d == 0 ? 1 : (d == 1 ? (int64_t)Nx : (int64_t)Nx * Ny);
+}
+
+// Penalty of a face: max of the two element values (Sec. 2), the own value
+// on the boundary.
+template <int N, typename T>
+__device__ __forceinline__ T tau_face(const OpArgs<N, T>& a, int64_t e, bool has, int64_t en) {
+  const T te = a.tau[e];
+  if (!has) return te;
+  const T tn = a.tau[en];
+  return te > tn ? te : tn;
+}
+
+// Geometry of face (d, s) of the element at ec: the 7 x n^2 block
+// (n^T J_L^{-T}, n^T J_R^{-T}, surface weight) of that face, n pointing
+// from the lower (L) to the upper (R) element.
+template <int N, typename T, int d>
+__device__ __forceinline__ const T* face_ptr(const OpArgs<N, T>& a, const int ec[3], int s) {
+  constexpr int NT = N * N;
+  constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+  const int Nd = d == 0 ? a.Nx : (d == 1 ? a.Ny : a.Nz);
+  const int Na = da == 0 ? a.Nx : a.Ny;
+  const int64_t f = (ec[d] + s) + (int64_t)(Nd + 1) * (ec[da] + (int64_t)Na * ec[db]);
+  return a.face[d] + f * 7 * NT;
+}
+
+// ------------------------------------------------------------------ curved faces
+// Neighbour nodal face data of the two faces of direction d: the end-node
+// value P and the normal derivative Q of the neighbour's polynomial on the
+// shared face.  F: LDS scratch, 2 values per face.
+template <int N, typename T, int d>
+__device__ __forceinline__ void nb_nodal(const OpArgs<N, T>& a, T* F, bool act, int t, int64_t e,
+                                         const bool has[6]) {
+  constexpr int NT = N * N, N3 = N * N * N;
+  const int64_t stride = dstride<d>(a.Nx, a.Ny);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const bool isneu = (a.bcmask >> (2 * d + s)) & 1;
-    dir[s] = !has[s] && !isneu;
-    neu[s] = !has[s] && isneu;
+    const int f = 2 * d + s;
+    T P = 0, Q = 0;
+    if (act && has[f]) {
+      const T* un = a.u + (e + (s ? stride : -stride)) * N3;
+      T nl[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) nl[m] = un[lidx<N, d>(t, m)];
+      P = s ? nl[0] : nl[N - 1];
+#pragma unroll
+      for (int m = 0; m < N; ++m) Q += (s ? a.tab.dl0[m] : a.tab.dl1[m]) * nl[m];
+    }
+    if (act) {
+      F[(2 * f) * NT + t] = P;
+      F[(2 * f + 1) * NT + t] = Q;
+    }
   }
+}
 
-  if constexpr (!CURVED) {
-    // Affine: n^T J^{-T} = (2s-1)/h_d e_d on both sides, surface weight
-    // h_a h_b w_a w_b, so the flux collapses to two nodal face arrays
-    // R1 = tau [u] - c {Q}/... followed by the face mass matrix M x M.
-    const T hd = a.h[d], hab = a.h[da] * a.h[db];
-    T R[4];
+// Second face sweep (along the b direction) of the neighbour data and the
+// normal derivative against the own outward normal.  F holds, per face, the
+// a-sweep results (value, a-derivative, normal derivative).
+template <int N, typename T, int d>
+__device__ __forceinline__ void nb_finish(const OpArgs<N, T>& a, const T* F, const T* LT, bool act,
+                                          int t, const int ec[3], const bool has[6], T (&un)[6],
+                                          T (&dnn)[6]) {
+  constexpr int NT = N * N;
+  constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+  const int ta = t % N, tb = t / N;
+  const T* Srow = LT + tb * N;
+  const T* Sprow = LT + NT + tb * N;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int f = 2 * d + s;
+    un[f] = 0;
+    dnn[f] = 0;
+    if (!act || !has[f]) continue;
+    T u = 0, ga = 0, gb = 0, gd = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const T sv = Srow[q], sp = Sprow[q];
+      const int o = ta + N * q;
+      const T x1 = F[(3 * f) * NT + o], x2 = F[(3 * f + 1) * NT + o], x3 = F[(3 * f + 2) * NT + o];
+      u += sv * x1;
+      ga += sv * x2;
+      gb += sp * x1;
+      gd += sv * x3;
+    }
+    const T* g = face_ptr<N, T, d>(a, ec, s);
+    T cn[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) cn[r] = s ? g[(3 + r) * NT + t] : -g[r * NT + t];
+    un[f] = u;
+    dnn[f] = cn[d] * gd + cn[da] * ga + cn[db] * gb;
+  }
+}
+
+// Own traces of the two faces of direction d by extrapolation along the
+// d-lines of the Gauss-point data R (u, du/dx, du/dy, du/dz), the flux, and
+// the face test coefficients: vt multiplies the test value, gt the test's
+// normal derivative (Sec. 2, SIPG flux with the mirror principle).
+template <int N, typename T, int d>
+__device__ __forceinline__ void own_flux(const OpArgs<N, T>& a, const T* R, bool act, int t, int64_t e,
+                                         const int ec[3], const bool has[6], const T (&un)[6],
+                                         const T (&dnn)[6], T (&vt)[6], T (&gt)[6]) {
+  constexpr int N3 = N * N * N, NT = N * N;
+  const auto& tab = a.tab;
+  const int64_t stride = dstride<d>(a.Nx, a.Ny);
+  T uq[N], g0[N], g1[N], g2[N];
+  if (act) {
+    read_line<N, T, d>(R, t, uq);
+    read_line<N, T, d>(R + N3, t, g0);
+    read_line<N, T, d>(R + 2 * N3, t, g1);
+    read_line<N, T, d>(R + 3 * N3, t, g2);
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int f = 2 * d + s;
+    vt[f] = 0;
+    gt[f] = 0;
+    if (!act) continue;
+    if (!has[f] && ((a.bcmask >> f) & 1)) continue;  // Neumann: no face term
+    T uo = 0, h0 = 0, h1 = 0, h2 = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const T l = s ? tab.lg1[m] : tab.lg0[m];
+      uo += l * uq[m];
+      h0 += l * g0[m];
+      h1 += l * g1[m];
+      h2 += l * g2[m];
+    }
+    const T* g = face_ptr<N, T, d>(a, ec, s);
+    T co[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) co[r] = s ? g[r * NT + t] : -g[(3 + r) * NT + t];
+    const T dA = g[6 * NT + t];
+    const T dno = co[0] * h0 + co[1] * h1 + co[2] * h2;
+    const T tauF = tau_face(a, e, has[f], e + (s ? stride : -stride));
+    T jump, avg;
+    if (has[f]) {
+      jump = uo - un[f];
+      avg = T(0.5) * (dno + dnn[f]);
+    } else {  // Dirichlet mirror: u+ = -u-, grad u+ = grad u-
+      jump = T(2) * uo;
+      avg = dno;
+    }
+    vt[f] = (tauF * jump - avg) * dA;
+    gt[f] = T(-0.5) * jump * dA;
+  }
+}
+
+// Add the face tests of direction d to the d-lines of the integration
+// arrays (vq: test value, fx/fy/fz: test reference gradient).
+template <int N, typename T, int d>
+__device__ __forceinline__ void inject(const OpArgs<N, T>& a, const int ec[3], int t, const T (&vt)[6],
+                                       const T (&gt)[6], T (&vq)[N], T (&fx)[N], T (&fy)[N], T (&fz)[N]) {
+  constexpr int NT = N * N;
+  const auto& tab = a.tab;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int f = 2 * d + s;
+    const T* g = face_ptr<N, T, d>(a, ec, s);
+    T c[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) c[r] = (s ? g[r * NT + t] : -g[(3 + r) * NT + t]) * gt[f];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const T l = s ? tab.lg1[m] : tab.lg0[m];
+      vq[m] += l * vt[f];
+      fx[m] += l * c[0];
+      fy[m] += l * c[1];
+      fz[m] += l * c[2];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ affine faces
+// Nodal face terms of direction d added to the x-line accumulator vacc.
+// With n^T J^{-T} = +-e_d / h_d on both sides and surface weight
+// h_a h_b w_a w_b, the flux reduces to the plane term tau [u] - c {du/dn}
+// and the normal-derivative term -c/2 [u], each taken through the face mass
+// matrix M (x) M.  A: own nodal u; F: LDS scratch of 4 n^2.
+template <int N, typename T, int d>
+__device__ __forceinline__ void affine_faces(const OpArgs<N, T>& a, const T* A, T* F, const T* LT,
+                                             bool act, int t, int64_t e, const bool has[6],
+                                             T (&vacc)[N]) {
+  constexpr int NT = N * N, N3 = N * N * N;
+  constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+  const auto& tab = a.tab;
+  const int ta = t % N, tbb = t / N;
+  const int64_t stride = dstride<d>(a.Nx, a.Ny);
+  if (act) {
+    T line[N];
+    read_line<N, T, d>(A, t, line);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const T cd = s ? T(1) / hd : T(-1) / hd;
-      const T tauF = has[s] ? (taue > taun[s] ? taue : taun[s]) : taue;
-      T Pj = has[s] ? Po[s] - Pn[s] : (dir[s] ? T(2) * Po[s] : T(0));
-      T Qs = has[s] ? Qo[s] + Qn[s] : (dir[s] ? T(2) * Qo[s] : T(0));
-      if (neu[s]) Pj = Qs = 0;
-      R[2 * s] = tauF * Pj - T(0.5) * cd * Qs;
-      R[2 * s + 1] = -T(0.5) * cd * Pj;
+      const int f = 2 * d + s;
+      const bool neu = !has[f] && ((a.bcmask >> f) & 1);
+      const T Po = line[s * (N - 1)];
+      T Qo = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) Qo += (s ? tab.dl1[m] : tab.dl0[m]) * line[m];
+      T Pj, Qs;
+      if (has[f]) {
+        const T* un = a.u + (e + (s ? stride : -stride)) * N3;
+        T nl[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) nl[m] = un[lidx<N, d>(t, m)];
+        T Qn = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) Qn += (s ? tab.dl0[m] : tab.dl1[m]) * nl[m];
+        Pj = Po - (s ? nl[0] : nl[N - 1]);
+        Qs = Qo + Qn;
+      } else {
+        Pj = neu ? T(0) : T(2) * Po;
+        Qs = neu ? T(0) : T(2) * Qo;
+      }
+      const T cd = (s ? T(1) : T(-1)) / a.h[d];
+      const T tauF = tau_face(a, e, has[f], e + (s ? stride : -stride));
+      F[(2 * s) * NT + t] = tauF * Pj - T(0.5) * cd * Qs;
+      F[(2 * s + 1) * NT + t] = T(-0.5) * cd * Pj;
     }
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) F[c * NT + t] = R[c];
-    __syncthreads();
-    T Z[4] = {0, 0, 0, 0};
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int q = 0; q < N; ++q) Z[c] += tb.M[ta * N + q] * F[c * NT + q + N * tbb];
-    __syncthreads();
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) F[c * NT + t] = Z[c];
-    __syncthreads();
-    T W[4] = {0, 0, 0, 0};
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int q = 0; q < N; ++q) W[c] += tb.M[tbb * N + q] * F[c * NT + ta + N * q];
-        W[c] *= hab;
-      }
-    __syncthreads();
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) F[c * NT + t] = W[c];
-    __syncthreads();
-  } else {
-    // Curved: full reference gradients of both traces at the face Gauss
-    // points, n^T J^{-T} of both sides and the surface weight per point.
-    if (act)
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        F[(s * 6 + 0) * NT + t] = Po[s];
-        F[(s * 6 + 1) * NT + t] = Qo[s];
-        F[(s * 6 + 2) * NT + t] = Pn[s];
-        F[(s * 6 + 3) * NT + t] = Qn[s];
-      }
-    __syncthreads();
-    T X[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) X[c] = 0;
-    if (act)
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          const T sv = tb.S[ta * N + q], sp = tb.Sp[ta * N + q];
-          const T po = F[(s * 6 + 0) * NT + q + N * tbb], qo = F[(s * 6 + 1) * NT + q + N * tbb];
-          const T pn = F[(s * 6 + 2) * NT + q + N * tbb], qn = F[(s * 6 + 3) * NT + q + N * tbb];
-          X[s * 6 + 0] += sv * po;
-          X[s * 6 + 1] += sp * po;
-          X[s * 6 + 2] += sv * qo;
-          X[s * 6 + 3] += sv * pn;
-          X[s * 6 + 4] += sp * pn;
-          X[s * 6 + 5] += sv * qn;
-        }
-    __syncthreads();
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 12; ++c) F[c * NT + t] = X[c];
-    __syncthreads();
-    T Tt[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) Tt[c] = 0;
-    if (act) {
-      const int pos_base = ec[d];
-      const int ea = ec[da], eb = ec[db];
-      const int Na = da == 0 ? a.Nx : a.Ny;
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        T uo = 0, ao = 0, bo = 0, dd = 0, un = 0, an = 0, bn = 0, dn = 0;
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          const T sv = tb.S[tbb * N + q], sp = tb.Sp[tbb * N + q];
-          const int o = ta + N * q;
-          const T x0 = F[(s * 6 + 0) * NT + o], x1 = F[(s * 6 + 1) * NT + o],
-                  x2 = F[(s * 6 + 2) * NT + o];
-          const T x3 = F[(s * 6 + 3) * NT + o], x4 = F[(s * 6 + 4) * NT + o],
-                  x5 = F[(s * 6 + 5) * NT + o];
-          uo += sv * x0;
-          ao += sv * x1;
-          bo += sp * x0;
-          dd += sv * x2;
-          un += sv * x3;
-          an += sv * x4;
-          bn += sp * x3;
-          dn += sv * x5;
-        }
-        if (neu[s]) continue;
-        const int64_t f = (pos_base + s) + (int64_t)(Nd + 1) * (ea + (int64_t)Na * eb);
-        const T* g = a.face[d] + f * 7 * NT;
-        T cL[3], cR[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          cL[r] = g[r * NT + t];
-          cR[r] = g[(3 + r) * NT + t];
-        }
-        const T dA = g[6 * NT + t];
-        T co[3], cn[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          co[r] = s ? cL[r] : -cR[r];
-          cn[r] = s ? cR[r] : -cL[r];
-        }
-        const T dno = co[d] * dd + co[da] * ao + co[db] * bo;
-        T jump, avg, tauF;
-        if (has[s]) {
-          const T dnn = cn[d] * dn + cn[da] * an + cn[db] * bn;
-          jump = uo - un;
-          avg = T(0.5) * (dno + dnn);
-          tauF = taue > taun[s] ? taue : taun[s];
-        } else {
-          jump = T(2) * uo;
-          avg = dno;
-          tauF = taue;
-        }
-        const T vt = (tauF * jump - avg) * dA;
-        const T gt = T(-0.5) * jump * dA;
-        Tt[s * 4 + 0] = vt;
-        Tt[s * 4 + 1] = gt * co[da];
-        Tt[s * 4 + 2] = gt * co[db];
-        Tt[s * 4 + 3] = gt * co[d];
-      }
-    }
-    __syncthreads();
-    if (act)
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) F[(s * 6 + c) * NT + t] = Tt[s * 4 + c];
-    __syncthreads();
-    T Y[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) Y[c] = 0;
-    if (act)
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          const T sv = tb.S[q * N + tbb], sp = tb.Sp[q * N + tbb];
-          const int o = ta + N * q;
-          Y[s * 3 + 0] += sv * F[(s * 6 + 0) * NT + o] + sp * F[(s * 6 + 2) * NT + o];
-          Y[s * 3 + 1] += sv * F[(s * 6 + 1) * NT + o];
-          Y[s * 3 + 2] += sv * F[(s * 6 + 3) * NT + o];
-        }
-    __syncthreads();
-    if (act)
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) F[(s * 6 + c) * NT + t] = Y[s * 3 + c];
-    __syncthreads();
-    T Pq[4] = {0, 0, 0, 0};
-    if (act)
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          const T sv = tb.S[q * N + ta], sp = tb.Sp[q * N + ta];
-          const int o = q + N * tbb;
-          Pq[s * 2 + 0] += sv * F[(s * 6 + 0) * NT + o] + sp * F[(s * 6 + 1) * NT + o];
-          Pq[s * 2 + 1] += sv * F[(s * 6 + 2) * NT + o];
-        }
-    __syncthreads();
-    if (act)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) F[c * NT + t] = Pq[c];
-    __syncthreads();
   }
-  // F[(2s)*NT + node] = plane contribution, F[(2s+1)*NT + node] = weight of
-  // l_p'(s) along the face normal.  Add into this thread's x-line.
+  wave_sync();
+  T Z[4] = {0, 0, 0, 0};
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < N; ++q) Z[c] += LT[2 * NT + ta * N + q] * F[c * NT + q + N * tbb];
+  wave_sync();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[c * NT + t] = Z[c];
+  wave_sync();
+  T W[4] = {0, 0, 0, 0};
+  if (act) {
+    const T hab = a.h[da] * a.h[db];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) W[c] += LT[2 * NT + tbb * N + q] * F[c * NT + ta + N * q];
+      W[c] *= hab;
+    }
+  }
+  wave_sync();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[c * NT + t] = W[c];
+  wave_sync();
+  // F[(2s) n^2 + node]: plane term at the end node; F[(2s+1) n^2 + node]:
+  // weight of l_i'(s) along the normal line.  Add into this lane's x-line.
   if (act) {
     const int j = t % N, l = t / N;
 #pragma unroll
@@ -330,59 +382,96 @@ __device__ __forceinline__ void face_pass(const OpArgs<N, T>& a, const T* A, T* 
       const int endp = s * (N - 1);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        const T dli = s ? tb.dl1[i] : tb.dl0[i];
         if (d == 0) {
-          vacc[i] += (i == endp ? Pv[t] : T(0)) + dli * Qv[t];
+          vacc[i] += (i == endp ? Pv[t] : T(0)) + (s ? tab.dl1[i] : tab.dl0[i]) * Qv[t];
         } else if (d == 1) {
-          const T dlj = s ? tb.dl1[j] : tb.dl0[j];
-          vacc[i] += (j == endp ? Pv[i + N * l] : T(0)) + dlj * Qv[i + N * l];
+          vacc[i] += (j == endp ? Pv[i + N * l] : T(0)) + LT[3 * NT + s * N + j] * Qv[i + N * l];
         } else {
-          const T dll = s ? tb.dl1[l] : tb.dl0[l];
-          vacc[i] += (l == endp ? Pv[i + N * j] : T(0)) + dll * Qv[i + N * j];
+          vacc[i] += (l == endp ? Pv[i + N * j] : T(0)) + LT[3 * NT + s * N + l] * Qv[i + N * j];
         }
       }
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
 // ------------------------------------------------------------------ operator
 template <int N, typename T, bool CURVED, bool FE, int MODE>
-__global__ void __launch_bounds__(Cfg<N>::THREADS) op_kernel(const OpArgs<N, T> a) {
-  using C = Cfg<N>;
-  constexpr int NT = C::NT, N3 = C::N3, E = C::E, PER = C::PER;
-  __shared__ T smem[E * PER];
-  __shared__ double red[16];
-  const int tid = threadIdx.x;
-  const int le = tid / NT, t = tid - le * NT;
-  const int64_t e0 = (int64_t)xcd_block() * E;
+__global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
+  using C = Cfg<N, CURVED, FE>;
+  constexpr int NT = C::NT, N3 = C::N3, EW = C::EW, PER = C::PER;
+  __shared__ T smem[C::WAVES * (EW * PER + C::LT)];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int le = lane / NT, t = lane - le * NT;
+  const int64_t e0 = (int64_t)xcd_block() * C::EB + (int64_t)wave * EW;  // first element of the wave
   const int64_t e = e0 + le;
-  const bool act = (le < E) && (e < a.nel);
-  T* A = smem + (le < E ? le : 0) * PER;
-  T* B = A + N3;
-  T* Cc = B + N3;
-  const auto& tb = a.tab;
+  const bool act = (le < EW) && (e < a.nel);
+  T* const W0 = smem + wave * (EW * PER + C::LT);  // this wavefront's LDS
+  T* const R = W0 + (le < EW ? le : 0) * PER;
+  T* const LT = W0 + EW * PER;
+  const auto& tab = a.tab;
+  for (int i = lane; i < C::LT; i += 64) LT[i] = a.ltab[i];
   int ec[3] = {0, 0, 0};
+  bool has[6] = {false, false, false, false, false, false};
   if (act) {
     ec[0] = (int)(e % a.Nx);
     const int64_t r = e / a.Nx;
     ec[1] = (int)(r % a.Ny);
     ec[2] = (int)(r / a.Ny);
+    has[0] = ec[0] > 0;
+    has[1] = ec[0] + 1 < a.Nx;
+    has[2] = ec[1] > 0;
+    has[3] = ec[1] + 1 < a.Ny;
+    has[4] = ec[2] > 0;
+    has[5] = ec[2] + 1 < a.Nz;
   }
-  const int64_t nloc = a.nel - e0 < E ? a.nel - e0 : E;
-  const int nload = (int)nloc * N3;
+  const int64_t left = a.nel - e0;
+  const int nload = (int)(left <= 0 ? 0 : (left < EW ? left : EW)) * N3;
+  const int ta = t % N, tbb = t / N;
 
-  // ---- gather the block's elements into LDS (coalesced)
+  // ---- neighbour traces (curved DG), before the own data occupies LDS
+  T un[6], dnn[6];
+  if constexpr (CURVED && !FE) {
+    nb_nodal<N, T, 0>(a, R, act, t, e, has);
+    nb_nodal<N, T, 1>(a, R, act, t, e, has);
+    nb_nodal<N, T, 2>(a, R, act, t, e, has);
+    wave_sync();
+    T X[18];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      X[3 * f] = X[3 * f + 1] = X[3 * f + 2] = 0;
+      if (act)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          const T sv = LT[ta * N + q], sp = LT[NT + ta * N + q];
+          const T p = R[(2 * f) * NT + q + N * tbb], qq = R[(2 * f + 1) * NT + q + N * tbb];
+          X[3 * f] += sv * p;
+          X[3 * f + 1] += sp * p;
+          X[3 * f + 2] += sv * qq;
+        }
+    }
+    wave_sync();
+    if (act)
+#pragma unroll
+      for (int c = 0; c < 18; ++c) R[c * NT + t] = X[c];
+    wave_sync();
+    nb_finish<N, T, 0>(a, R, LT, act, t, ec, has, un, dnn);
+    nb_finish<N, T, 1>(a, R, LT, act, t, ec, has, un, dnn);
+    nb_finish<N, T, 2>(a, R, LT, act, t, ec, has, un, dnn);
+    wave_sync();
+  }
+
+  // ---- own element data into LDS (coalesced per wavefront)
   if constexpr (!FE) {
     const T* src = a.u + e0 * N3;
-    for (int idx = tid; idx < nload; idx += C::THREADS) {
+    for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3;
-      smem[li * PER + (idx - li * N3)] = src[idx];
+      W0[li * PER + (idx - li * N3)] = src[idx];
     }
   } else {
     constexpr int k = N - 1;
     const int64_t Mx = (int64_t)a.Nx * k + 1, My = (int64_t)a.Ny * k + 1, Mz = (int64_t)a.Nz * k + 1;
-    for (int idx = tid; idx < nload; idx += C::THREADS) {
+    for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3, p = idx - li * N3;
       const int64_t ee = e0 + li;
       const int64_t gx = (ee % a.Nx) * k + p % N;
@@ -390,184 +479,197 @@ __global__ void __launch_bounds__(Cfg<N>::THREADS) op_kernel(const OpArgs<N, T> 
       const int64_t gy = (rr % a.Ny) * k + (p / N) % N;
       const int64_t gz = (rr / a.Ny) * k + p / NT;
       const int m = a.bcmask;
-      const bool fixed = (gx == 0 && !(m & 1)) || (gx == Mx - 1 && !(m & 2)) ||
-                         (gy == 0 && !(m & 4)) || (gy == My - 1 && !(m & 8)) ||
-                         (gz == 0 && !(m & 16)) || (gz == Mz - 1 && !(m & 32));
-      smem[li * PER + p] = fixed ? T(0) : a.u[gx + Mx * (gy + My * gz)];
+      const bool fixed = (gx == 0 && !(m & 1)) || (gx == Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
+                         (gy == My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == Mz - 1 && !(m & 32));
+      W0[li * PER + p] = fixed ? T(0) : a.u[gx + Mx * (gy + My * gz)];
     }
   }
-  __syncthreads();
+  wave_sync();
 
-  T vacc[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) vacc[i] = 0;
-  if constexpr (!FE) {
-    face_pass<N, T, CURVED, 0>(a, A, B, act, t, e, ec, vacc);
-    face_pass<N, T, CURVED, 1>(a, A, B, act, t, e, ec, vacc);
-    face_pass<N, T, CURVED, 2>(a, A, B, act, t, e, ec, vacc);
-  }
+  T* const A = R;
+  T* const B = R + N3;
+  T* const Cc = R + 2 * N3;
+  T v[N];
 
-  const int ta = t % N, tbb = t / N;
-  // ---- cell: interpolation to Gauss points, x then y then z
-  if (act) {
-    T in[N], o[N];
+  if constexpr (!CURVED) {
+    // ---- affine: faces in nodal space, cell as sum_d c_d K_d (x) M (x) M
+    T vacc[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = A[m + N * t];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += tb.S[q * N + m] * in[m];
-      o[q] = s;
+    for (int i = 0; i < N; ++i) vacc[i] = 0;
+    if constexpr (!FE) {
+      affine_faces<N, T, 0>(a, A, B, LT, act, t, e, has, vacc);
+      affine_faces<N, T, 1>(a, A, B, LT, act, t, e, has, vacc);
+      affine_faces<N, T, 2>(a, A, B, LT, act, t, e, has, vacc);
     }
-#pragma unroll
-    for (int q = 0; q < N; ++q) A[q + N * t] = o[q];
-  }
-  __syncthreads();
-  if (act) {
-    T in[N], o[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = A[ta + N * m + NT * tbb];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += tb.S[q * N + m] * in[m];
-      o[q] = s;
+    const T cx = a.h[1] * a.h[2] / a.h[0], cy = a.h[0] * a.h[2] / a.h[1], cz = a.h[0] * a.h[1] / a.h[2];
+    if (act) {  // z: p = M u, q = K u
+      T x[N], p[N], q[N];
+      read_line<N, T, 2>(A, t, x);
+      mat<N, T>(tab.M, x, p);
+      mat<N, T>(tab.K, x, q);
+      write_line<N, T, 2>(B, t, p);
+      write_line<N, T, 2>(Cc, t, q);
     }
+    wave_sync();
+    if (act) {  // y: r = M p, s = cy K p + cz M q
+      T p[N], q[N], r[N], s1[N], s2[N];
+      read_line<N, T, 1>(B, t, p);
+      read_line<N, T, 1>(Cc, t, q);
+      mat<N, T>(tab.M, p, r);
+      mat<N, T>(tab.K, p, s1);
+      mat<N, T>(tab.M, q, s2);
 #pragma unroll
-    for (int q = 0; q < N; ++q) A[ta + N * q + NT * tbb] = o[q];
-  }
-  __syncthreads();
-  T gz[N];
-  if (act) {
-    T in[N], uq[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = A[t + NT * m];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += tb.S[q * N + m] * in[m];
-      uq[q] = s;
+      for (int m = 0; m < N; ++m) s1[m] = cy * s1[m] + cz * s2[m];
+      write_line<N, T, 1>(B, t, r);
+      write_line<N, T, 1>(Cc, t, s1);
     }
+    wave_sync();
+    if (act) {  // x: v = cx K r + M s
+      T r[N], s[N], v1[N], v2[N];
+      read_line<N, T, 0>(B, t, r);
+      read_line<N, T, 0>(Cc, t, s);
+      mat<N, T>(tab.K, r, v1);
+      mat<N, T>(tab.M, s, v2);
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += tb.D[q * N + m] * uq[m];
-      gz[q] = s;
+      for (int m = 0; m < N; ++m) v[m] = cx * v1[m] + v2[m] + vacc[m];
     }
-#pragma unroll
-    for (int q = 0; q < N; ++q) A[t + NT * q] = uq[q];
-  }
-  __syncthreads();
-  // ---- collocation derivatives in x (into B) and y (into C)
-  if (act) {
-    T in[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = A[m + N * t];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += tb.D[q * N + m] * in[m];
-      B[q + N * t] = s;
+  } else {
+    T* const Dg = R + 3 * N3;
+    // ---- curved: interpolation to Gauss points, x then y then z
+    if (act) {
+      T x[N], y[N];
+      read_line<N, T, 0>(A, t, x);
+      mat<N, T>(tab.S, x, y);
+      write_line<N, T, 0>(A, t, y);
     }
-#pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = A[ta + N * m + NT * tbb];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += tb.D[q * N + m] * in[m];
-      Cc[ta + N * q + NT * tbb] = s;
+    wave_sync();
+    if (act) {
+      T x[N], y[N];
+      read_line<N, T, 1>(A, t, x);
+      mat<N, T>(tab.S, x, y);
+      write_line<N, T, 1>(A, t, y);
     }
-  }
-  __syncthreads();
-  // ---- quadrature-point operator on z-lines, start of integration in z
-  if (act) {
-    T fx[N], fy[N], fz[N];
+    wave_sync();
+    if (act) {
+      T x[N], uq[N], gz[N];
+      read_line<N, T, 2>(A, t, x);
+      mat<N, T>(tab.S, x, uq);
+      mat<N, T>(tab.D, uq, gz);
+      write_line<N, T, 2>(A, t, uq);
+      write_line<N, T, 2>(Dg, t, gz);
+    }
+    wave_sync();
+    if (act) {  // collocation derivatives in x (-> B) and y (-> Cc)
+      T x[N], y[N];
+      read_line<N, T, 0>(A, t, x);
+      mat<N, T>(tab.D, x, y);
+      write_line<N, T, 0>(B, t, y);
+      read_line<N, T, 1>(A, t, x);
+      mat<N, T>(tab.D, x, y);
+      write_line<N, T, 1>(Cc, t, y);
+    }
+    wave_sync();
+    // ---- face fluxes (DG): own traces by extrapolation
+    T vt[6], gt[6];
+    if constexpr (!FE) {
+      own_flux<N, T, 0>(a, R, act, t, e, ec, has, un, dnn, vt, gt);
+      own_flux<N, T, 1>(a, R, act, t, e, ec, has, un, dnn, vt, gt);
+      own_flux<N, T, 2>(a, R, act, t, e, ec, has, un, dnn, vt, gt);
+      wave_sync();
+    }
+    // ---- quadrature-point operator on z-lines, z-face tests
+    if (act) {
+      T vq[N], fx[N], fy[N], fz[N];
+      const T* G = a.metric + e * 6 * N3 + t;
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const T gx = B[t + NT * m], gy = Cc[t + NT * m], g3 = gz[m];
-      if constexpr (CURVED) {
-        const T* G = a.metric + e * 6 * N3 + t + NT * m;
-        const T g00 = G[0], g11 = G[N3], g22 = G[2 * N3], g01 = G[3 * N3], g02 = G[4 * N3],
-                g12 = G[5 * N3];
+      for (int m = 0; m < N; ++m) {
+        const int o = t + NT * m;
+        const T gx = B[o], gy = Cc[o], g3 = Dg[o];
+        const T* Gm = G + NT * m;
+        const T g00 = Gm[0], g11 = Gm[N3], g22 = Gm[2 * N3], g01 = Gm[3 * N3], g02 = Gm[4 * N3],
+                g12 = Gm[5 * N3];
         fx[m] = g00 * gx + g01 * gy + g02 * g3;
         fy[m] = g01 * gx + g11 * gy + g12 * g3;
         fz[m] = g02 * gx + g12 * gy + g22 * g3;
-      } else {
-        const T w = tb.w[ta] * tb.w[tbb] * tb.w[m];
-        fx[m] = w * (a.h[1] * a.h[2] / a.h[0]) * gx;
-        fy[m] = w * (a.h[0] * a.h[2] / a.h[1]) * gy;
-        fz[m] = w * (a.h[0] * a.h[1] / a.h[2]) * g3;
+        vq[m] = 0;
       }
+      if constexpr (!FE) inject<N, T, 2>(a, ec, t, vt, gt, vq, fx, fy, fz);
+      if constexpr (!FE) write_line<N, T, 2>(A, t, vq);
+      write_line<N, T, 2>(B, t, fx);
+      write_line<N, T, 2>(Cc, t, fy);
+      write_line<N, T, 2>(Dg, t, fz);
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        s1 += tb.S[q * N + i] * fx[q];
-        s2 += tb.S[q * N + i] * fy[q];
-        s3 += tb.Sp[q * N + i] * fz[q];
+    wave_sync();
+    if constexpr (!FE) {  // x-face tests along x-lines
+      if (act) {
+        T vq[N], fx[N], fy[N], fz[N];
+        read_line<N, T, 0>(A, t, vq);
+        read_line<N, T, 0>(B, t, fx);
+        read_line<N, T, 0>(Cc, t, fy);
+        read_line<N, T, 0>(Dg, t, fz);
+        inject<N, T, 0>(a, ec, t, vt, gt, vq, fx, fy, fz);
+        write_line<N, T, 0>(A, t, vq);
+        write_line<N, T, 0>(B, t, fx);
+        write_line<N, T, 0>(Cc, t, fy);
+        write_line<N, T, 0>(Dg, t, fz);
       }
-      B[t + NT * i] = s1;
-      Cc[t + NT * i] = s2;
-      A[t + NT * i] = s3;
+      wave_sync();
+    }
+    if (act) {  // y-face tests, then integration in y
+      T fx[N], fy[N], fz[N], ay[N], by[N], cy[N], w2[N];
+      read_line<N, T, 1>(B, t, fx);
+      read_line<N, T, 1>(Cc, t, fy);
+      read_line<N, T, 1>(Dg, t, fz);
+      if constexpr (!FE) {
+        T vq[N];
+        read_line<N, T, 1>(A, t, vq);
+        inject<N, T, 1>(a, ec, t, vt, gt, vq, fx, fy, fz);
+        matT<N, T>(tab.S, vq, cy);
+      }
+      matT<N, T>(tab.S, fx, ay);
+      matT<N, T>(tab.S, fz, by);
+      matT<N, T>(tab.Sp, fy, w2);
+#pragma unroll
+      for (int m = 0; m < N; ++m) cy[m] = FE ? w2[m] : cy[m] + w2[m];
+      write_line<N, T, 1>(A, t, ay);
+      write_line<N, T, 1>(B, t, by);
+      write_line<N, T, 1>(Cc, t, cy);
+    }
+    wave_sync();
+    if (act) {  // integration in z
+      T ay[N], by[N], cy[N], az[N], bz[N], w2[N];
+      read_line<N, T, 2>(A, t, ay);
+      read_line<N, T, 2>(B, t, by);
+      read_line<N, T, 2>(Cc, t, cy);
+      matT<N, T>(tab.S, ay, az);
+      matT<N, T>(tab.Sp, by, bz);
+      matT<N, T>(tab.S, cy, w2);
+#pragma unroll
+      for (int m = 0; m < N; ++m) bz[m] += w2[m];
+      write_line<N, T, 2>(A, t, az);
+      write_line<N, T, 2>(B, t, bz);
+    }
+    wave_sync();
+    if (act) {  // integration in x
+      T az[N], bz[N], w2[N];
+      read_line<N, T, 0>(A, t, az);
+      read_line<N, T, 0>(B, t, bz);
+      matT<N, T>(tab.Sp, az, v);
+      matT<N, T>(tab.S, bz, w2);
+#pragma unroll
+      for (int m = 0; m < N; ++m) v[m] += w2[m];
     }
   }
-  __syncthreads();
-  // ---- integration in y
-  if (act) {
-    T cz[N], az[N], bz[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const int o = ta + N * m + NT * tbb;
-      cz[m] = A[o];
-      az[m] = B[o];
-      bz[m] = Cc[o];
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s1 = 0, s2 = 0;
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        s1 += tb.S[q * N + i] * cz[q] + tb.Sp[q * N + i] * bz[q];
-        s2 += tb.S[q * N + i] * az[q];
-      }
-      const int o = ta + N * i + NT * tbb;
-      A[o] = s1;
-      B[o] = s2;
-    }
-  }
-  __syncthreads();
-  // ---- integration in x, add the face terms, stage for the store
-  if (act) {
-    T dy[N], ey[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      dy[m] = A[m + N * t];
-      ey[m] = B[m + N * t];
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s = vacc[i];
-#pragma unroll
-      for (int q = 0; q < N; ++q) s += tb.S[q * N + i] * dy[q] + tb.Sp[q * N + i] * ey[q];
-      A[i + N * t] = s;
-    }
-  }
-  __syncthreads();
+  wave_sync();
+  if (act) write_line<N, T, 0>(A, t, v);
+  wave_sync();
 
-  // ---- coalesced epilogue
+  // ---- coalesced epilogue over the wavefront's elements
   const int64_t gbase = e0 * N3;
   double acc = 0.0;
-  for (int idx = tid; idx < nload; idx += C::THREADS) {
+  for (int idx = lane; idx < nload; idx += 64) {
     const int li = idx / N3;
-    const T val = smem[li * PER + (idx - li * N3)];
+    const T val = W0[li * PER + (idx - li * N3)];
     const int64_t g = gbase + idx;
     if constexpr (FE || MODE == OP_APPLY) {
       a.out[g] = val;
@@ -582,8 +684,8 @@ __global__ void __launch_bounds__(Cfg<N>::THREADS) op_kernel(const OpArgs<N, T> 
     }
   }
   if constexpr (!FE && MODE == OP_DOT) {
-    const double s = block_sum(acc, red);
-    if (tid == 0) a.partials[blockIdx.x] = s;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) a.partials[(int64_t)blockIdx.x * C::WAVES + wave] = acc;
   }
 }
 
@@ -601,6 +703,7 @@ static OpArgs<N, T> make_args(const hmg_level* L) {
   a.metric = (const T*)L->metric();
   for (int d = 0; d < 3; ++d) a.face[d] = (const T*)L->face(d);
   a.tau = (const T*)L->tau();
+  a.ltab = (const T*)L->ltab();
   a.nel = L->n_el;
   a.Nx = L->mesh.N[0];
   a.Ny = L->mesh.N[1];
@@ -614,7 +717,7 @@ static OpArgs<N, T> make_args(const hmg_level* L) {
 template <int N, typename T, bool CURVED, bool FE>
 static int run_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                   const void* xold, double sigma, double theta, int* nparts, hipStream_t s) {
-  using C = Cfg<N>;
+  using C = Cfg<N, CURVED, FE>;
   OpArgs<N, T> a = make_args<N, T>(L);
   a.u = (const T*)u;
   a.out = (T*)(FE ? L->scratch() : out);
@@ -622,10 +725,11 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   a.xold = (const T*)xold;
   a.sigma = (T)sigma;
   a.theta = (T)theta;
-  const int64_t nb = (L->n_el + C::E - 1) / C::E;
-  if (nb > INT32_MAX) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
-  if (nparts) *nparts = (int)nb;
-  dim3 grid((unsigned)nb), block(C::THREADS);
+  const int64_t nb = (L->n_el + C::EB - 1) / C::EB;
+  if (nb > INT32_MAX / C::WAVES) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
+  // one partial per wavefront; the level's partials buffer holds n_el + 64
+  if (nparts) *nparts = (int)nb * C::WAVES;
+  dim3 grid((unsigned)nb), block(64 * C::WAVES);
   if (FE) {
     hipLaunchKernelGGL((op_kernel<N, T, CURVED, true, OP_APPLY>), grid, block, 0, s, a);
   } else {

@@ -130,10 +130,20 @@ Basis1D make_basis(int k) {
       for (int q = 0; q < n; ++q) s += b.gw[q] * b.S[q * n + i] * b.S[q * n + j];
       b.M[i * n + j] = s;
     }
-  std::vector<double> Dend;
+  b.K.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int q = 0; q < n; ++q) s += b.gw[q] * b.Sp[q * n + i] * b.Sp[q * n + j];
+      b.K[i * n + j] = s;
+    }
+  std::vector<double> Dend, Gend;
   lagrange(b.gll, {0.0, 1.0}, nullptr, &Dend);
   b.dl0.assign(Dend.begin(), Dend.begin() + n);
   b.dl1.assign(Dend.begin() + n, Dend.end());
+  lagrange(b.gz, {0.0, 1.0}, &Gend, nullptr);
+  b.lg0.assign(Gend.begin(), Gend.begin() + n);
+  b.lg1.assign(Gend.begin() + n, Gend.end());
   return b;
 }
 
