@@ -267,7 +267,7 @@ static int level_init(const Mesh& m, int space, int prec, hmg_level** out) {
   L->off_scratch = take(space == HMG_FE ? (size_t)L->n_dg * es : 0);
   L->off_part = take((size_t)std::max<int64_t>(kPartials, L->n_el + 64) * 8);
   L->off_scal = take(16 * 8);
-  L->off_ltab = take((size_t)(3 * L->n * L->n + 2 * L->n) * es);
+  L->off_tabs = take((size_t)TabOff(L->n).size() * es);
   L->ws_bytes = off;
   *out = L;
   return HMG_OK;
@@ -317,17 +317,12 @@ extern "C" int hmg_level_bind(hmg_level* L, void* ws, size_t bytes, hipStream_t 
     TRY(upload<float>(g.tau, L->tau(), s, keep));
   }
   {
-    const Basis1D& b = L->basis;
-    std::vector<double> lt;
-    lt.insert(lt.end(), b.S.begin(), b.S.end());
-    lt.insert(lt.end(), b.Sp.begin(), b.Sp.end());
-    lt.insert(lt.end(), b.M.begin(), b.M.end());
-    lt.insert(lt.end(), b.dl0.begin(), b.dl0.end());
-    lt.insert(lt.end(), b.dl1.begin(), b.dl1.end());
-    if (L->prec == HMG_F64)
-      TRY(upload<double>(lt, L->ltab(), s, keep));
-    else
-      TRY(upload<float>(lt, L->ltab(), s, keep));
+    const std::vector<double> tabs = op_tables(L->basis);
+    if (L->prec == HMG_F64) {
+      TRY(upload<double>(tabs, L->tabs(), s, keep));
+    } else {
+      TRY(upload<float>(tabs, L->tabs(), s, keep));
+    }
   }
   // diagonal (computed during create) and its inverse
   const std::vector<double>& dg = L->diag_h;

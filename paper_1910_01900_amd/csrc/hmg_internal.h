@@ -45,30 +45,34 @@ void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
 void lagrange(const std::vector<double>& nodes, const std::vector<double>& x,
               std::vector<double>* V, std::vector<double>* Dv);
 
-// Kernel-argument copy of the tables for a compile-time n.
-template <int N, typename T>
-struct OpTab {
-  T S[N * N], Sp[N * N], D[N * N], M[N * N], K[N * N], dl0[N], dl1[N], lg0[N], lg1[N], w[N];
+// Operator tables in device memory (level precision), built by op_tables():
+//   [S, Sp, M]            n x n row-major, read per lane (face sweeps)
+//   [l'(0), l'(1)]        GLL basis derivatives at the element ends
+//   [lg(0), lg(1)]        Gauss-point Lagrange basis at the element ends
+//   even-odd packed S, S^T, Sp^T, D, M, K (eo_count(n) values each)
+// Even-odd packing of an n x n matrix A with A[n-1-q][n-1-i] = sig A[q][i]
+// (h = n/2): E[q][i] = (A[q][i] + A[q][n-1-i])/2, O[q][i] = (A[q][i] -
+// A[q][n-1-i])/2 for q, i < h; for odd n also A[q][h] (q < h), the middle
+// row A[h][i] (i < h) and A[h][h].  Then with x_e = x_i + x_{n-1-i},
+// x_o = x_i - x_{n-1-i}: y_q = E x_e + O x_o (+ A[q][h] x_h) and
+// y_{n-1-q} = sig (E x_e - O x_o (+ A[q][h] x_h)).
+constexpr int eo_count(int n) { return 2 * (n / 2) * (n / 2) + ((n & 1) ? 2 * (n / 2) + 1 : 0); }
+struct TabOff {
+  int n, nt, c;
+  constexpr TabOff(int n_) : n(n_), nt(n_ * n_), c(eo_count(n_)) {}
+  constexpr int S() const { return 0; }
+  constexpr int Sp() const { return nt; }
+  constexpr int M() const { return 2 * nt; }
+  constexpr int dl0() const { return 3 * nt; }
+  constexpr int dl1() const { return 3 * nt + n; }
+  constexpr int lane_size() const { return 3 * nt + 2 * n; }  // part read per lane
+  constexpr int lg0() const { return 3 * nt + 2 * n; }
+  constexpr int lg1() const { return 3 * nt + 3 * n; }
+  constexpr int eo(int j) const { return 3 * nt + 4 * n + j * c; }  // 0 S, 1 S^T, 2 Sp^T, 3 D, 4 M, 5 K
+  constexpr int size() const { return eo(6); }
 };
-template <int N, typename T>
-OpTab<N, T> make_tab(const Basis1D& b) {
-  OpTab<N, T> t;
-  for (int i = 0; i < N * N; ++i) {
-    t.S[i] = (T)b.S[i];
-    t.Sp[i] = (T)b.Sp[i];
-    t.D[i] = (T)b.D[i];
-    t.M[i] = (T)b.M[i];
-    t.K[i] = (T)b.K[i];
-  }
-  for (int i = 0; i < N; ++i) {
-    t.dl0[i] = (T)b.dl0[i];
-    t.dl1[i] = (T)b.dl1[i];
-    t.lg0[i] = (T)b.lg0[i];
-    t.lg1[i] = (T)b.lg1[i];
-    t.w[i] = (T)b.gw[i];
-  }
-  return t;
-}
+enum EoTab { EO_S = 0, EO_ST = 1, EO_SPT = 2, EO_D = 3, EO_M = 4, EO_K = 5 };
+std::vector<double> op_tables(const Basis1D& b);
 
 // ---------------------------------------------------------------- mesh / geometry
 struct Mesh {
@@ -125,7 +129,7 @@ struct hmg_level {
   // workspace layout (byte offsets) and bound pointers
   size_t ws_bytes = 0;
   size_t off_metric = 0, off_face[3] = {0, 0, 0}, off_tau = 0, off_diag = 0, off_dinv = 0, off_tmp = 0,
-         off_scratch = 0, off_part = 0, off_scal = 0, off_ltab = 0;
+         off_scratch = 0, off_part = 0, off_scal = 0, off_tabs = 0;
   char* ws = nullptr;
   bool bound = false;
   size_t elem_size() const { return prec == HMG_F64 ? 8 : 4; }
@@ -138,8 +142,7 @@ struct hmg_level {
   void* scratch() const { return ws + off_scratch; }  // DG-layout buffer (FE levels)
   double* partials() const { return (double*)(ws + off_part); }
   double* scal() const { return (double*)(ws + off_scal); }
-  // 1-D tables the operator kernel indexes per lane: S, Sp, M (n x n), l'(0), l'(1)
-  void* ltab() const { return ws + off_ltab; }
+  void* tabs() const { return ws + off_tabs; }  // op_tables(basis), level precision
   size_t vec_bytes() const { return (size_t)n_dofs * elem_size(); }
 };
 

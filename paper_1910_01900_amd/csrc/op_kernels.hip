@@ -9,8 +9,12 @@
 // others).  Lane t of an element owns one line of n points along the
 // direction of the current phase (x-lines: t = j + n*l, y-lines:
 // t = i + n*l, z-lines: t = i + n*j), so every 1-D contraction is a
-// register-only loop with the n x n tables in scalar registers; LDS only
-// changes the direction.
+// register-only loop; LDS only changes the direction.
+//
+// 1-D contractions use the even-odd decomposition of the centro-symmetric
+// (S, M, K) and skew (D, Sp) tables (Sec. 4 sum factorization), with the
+// packed coefficients in scalar registers, loaded per phase from a
+// device-memory table so that only one phase's coefficients are live.
 //
 // Curvilinear cells (Sec. 4): interpolation to the Gauss points (3 sweeps
 // with S), collocation gradient (3 sweeps with D), the stored metric
@@ -40,14 +44,18 @@ struct Cfg {
   // LDS values per element: curved uses 4 arrays (value/flux x, y, z) and,
   // for DG, 18 n^2 neighbour face values; affine uses 3 arrays and 4 n^2
   // face values.
-  static constexpr int PER = CURVED ? (FE ? 4 * N3 : (4 * N3 > 18 * NT ? 4 * N3 : 18 * NT))
-                                    : (FE ? 3 * N3 : (3 * N3 > N3 + 4 * NT ? 3 * N3 : N3 + 4 * NT));
-  // per-wavefront copy of the tables indexed by lane: S, Sp, M, l'(0), l'(1)
-  static constexpr int LT = 3 * NT + 2 * N;
-  static constexpr int LT_S = 0, LT_SP = NT, LT_M = 2 * NT, LT_DL0 = 3 * NT, LT_DL1 = 3 * NT + N;
+  // Padded to PER = 9 (mod 16) values so that the lines of the elements
+  // sharing a wavefront fall on different LDS banks.
+  static constexpr int PER0 = CURVED ? (FE ? 4 * N3 : (4 * N3 > 18 * NT ? 4 * N3 : 18 * NT))
+                                     : (FE ? 3 * N3 : (3 * N3 > N3 + 4 * NT ? 3 * N3 : N3 + 4 * NT));
+  static constexpr int PER = PER0 + ((9 - PER0 % 16) + 16) % 16;
+  static constexpr int LT = TabOff(N).lane_size();
+  // minimum waves per SIMD the register allocation must allow (n >= 7: LDS
+  // already limits residency to two)
+  static constexpr int WPE = N >= 7 ? 2 : 3;  // per-wavefront copy of S, Sp, M, l'(0), l'(1)
 };
 
-template <int N, typename T>
+template <typename T>
 struct OpArgs {
   const T* u;
   T* out;
@@ -59,19 +67,63 @@ struct OpArgs {
   const T* metric;
   const T* face[3];
   const T* tau;
-  const T* ltab;  // S, Sp, M, l'(0), l'(1) in device memory (indexed per lane)
+  const T* tabs;  // op_tables() in device memory
   int64_t nel;
   int Nx, Ny, Nz, bcmask;
+  int rowchunks, tile_y;  // workgroup order: chunks per x-row (0: linear), y-tile height
   T h[3];
-  OpTab<N, T> tab;
 };
 
+// ------------------------------------------------------------------ helpers
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+// A copy of p the compiler cannot trace back: loads through it are issued
+// where it is made (scalar loads, uniform address), so table coefficients
+// live in scalar registers for one phase only.
+template <typename T>
+__device__ __forceinline__ cptr<T> fresh(const T* p) {
+  cptr<T> c = (cptr<T>)(uintptr_t)p;
+  asm volatile("" : "+s"(c)::"memory");
+  return c;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of element batches so neighbouring elements share an L2.
+// contiguous range of logical workgroups so that neighbouring elements are
+// processed on the same XCD (one L2).
 __device__ __forceinline__ int xcd_block() {
   int nb = gridDim.x, x = blockIdx.x & 7, y = blockIdx.x >> 3;
   int per = nb >> 3, rem = nb & 7;
   return x * per + min(x, rem) + y;
+}
+
+// Chunk of EB consecutive elements processed by logical workgroup b.  With
+// whole chunks per x-row, rows are visited in y-tiles of tile_y rows, z
+// before y inside a tile: the x, y and z neighbours of an element are then
+// processed close in time (a few dozen workgroups apart) and the shared
+// face geometry and neighbour values are still in L2.
+template <typename T>
+__device__ __forceinline__ int64_t block_chunk(const OpArgs<T>& a, int b) {
+  const int R = a.rowchunks;
+  if (R == 0) return b;
+  const int TY = a.tile_y;
+  const int64_t full = (int64_t)R * a.Nz * TY;
+  const int ty = (int)(b / full);
+  const int th = min(TY, a.Ny - ty * TY);
+  const int64_t bp = b - ty * full;
+  const int cx = (int)(bp % R);
+  const int64_t r = bp / R;
+  const int yi = (int)(r % th);
+  const int z = (int)(r / th);
+  return cx + (int64_t)R * ((ty * TY + yi) + (int64_t)a.Ny * z);
+}
+
+// Pin a value in registers at this point: computations that feed stores
+// after a wave_sync() are otherwise sunk past it, which keeps all of their
+// LDS inputs live across the fence.
+template <typename T>
+__device__ __forceinline__ void pin(T& x) {
+  asm volatile("" : "+v"(x));
 }
 
 // Order LDS traffic between the lanes of one wavefront.
@@ -100,26 +152,37 @@ __device__ __forceinline__ void write_line(T* A, int t, const T (&x)[N]) {
 #pragma unroll
   for (int m = 0; m < N; ++m) A[lidx<N, d>(t, m)] = x[m];
 }
-// y[q] = sum_m M[q][m] x[m]  (M row-major n x n)
-template <int N, typename T>
-__device__ __forceinline__ void mat(const T* M, const T (&x)[N], T (&y)[N]) {
+
+// y = A x with A given by its even-odd packing c (see TabOff); SIG = +1 for
+// centro-symmetric, -1 for skew tables.
+template <int N, typename T, int SIG>
+__device__ __forceinline__ void eo_apply(cptr<T> c, const T (&x)[N], T (&y)[N]) {
+  constexpr int h = N / 2;
+  constexpr bool odd = N & 1;
+  T xe[h > 0 ? h : 1], xo[h > 0 ? h : 1];
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
-    T s = 0;
-#pragma unroll
-    for (int m = 0; m < N; ++m) s += M[q * N + m] * x[m];
-    y[q] = s;
+  for (int i = 0; i < h; ++i) {
+    xe[i] = x[i] + x[N - 1 - i];
+    xo[i] = x[i] - x[N - 1 - i];
   }
-}
-// y[i] = sum_q M[q][i] x[q]  (transpose)
-template <int N, typename T>
-__device__ __forceinline__ void matT(const T* M, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    T s = 0;
+  for (int q = 0; q < h; ++q) {
+    T ye = c[q * h] * xe[0];
+    T yo = c[h * h + q * h] * xo[0];
 #pragma unroll
-    for (int q = 0; q < N; ++q) s += M[q * N + i] * x[q];
-    y[i] = s;
+    for (int i = 1; i < h; ++i) {
+      ye += c[q * h + i] * xe[i];
+      yo += c[h * h + q * h + i] * xo[i];
+    }
+    if (odd) ye += c[2 * h * h + q] * x[h];
+    y[q] = ye + yo;
+    y[N - 1 - q] = SIG > 0 ? ye - yo : yo - ye;
+  }
+  if (odd) {
+    T ym = SIG > 0 ? c[2 * h * h + 2 * h] * x[h] : T(0);
+#pragma unroll
+    for (int i = 0; i < h; ++i) ym += c[2 * h * h + h + i] * (SIG > 0 ? xe[i] : xo[i]);
+    y[h] = ym;
   }
 }
 
@@ -130,63 +193,87 @@ __device__ __forceinline__ int64_t dstride(int Nx, int Ny) {
 
 // Penalty of a face: max of the two element values (Sec. 2), the own value
 // on the boundary.
-template <int N, typename T>
-__device__ __forceinline__ T tau_face(const OpArgs<N, T>& a, int64_t e, bool has, int64_t en) {
-  const T te = a.tau[e];
-  if (!has) return te;
-  const T tn = a.tau[en];
-  return te > tn ? te : tn;
+template <typename T>
+__device__ __forceinline__ T tau_face(T te, T tn, bool has) {
+  return has ? (te > tn ? te : tn) : te;
 }
 
-// Geometry of face (d, s) of the element at ec: the 7 x n^2 block
-// (n^T J_L^{-T}, n^T J_R^{-T}, surface weight) of that face, n pointing
-// from the lower (L) to the upper (R) element.
+// Per element: a valid element index (lanes without an element use a
+// clamped one, so that every address stays inside the arrays and loads need
+// no branch), neighbour flags (bit f for face f = 2d + s) and, per direction,
+// the index of the lower face in that direction's face array.
+struct ElemInfo {
+  int64_t e;
+  int hb;
+  int fidx[3];
+};
+
+template <typename T>
+__device__ __forceinline__ ElemInfo elem_info(const OpArgs<T>& a, int64_t e) {
+  ElemInfo I;
+  I.e = e < a.nel ? e : a.nel - 1;
+  const int ex = (int)(I.e % a.Nx);
+  const int64_t r = I.e / a.Nx;
+  const int ey = (int)(r % a.Ny), ez = (int)(r / a.Ny);
+  I.hb = (ex > 0) | ((ex + 1 < a.Nx) << 1) | ((ey > 0) << 2) | ((ey + 1 < a.Ny) << 3) | ((ez > 0) << 4) |
+         ((ez + 1 < a.Nz) << 5);
+  // faces of direction d are numbered (pos_d) + (N_d + 1) (pos_a + N_a pos_b)
+  I.fidx[0] = ex + (a.Nx + 1) * (ey + a.Ny * ez);
+  I.fidx[1] = ey + (a.Ny + 1) * (ex + a.Nx * ez);
+  I.fidx[2] = ez + (a.Nz + 1) * (ex + a.Nx * ey);
+  return I;
+}
+
+__device__ __forceinline__ bool has_nb(const ElemInfo& I, int f) { return (I.hb >> f) & 1; }
+
+// Neighbour across face (d, s), or the element itself on the boundary (its
+// data is then loaded but not used).
+template <int d, typename T>
+__device__ __forceinline__ int64_t nb_elem(const OpArgs<T>& a, const ElemInfo& I, int s) {
+  return has_nb(I, 2 * d + s) ? I.e + (s ? dstride<d>(a.Nx, a.Ny) : -dstride<d>(a.Nx, a.Ny)) : I.e;
+}
+
+// Geometry block of face (d, s) at face point t: 7 x n^2 values
+// (n^T J_L^{-T}, n^T J_R^{-T}, surface weight), n pointing from the lower (L)
+// to the upper (R) element.
 template <int N, typename T, int d>
-__device__ __forceinline__ const T* face_ptr(const OpArgs<N, T>& a, const int ec[3], int s) {
+__device__ __forceinline__ const T* face_ptr(const OpArgs<T>& a, const ElemInfo& I, int s, int t) {
+  return a.face[d] + (int64_t)(I.fidx[d] + s) * (7 * N * N) + t;
+}
+
+// n^T J^{-T} of face (d, s) at face point t with n the own outward normal,
+// of the own side (OWN) or of the neighbour side.
+template <int N, typename T, int d, bool OWN>
+__device__ __forceinline__ void face_metric(const OpArgs<T>& a, const ElemInfo& I, int s, int t, T (&c)[3]) {
   constexpr int NT = N * N;
-  constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
-  const int Nd = d == 0 ? a.Nx : (d == 1 ? a.Ny : a.Nz);
-  const int Na = da == 0 ? a.Nx : a.Ny;
-  const int64_t f = (ec[d] + s) + (int64_t)(Nd + 1) * (ec[da] + (int64_t)Na * ec[db]);
-  return a.face[d] + f * 7 * NT;
+  const T* g = face_ptr<N, T, d>(a, I, s, t);
+  const int off = (OWN == (s == 1)) ? 0 : 3;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) c[r] = s ? g[(off + r) * NT] : -g[(off + r) * NT];
 }
 
 // ------------------------------------------------------------------ curved faces
-// Neighbour nodal face data of the two faces of direction d: the end-node
-// value P and the normal derivative Q of the neighbour's polynomial on the
-// shared face.  F: LDS scratch, 2 values per face.
+// Neighbour lines of the two faces of direction d (global memory).
 template <int N, typename T, int d>
-__device__ __forceinline__ void nb_nodal(const OpArgs<N, T>& a, T* F, bool act, int t, int64_t e,
-                                         const bool has[6]) {
-  constexpr int NT = N * N, N3 = N * N * N;
-  const int64_t stride = dstride<d>(a.Nx, a.Ny);
+__device__ __forceinline__ void load_nb_lines(const OpArgs<T>& a, const ElemInfo& I, int t, T (&l0)[N],
+                                              T (&l1)[N]) {
+  constexpr int N3 = N * N * N;
+  const T* u0 = a.u + nb_elem<d>(a, I, 0) * N3;
+  const T* u1 = a.u + nb_elem<d>(a, I, 1) * N3;
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int f = 2 * d + s;
-    T P = 0, Q = 0;
-    if (act && has[f]) {
-      const T* un = a.u + (e + (s ? stride : -stride)) * N3;
-      T nl[N];
-#pragma unroll
-      for (int m = 0; m < N; ++m) nl[m] = un[lidx<N, d>(t, m)];
-      P = s ? nl[0] : nl[N - 1];
-#pragma unroll
-      for (int m = 0; m < N; ++m) Q += (s ? a.tab.dl0[m] : a.tab.dl1[m]) * nl[m];
-    }
-    if (act) {
-      F[(2 * f) * NT + t] = P;
-      F[(2 * f + 1) * NT + t] = Q;
-    }
+  for (int m = 0; m < N; ++m) {
+    l0[m] = u0[lidx<N, d>(t, m)];
+    l1[m] = u1[lidx<N, d>(t, m)];
   }
 }
 
 // Second face sweep (along the b direction) of the neighbour data and the
 // normal derivative against the own outward normal.  F holds, per face, the
-// a-sweep results (value, a-derivative, normal derivative).
+// a-sweep results (value, a-derivative, normal derivative); cn is the
+// neighbour-side metric of the faces.
 template <int N, typename T, int d>
-__device__ __forceinline__ void nb_finish(const OpArgs<N, T>& a, const T* F, const T* LT, bool act,
-                                          int t, const int ec[3], const bool has[6], T (&un)[6],
-                                          T (&dnn)[6]) {
+__device__ __forceinline__ void nb_finish(const T* F, const T* LT, int t, const ElemInfo& I,
+                                          const T (&cn)[6][3], T (&un)[6], T (&dnn)[6]) {
   constexpr int NT = N * N;
   constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
   const int ta = t % N, tb = t / N;
@@ -195,9 +282,6 @@ __device__ __forceinline__ void nb_finish(const OpArgs<N, T>& a, const T* F, con
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int f = 2 * d + s;
-    un[f] = 0;
-    dnn[f] = 0;
-    if (!act || !has[f]) continue;
     T u = 0, ga = 0, gb = 0, gd = 0;
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -209,12 +293,9 @@ __device__ __forceinline__ void nb_finish(const OpArgs<N, T>& a, const T* F, con
       gb += sp * x1;
       gd += sv * x3;
     }
-    const T* g = face_ptr<N, T, d>(a, ec, s);
-    T cn[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) cn[r] = s ? g[(3 + r) * NT + t] : -g[r * NT + t];
-    un[f] = u;
-    dnn[f] = cn[d] * gd + cn[da] * ga + cn[db] * gb;
+    const bool hf = has_nb(I, f);
+    un[f] = hf ? u : T(0);
+    dnn[f] = hf ? cn[f][d] * gd + cn[f][da] * ga + cn[f][db] * gb : T(0);
   }
 }
 
@@ -223,76 +304,69 @@ __device__ __forceinline__ void nb_finish(const OpArgs<N, T>& a, const T* F, con
 // the face test coefficients: vt multiplies the test value, gt the test's
 // normal derivative (Sec. 2, SIPG flux with the mirror principle).
 template <int N, typename T, int d>
-__device__ __forceinline__ void own_flux(const OpArgs<N, T>& a, const T* R, bool act, int t, int64_t e,
-                                         const int ec[3], const bool has[6], const T (&un)[6],
-                                         const T (&dnn)[6], T (&vt)[6], T (&gt)[6]) {
+__device__ __forceinline__ void own_flux(const OpArgs<T>& a, const T* R, int t, const ElemInfo& I,
+                                         const T (&un)[6], const T (&dnn)[6], T (&vt)[6], T (&gt)[6]) {
   constexpr int N3 = N * N * N, NT = N * N;
-  const auto& tab = a.tab;
-  const int64_t stride = dstride<d>(a.Nx, a.Ny);
+  constexpr TabOff O(N);
+  // global loads first: own-side metric, surface weights, penalties
+  T co[2][3], dA[2];
+  face_metric<N, T, d, true>(a, I, 0, t, co[0]);
+  face_metric<N, T, d, true>(a, I, 1, t, co[1]);
+  dA[0] = face_ptr<N, T, d>(a, I, 0, t)[6 * NT];
+  dA[1] = face_ptr<N, T, d>(a, I, 1, t)[6 * NT];
+  const T te = a.tau[I.e];
+  const T tn[2] = {a.tau[nb_elem<d>(a, I, 0)], a.tau[nb_elem<d>(a, I, 1)]};
   T uq[N], g0[N], g1[N], g2[N];
-  if (act) {
-    read_line<N, T, d>(R, t, uq);
-    read_line<N, T, d>(R + N3, t, g0);
-    read_line<N, T, d>(R + 2 * N3, t, g1);
-    read_line<N, T, d>(R + 3 * N3, t, g2);
-  }
+  read_line<N, T, d>(R, t, uq);
+  read_line<N, T, d>(R + N3, t, g0);
+  read_line<N, T, d>(R + 2 * N3, t, g1);
+  read_line<N, T, d>(R + 3 * N3, t, g2);
+  const cptr<T> c = fresh(a.tabs);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int f = 2 * d + s;
-    vt[f] = 0;
-    gt[f] = 0;
-    if (!act) continue;
-    if (!has[f] && ((a.bcmask >> f) & 1)) continue;  // Neumann: no face term
     T uo = 0, h0 = 0, h1 = 0, h2 = 0;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      const T l = s ? tab.lg1[m] : tab.lg0[m];
+      const T l = c[(s ? O.lg1() : O.lg0()) + m];
       uo += l * uq[m];
       h0 += l * g0[m];
       h1 += l * g1[m];
       h2 += l * g2[m];
     }
-    const T* g = face_ptr<N, T, d>(a, ec, s);
-    T co[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) co[r] = s ? g[r * NT + t] : -g[(3 + r) * NT + t];
-    const T dA = g[6 * NT + t];
-    const T dno = co[0] * h0 + co[1] * h1 + co[2] * h2;
-    const T tauF = tau_face(a, e, has[f], e + (s ? stride : -stride));
-    T jump, avg;
-    if (has[f]) {
-      jump = uo - un[f];
-      avg = T(0.5) * (dno + dnn[f]);
-    } else {  // Dirichlet mirror: u+ = -u-, grad u+ = grad u-
-      jump = T(2) * uo;
-      avg = dno;
-    }
-    vt[f] = (tauF * jump - avg) * dA;
-    gt[f] = T(-0.5) * jump * dA;
+    const bool hf = has_nb(I, f);
+    const bool neu = !hf && ((a.bcmask >> f) & 1);  // Neumann: no face term
+    const T dno = co[s][0] * h0 + co[s][1] * h1 + co[s][2] * h2;
+    // interior: [u] = u- - u+, {du/dn}; Dirichlet mirror: u+ = -u-, grad u+ = grad u-
+    const T jump = hf ? uo - un[f] : T(2) * uo;
+    const T avg = hf ? T(0.5) * (dno + dnn[f]) : dno;
+    const T w = neu ? T(0) : dA[s];
+    vt[f] = (tau_face(te, tn[s], hf) * jump - avg) * w;
+    gt[f] = T(-0.5) * jump * w;
   }
 }
 
 // Add the face tests of direction d to the d-lines of the integration
 // arrays (vq: test value, fx/fy/fz: test reference gradient).
 template <int N, typename T, int d>
-__device__ __forceinline__ void inject(const OpArgs<N, T>& a, const int ec[3], int t, const T (&vt)[6],
+__device__ __forceinline__ void inject(const OpArgs<T>& a, const ElemInfo& I, int t, const T (&vt)[6],
                                        const T (&gt)[6], T (&vq)[N], T (&fx)[N], T (&fy)[N], T (&fz)[N]) {
-  constexpr int NT = N * N;
-  const auto& tab = a.tab;
+  constexpr TabOff O(N);
+  T cd[2][3];
+  face_metric<N, T, d, true>(a, I, 0, t, cd[0]);
+  face_metric<N, T, d, true>(a, I, 1, t, cd[1]);
+  const cptr<T> c = fresh(a.tabs);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int f = 2 * d + s;
-    const T* g = face_ptr<N, T, d>(a, ec, s);
-    T c[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) c[r] = (s ? g[r * NT + t] : -g[(3 + r) * NT + t]) * gt[f];
+    const T c0 = cd[s][0] * gt[f], c1 = cd[s][1] * gt[f], c2 = cd[s][2] * gt[f];
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      const T l = s ? tab.lg1[m] : tab.lg0[m];
+      const T l = c[(s ? O.lg1() : O.lg0()) + m];
       vq[m] += l * vt[f];
-      fx[m] += l * c[0];
-      fy[m] += l * c[1];
-      fz[m] += l * c[2];
+      fx[m] += l * c0;
+      fy[m] += l * c1;
+      fz[m] += l * c2;
     }
   }
 }
@@ -302,78 +376,78 @@ __device__ __forceinline__ void inject(const OpArgs<N, T>& a, const int ec[3], i
 // With n^T J^{-T} = +-e_d / h_d on both sides and surface weight
 // h_a h_b w_a w_b, the flux reduces to the plane term tau [u] - c {du/dn}
 // and the normal-derivative term -c/2 [u], each taken through the face mass
-// matrix M (x) M.  A: own nodal u; F: LDS scratch of 4 n^2.
+// matrix M (x) M.  A: own nodal u; F: LDS scratch of 4 n^2; LT: lane tables.
 template <int N, typename T, int d>
-__device__ __forceinline__ void affine_faces(const OpArgs<N, T>& a, const T* A, T* F, const T* LT,
-                                             bool act, int t, int64_t e, const bool has[6],
-                                             T (&vacc)[N]) {
-  constexpr int NT = N * N, N3 = N * N * N;
+__device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* A, T* F, const T* LT, bool act,
+                                             int t, const ElemInfo& I, T (&vacc)[N]) {
+  constexpr int NT = N * N;
   constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
-  const auto& tab = a.tab;
+  constexpr TabOff O(N);
   const int ta = t % N, tbb = t / N;
-  const int64_t stride = dstride<d>(a.Nx, a.Ny);
   if (act) {
+    // global loads first: neighbour lines and penalties
+    T nl[2][N];
+    load_nb_lines<N, T, d>(a, I, t, nl[0], nl[1]);
+    const T te = a.tau[I.e];
+    const T tn[2] = {a.tau[nb_elem<d>(a, I, 0)], a.tau[nb_elem<d>(a, I, 1)]};
     T line[N];
     read_line<N, T, d>(A, t, line);
+    const cptr<T> c = fresh(a.tabs);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int f = 2 * d + s;
-      const bool neu = !has[f] && ((a.bcmask >> f) & 1);
+      const bool hf = has_nb(I, f);
+      const bool neu = !hf && ((a.bcmask >> f) & 1);
       const T Po = line[s * (N - 1)];
-      T Qo = 0;
+      T Qo = 0, Qn = 0;
 #pragma unroll
-      for (int m = 0; m < N; ++m) Qo += (s ? tab.dl1[m] : tab.dl0[m]) * line[m];
-      T Pj, Qs;
-      if (has[f]) {
-        const T* un = a.u + (e + (s ? stride : -stride)) * N3;
-        T nl[N];
-#pragma unroll
-        for (int m = 0; m < N; ++m) nl[m] = un[lidx<N, d>(t, m)];
-        T Qn = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) Qn += (s ? tab.dl0[m] : tab.dl1[m]) * nl[m];
-        Pj = Po - (s ? nl[0] : nl[N - 1]);
-        Qs = Qo + Qn;
-      } else {
-        Pj = neu ? T(0) : T(2) * Po;
-        Qs = neu ? T(0) : T(2) * Qo;
+      for (int m = 0; m < N; ++m) {
+        Qo += c[(s ? O.dl1() : O.dl0()) + m] * line[m];
+        Qn += c[(s ? O.dl0() : O.dl1()) + m] * nl[s][m];
       }
-      const T cd = (s ? T(1) : T(-1)) / a.h[d];
-      const T tauF = tau_face(a, e, has[f], e + (s ? stride : -stride));
-      F[(2 * s) * NT + t] = tauF * Pj - T(0.5) * cd * Qs;
-      F[(2 * s + 1) * NT + t] = T(-0.5) * cd * Pj;
+      const T Pn = s ? nl[s][0] : nl[s][N - 1];
+      const T Pj = hf ? Po - Pn : (neu ? T(0) : T(2) * Po);
+      const T Qs = hf ? Qo + Qn : (neu ? T(0) : T(2) * Qo);
+      const T cdn = (s ? T(1) : T(-1)) / a.h[d];
+      F[(2 * s) * NT + t] = tau_face(te, tn[s], hf) * Pj - T(0.5) * cdn * Qs;
+      F[(2 * s + 1) * NT + t] = T(-0.5) * cdn * Pj;
     }
   }
   wave_sync();
   T Z[4] = {0, 0, 0, 0};
-  if (act)
+  if (act) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int cc = 0; cc < 4; ++cc)
 #pragma unroll
-      for (int q = 0; q < N; ++q) Z[c] += LT[2 * NT + ta * N + q] * F[c * NT + q + N * tbb];
+      for (int q = 0; q < N; ++q) Z[cc] += LT[O.M() + ta * N + q] * F[cc * NT + q + N * tbb];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) pin(Z[cc]);
+  }
   wave_sync();
   if (act)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) F[c * NT + t] = Z[c];
+    for (int cc = 0; cc < 4; ++cc) F[cc * NT + t] = Z[cc];
   wave_sync();
   T W[4] = {0, 0, 0, 0};
   if (act) {
     const T hab = a.h[da] * a.h[db];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int cc = 0; cc < 4; ++cc) {
 #pragma unroll
-      for (int q = 0; q < N; ++q) W[c] += LT[2 * NT + tbb * N + q] * F[c * NT + ta + N * q];
-      W[c] *= hab;
+      for (int q = 0; q < N; ++q) W[cc] += LT[O.M() + tbb * N + q] * F[cc * NT + ta + N * q];
+      W[cc] *= hab;
+      pin(W[cc]);
     }
   }
   wave_sync();
   if (act)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) F[c * NT + t] = W[c];
+    for (int cc = 0; cc < 4; ++cc) F[cc * NT + t] = W[cc];
   wave_sync();
   // F[(2s) n^2 + node]: plane term at the end node; F[(2s+1) n^2 + node]:
   // weight of l_i'(s) along the normal line.  Add into this lane's x-line.
   if (act) {
+    const cptr<T> c = fresh(a.tabs);
     const int j = t % N, l = t / N;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -383,11 +457,11 @@ __device__ __forceinline__ void affine_faces(const OpArgs<N, T>& a, const T* A, 
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         if (d == 0) {
-          vacc[i] += (i == endp ? Pv[t] : T(0)) + (s ? tab.dl1[i] : tab.dl0[i]) * Qv[t];
+          vacc[i] += (i == endp ? Pv[t] : T(0)) + c[(s ? O.dl1() : O.dl0()) + i] * Qv[t];
         } else if (d == 1) {
-          vacc[i] += (j == endp ? Pv[i + N * l] : T(0)) + LT[3 * NT + s * N + j] * Qv[i + N * l];
+          vacc[i] += (j == endp ? Pv[i + N * l] : T(0)) + LT[(s ? O.dl1() : O.dl0()) + j] * Qv[i + N * l];
         } else {
-          vacc[i] += (l == endp ? Pv[i + N * j] : T(0)) + LT[3 * NT + s * N + l] * Qv[i + N * j];
+          vacc[i] += (l == endp ? Pv[i + N * j] : T(0)) + LT[(s ? O.dl1() : O.dl0()) + l] * Qv[i + N * j];
         }
       }
     }
@@ -396,35 +470,34 @@ __device__ __forceinline__ void affine_faces(const OpArgs<N, T>& a, const T* A, 
 }
 
 // ------------------------------------------------------------------ operator
+// Phases are separated by wave_sync().  Each phase is one `if (act)` block
+// whose global loads are issued together at its start (clamped addresses,
+// no per-face branches), so a phase costs one memory round trip.
 template <int N, typename T, bool CURVED, bool FE, int MODE>
-__global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<N, CURVED, FE>::WPE)))
+op_kernel(const OpArgs<T> a) {
   using C = Cfg<N, CURVED, FE>;
   constexpr int NT = C::NT, N3 = C::N3, EW = C::EW, PER = C::PER;
+  constexpr TabOff O(N);
   __shared__ T smem[C::WAVES * (EW * PER + C::LT)];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int le = lane / NT, t = lane - le * NT;
-  const int64_t e0 = (int64_t)xcd_block() * C::EB + (int64_t)wave * EW;  // first element of the wave
+  const int64_t e0 = block_chunk(a, xcd_block()) * C::EB + (int64_t)wave * EW;  // first element of the wave
   const int64_t e = e0 + le;
   const bool act = (le < EW) && (e < a.nel);
   T* const W0 = smem + wave * (EW * PER + C::LT);  // this wavefront's LDS
   T* const R = W0 + (le < EW ? le : 0) * PER;
   T* const LT = W0 + EW * PER;
-  const auto& tab = a.tab;
-  for (int i = lane; i < C::LT; i += 64) LT[i] = a.ltab[i];
-  int ec[3] = {0, 0, 0};
-  bool has[6] = {false, false, false, false, false, false};
-  if (act) {
-    ec[0] = (int)(e % a.Nx);
-    const int64_t r = e / a.Nx;
-    ec[1] = (int)(r % a.Ny);
-    ec[2] = (int)(r / a.Ny);
-    has[0] = ec[0] > 0;
-    has[1] = ec[0] + 1 < a.Nx;
-    has[2] = ec[1] > 0;
-    has[3] = ec[1] + 1 < a.Ny;
-    has[4] = ec[2] > 0;
-    has[5] = ec[2] + 1 < a.Nz;
+  {  // lane tables into this wavefront's LDS (loads first, one round trip)
+    constexpr int KL = (C::LT + 63) / 64;
+    T lt[KL];
+#pragma unroll
+    for (int i = 0; i < KL; ++i) lt[i] = a.tabs[lane + 64 * i < C::LT ? lane + 64 * i : 0];
+#pragma unroll
+    for (int i = 0; i < KL; ++i)
+      if (lane + 64 * i < C::LT) LT[lane + 64 * i] = lt[i];
   }
+  const ElemInfo I = elem_info(a, e);
   const int64_t left = a.nel - e0;
   const int nload = (int)(left <= 0 ? 0 : (left < EW ? left : EW)) * N3;
   const int ta = t % N, tbb = t / N;
@@ -432,9 +505,24 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
   // ---- neighbour traces (curved DG), before the own data occupies LDS
   T un[6], dnn[6];
   if constexpr (CURVED && !FE) {
-    nb_nodal<N, T, 0>(a, R, act, t, e, has);
-    nb_nodal<N, T, 1>(a, R, act, t, e, has);
-    nb_nodal<N, T, 2>(a, R, act, t, e, has);
+    {  // neighbour lines of all six faces: end value P, normal derivative Q
+      T nl[6][N];
+      load_nb_lines<N, T, 0>(a, I, t, nl[0], nl[1]);
+      load_nb_lines<N, T, 1>(a, I, t, nl[2], nl[3]);
+      load_nb_lines<N, T, 2>(a, I, t, nl[4], nl[5]);
+      const cptr<T> c = fresh(a.tabs);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const int s = f & 1;
+        T Q = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) Q += c[(s ? O.dl0() : O.dl1()) + m] * nl[f][m];
+        if (act) {
+          R[(2 * f) * NT + t] = s ? nl[f][0] : nl[f][N - 1];
+          R[(2 * f + 1) * NT + t] = Q;
+        }
+      }
+    }
     wave_sync();
     T X[18];
 #pragma unroll
@@ -443,7 +531,7 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
       if (act)
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-          const T sv = LT[ta * N + q], sp = LT[NT + ta * N + q];
+          const T sv = LT[O.S() + ta * N + q], sp = LT[O.Sp() + ta * N + q];
           const T p = R[(2 * f) * NT + q + N * tbb], qq = R[(2 * f + 1) * NT + q + N * tbb];
           X[3 * f] += sv * p;
           X[3 * f + 1] += sp * p;
@@ -453,13 +541,25 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
     wave_sync();
     if (act)
 #pragma unroll
-      for (int c = 0; c < 18; ++c) R[c * NT + t] = X[c];
+      for (int cc = 0; cc < 18; ++cc) R[cc * NT + t] = X[cc];
     wave_sync();
-    nb_finish<N, T, 0>(a, R, LT, act, t, ec, has, un, dnn);
-    nb_finish<N, T, 1>(a, R, LT, act, t, ec, has, un, dnn);
-    nb_finish<N, T, 2>(a, R, LT, act, t, ec, has, un, dnn);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) un[f] = dnn[f] = 0;
+    if (act) {
+      T cn[6][3];
+      face_metric<N, T, 0, false>(a, I, 0, t, cn[0]);
+      face_metric<N, T, 0, false>(a, I, 1, t, cn[1]);
+      face_metric<N, T, 1, false>(a, I, 0, t, cn[2]);
+      face_metric<N, T, 1, false>(a, I, 1, t, cn[3]);
+      face_metric<N, T, 2, false>(a, I, 0, t, cn[4]);
+      face_metric<N, T, 2, false>(a, I, 1, t, cn[5]);
+      nb_finish<N, T, 0>(R, LT, t, I, cn, un, dnn);
+      nb_finish<N, T, 1>(R, LT, t, I, cn, un, dnn);
+      nb_finish<N, T, 2>(R, LT, t, I, cn, un, dnn);
+    }
     wave_sync();
   }
+
 
   // ---- own element data into LDS (coalesced per wavefront)
   if constexpr (!FE) {
@@ -497,27 +597,29 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
 #pragma unroll
     for (int i = 0; i < N; ++i) vacc[i] = 0;
     if constexpr (!FE) {
-      affine_faces<N, T, 0>(a, A, B, LT, act, t, e, has, vacc);
-      affine_faces<N, T, 1>(a, A, B, LT, act, t, e, has, vacc);
-      affine_faces<N, T, 2>(a, A, B, LT, act, t, e, has, vacc);
+      affine_faces<N, T, 0>(a, A, B, LT, act, t, I, vacc);
+      affine_faces<N, T, 1>(a, A, B, LT, act, t, I, vacc);
+      affine_faces<N, T, 2>(a, A, B, LT, act, t, I, vacc);
     }
     const T cx = a.h[1] * a.h[2] / a.h[0], cy = a.h[0] * a.h[2] / a.h[1], cz = a.h[0] * a.h[1] / a.h[2];
     if (act) {  // z: p = M u, q = K u
+      const cptr<T> c = fresh(a.tabs);
       T x[N], p[N], q[N];
       read_line<N, T, 2>(A, t, x);
-      mat<N, T>(tab.M, x, p);
-      mat<N, T>(tab.K, x, q);
+      eo_apply<N, T, 1>(c + O.eo(EO_M), x, p);
+      eo_apply<N, T, 1>(c + O.eo(EO_K), x, q);
       write_line<N, T, 2>(B, t, p);
       write_line<N, T, 2>(Cc, t, q);
     }
     wave_sync();
     if (act) {  // y: r = M p, s = cy K p + cz M q
+      const cptr<T> c = fresh(a.tabs);
       T p[N], q[N], r[N], s1[N], s2[N];
       read_line<N, T, 1>(B, t, p);
       read_line<N, T, 1>(Cc, t, q);
-      mat<N, T>(tab.M, p, r);
-      mat<N, T>(tab.K, p, s1);
-      mat<N, T>(tab.M, q, s2);
+      eo_apply<N, T, 1>(c + O.eo(EO_M), p, r);
+      eo_apply<N, T, 1>(c + O.eo(EO_K), p, s1);
+      eo_apply<N, T, 1>(c + O.eo(EO_M), q, s2);
 #pragma unroll
       for (int m = 0; m < N; ++m) s1[m] = cy * s1[m] + cz * s2[m];
       write_line<N, T, 1>(B, t, r);
@@ -525,11 +627,12 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
     }
     wave_sync();
     if (act) {  // x: v = cx K r + M s
+      const cptr<T> c = fresh(a.tabs);
       T r[N], s[N], v1[N], v2[N];
       read_line<N, T, 0>(B, t, r);
       read_line<N, T, 0>(Cc, t, s);
-      mat<N, T>(tab.K, r, v1);
-      mat<N, T>(tab.M, s, v2);
+      eo_apply<N, T, 1>(c + O.eo(EO_K), r, v1);
+      eo_apply<N, T, 1>(c + O.eo(EO_M), s, v2);
 #pragma unroll
       for (int m = 0; m < N; ++m) v[m] = cx * v1[m] + v2[m] + vacc[m];
     }
@@ -537,44 +640,54 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
     T* const Dg = R + 3 * N3;
     // ---- curved: interpolation to Gauss points, x then y then z
     if (act) {
+      const cptr<T> c = fresh(a.tabs);
       T x[N], y[N];
       read_line<N, T, 0>(A, t, x);
-      mat<N, T>(tab.S, x, y);
+      eo_apply<N, T, 1>(c + O.eo(EO_S), x, y);
       write_line<N, T, 0>(A, t, y);
     }
     wave_sync();
     if (act) {
+      const cptr<T> c = fresh(a.tabs);
       T x[N], y[N];
       read_line<N, T, 1>(A, t, x);
-      mat<N, T>(tab.S, x, y);
+      eo_apply<N, T, 1>(c + O.eo(EO_S), x, y);
       write_line<N, T, 1>(A, t, y);
     }
     wave_sync();
     if (act) {
+      const cptr<T> c = fresh(a.tabs);
       T x[N], uq[N], gz[N];
       read_line<N, T, 2>(A, t, x);
-      mat<N, T>(tab.S, x, uq);
-      mat<N, T>(tab.D, uq, gz);
+      eo_apply<N, T, 1>(c + O.eo(EO_S), x, uq);
+      eo_apply<N, T, -1>(c + O.eo(EO_D), uq, gz);
       write_line<N, T, 2>(A, t, uq);
       write_line<N, T, 2>(Dg, t, gz);
     }
     wave_sync();
     if (act) {  // collocation derivatives in x (-> B) and y (-> Cc)
+      const cptr<T> c = fresh(a.tabs);
       T x[N], y[N];
       read_line<N, T, 0>(A, t, x);
-      mat<N, T>(tab.D, x, y);
+      eo_apply<N, T, -1>(c + O.eo(EO_D), x, y);
       write_line<N, T, 0>(B, t, y);
       read_line<N, T, 1>(A, t, x);
-      mat<N, T>(tab.D, x, y);
+      eo_apply<N, T, -1>(c + O.eo(EO_D), x, y);
       write_line<N, T, 1>(Cc, t, y);
     }
     wave_sync();
     // ---- face fluxes (DG): own traces by extrapolation
     T vt[6], gt[6];
     if constexpr (!FE) {
-      own_flux<N, T, 0>(a, R, act, t, e, ec, has, un, dnn, vt, gt);
-      own_flux<N, T, 1>(a, R, act, t, e, ec, has, un, dnn, vt, gt);
-      own_flux<N, T, 2>(a, R, act, t, e, ec, has, un, dnn, vt, gt);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) vt[f] = gt[f] = 0;
+      // one direction per block (the fences keep the blocks from being
+      // merged, which would put all three directions' data in flight)
+      if (act) own_flux<N, T, 0>(a, R, t, I, un, dnn, vt, gt);
+      wave_sync();
+      if (act) own_flux<N, T, 1>(a, R, t, I, un, dnn, vt, gt);
+      wave_sync();
+      if (act) own_flux<N, T, 2>(a, R, t, I, un, dnn, vt, gt);
       wave_sync();
     }
     // ---- quadrature-point operator on z-lines, z-face tests
@@ -586,14 +699,14 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
         const int o = t + NT * m;
         const T gx = B[o], gy = Cc[o], g3 = Dg[o];
         const T* Gm = G + NT * m;
-        const T g00 = Gm[0], g11 = Gm[N3], g22 = Gm[2 * N3], g01 = Gm[3 * N3], g02 = Gm[4 * N3],
-                g12 = Gm[5 * N3];
+        // stored order 00, 11, 22, 01, 02, 12
+                const T g00 = Gm[0], g11 = Gm[N3], g22 = Gm[2 * N3], g01 = Gm[3 * N3], g02 = Gm[4 * N3], g12 = Gm[5 * N3];
         fx[m] = g00 * gx + g01 * gy + g02 * g3;
         fy[m] = g01 * gx + g11 * gy + g12 * g3;
         fz[m] = g02 * gx + g12 * gy + g22 * g3;
         vq[m] = 0;
       }
-      if constexpr (!FE) inject<N, T, 2>(a, ec, t, vt, gt, vq, fx, fy, fz);
+      if constexpr (!FE) inject<N, T, 2>(a, I, t, vt, gt, vq, fx, fy, fz);
       if constexpr (!FE) write_line<N, T, 2>(A, t, vq);
       write_line<N, T, 2>(B, t, fx);
       write_line<N, T, 2>(Cc, t, fy);
@@ -607,7 +720,7 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
         read_line<N, T, 0>(B, t, fx);
         read_line<N, T, 0>(Cc, t, fy);
         read_line<N, T, 0>(Dg, t, fz);
-        inject<N, T, 0>(a, ec, t, vt, gt, vq, fx, fy, fz);
+        inject<N, T, 0>(a, I, t, vt, gt, vq, fx, fy, fz);
         write_line<N, T, 0>(A, t, vq);
         write_line<N, T, 0>(B, t, fx);
         write_line<N, T, 0>(Cc, t, fy);
@@ -623,12 +736,14 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
       if constexpr (!FE) {
         T vq[N];
         read_line<N, T, 1>(A, t, vq);
-        inject<N, T, 1>(a, ec, t, vt, gt, vq, fx, fy, fz);
-        matT<N, T>(tab.S, vq, cy);
+        inject<N, T, 1>(a, I, t, vt, gt, vq, fx, fy, fz);
+        const cptr<T> c = fresh(a.tabs);
+        eo_apply<N, T, 1>(c + O.eo(EO_ST), vq, cy);
       }
-      matT<N, T>(tab.S, fx, ay);
-      matT<N, T>(tab.S, fz, by);
-      matT<N, T>(tab.Sp, fy, w2);
+      const cptr<T> c = fresh(a.tabs);
+      eo_apply<N, T, 1>(c + O.eo(EO_ST), fx, ay);
+      eo_apply<N, T, 1>(c + O.eo(EO_ST), fz, by);
+      eo_apply<N, T, -1>(c + O.eo(EO_SPT), fy, w2);
 #pragma unroll
       for (int m = 0; m < N; ++m) cy[m] = FE ? w2[m] : cy[m] + w2[m];
       write_line<N, T, 1>(A, t, ay);
@@ -637,13 +752,14 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
     }
     wave_sync();
     if (act) {  // integration in z
+      const cptr<T> c = fresh(a.tabs);
       T ay[N], by[N], cy[N], az[N], bz[N], w2[N];
       read_line<N, T, 2>(A, t, ay);
       read_line<N, T, 2>(B, t, by);
       read_line<N, T, 2>(Cc, t, cy);
-      matT<N, T>(tab.S, ay, az);
-      matT<N, T>(tab.Sp, by, bz);
-      matT<N, T>(tab.S, cy, w2);
+      eo_apply<N, T, 1>(c + O.eo(EO_ST), ay, az);
+      eo_apply<N, T, 1>(c + O.eo(EO_ST), cy, w2);
+      eo_apply<N, T, -1>(c + O.eo(EO_SPT), by, bz);
 #pragma unroll
       for (int m = 0; m < N; ++m) bz[m] += w2[m];
       write_line<N, T, 2>(A, t, az);
@@ -651,11 +767,12 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
     }
     wave_sync();
     if (act) {  // integration in x
+      const cptr<T> c = fresh(a.tabs);
       T az[N], bz[N], w2[N];
       read_line<N, T, 0>(A, t, az);
       read_line<N, T, 0>(B, t, bz);
-      matT<N, T>(tab.Sp, az, v);
-      matT<N, T>(tab.S, bz, w2);
+      eo_apply<N, T, -1>(c + O.eo(EO_SPT), az, v);
+      eo_apply<N, T, 1>(c + O.eo(EO_ST), bz, w2);
 #pragma unroll
       for (int m = 0; m < N; ++m) v[m] += w2[m];
     }
@@ -690,9 +807,9 @@ __global__ void __launch_bounds__(256) op_kernel(const OpArgs<N, T> a) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <int N, typename T>
-static OpArgs<N, T> make_args(const hmg_level* L) {
-  OpArgs<N, T> a;
+template <typename T>
+static OpArgs<T> make_args(const hmg_level* L) {
+  OpArgs<T> a;
   a.u = nullptr;
   a.out = nullptr;
   a.b = nullptr;
@@ -703,28 +820,36 @@ static OpArgs<N, T> make_args(const hmg_level* L) {
   a.metric = (const T*)L->metric();
   for (int d = 0; d < 3; ++d) a.face[d] = (const T*)L->face(d);
   a.tau = (const T*)L->tau();
-  a.ltab = (const T*)L->ltab();
+  a.tabs = (const T*)L->tabs();
   a.nel = L->n_el;
   a.Nx = L->mesh.N[0];
   a.Ny = L->mesh.N[1];
   a.Nz = L->mesh.N[2];
   a.bcmask = L->mesh.bcmask();
+  a.rowchunks = 0;
+  a.tile_y = 1;
   for (int d = 0; d < 3; ++d) a.h[d] = (T)L->mesh.h(d);
-  a.tab = make_tab<N, T>(L->basis);
   return a;
 }
+
+// y-tile height of the workgroup order (rows of elements)
+static constexpr int kTileY = 4;
 
 template <int N, typename T, bool CURVED, bool FE>
 static int run_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                   const void* xold, double sigma, double theta, int* nparts, hipStream_t s) {
   using C = Cfg<N, CURVED, FE>;
-  OpArgs<N, T> a = make_args<N, T>(L);
+  OpArgs<T> a = make_args<T>(L);
   a.u = (const T*)u;
   a.out = (T*)(FE ? L->scratch() : out);
   a.b = (const T*)b;
   a.xold = (const T*)xold;
   a.sigma = (T)sigma;
   a.theta = (T)theta;
+  if (a.Nx % C::EB == 0) {
+    a.rowchunks = a.Nx / C::EB;
+    a.tile_y = kTileY;
+  }
   const int64_t nb = (L->n_el + C::EB - 1) / C::EB;
   if (nb > INT32_MAX / C::WAVES) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
   // one partial per wavefront; the level's partials buffer holds n_el + 64

@@ -147,6 +147,46 @@ Basis1D make_basis(int k) {
   return b;
 }
 
+// Even-odd packing (sig = +1 centrosymmetric, -1 skew): see TabOff.
+static void eo_pack(const std::vector<double>& A, int n, std::vector<double>& out) {
+  const int h = n / 2;
+  for (int q = 0; q < h; ++q)
+    for (int i = 0; i < h; ++i) out.push_back(0.5 * (A[q * n + i] + A[q * n + n - 1 - i]));
+  for (int q = 0; q < h; ++q)
+    for (int i = 0; i < h; ++i) out.push_back(0.5 * (A[q * n + i] - A[q * n + n - 1 - i]));
+  if (n & 1) {
+    for (int q = 0; q < h; ++q) out.push_back(A[q * n + h]);
+    for (int i = 0; i < h; ++i) out.push_back(A[h * n + i]);
+    out.push_back(A[h * n + h]);
+  }
+}
+
+static std::vector<double> transpose(const std::vector<double>& A, int n) {
+  std::vector<double> T((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T[j * n + i] = A[i * n + j];
+  return T;
+}
+
+std::vector<double> op_tables(const Basis1D& b) {
+  const int n = b.n;
+  std::vector<double> t;
+  t.insert(t.end(), b.S.begin(), b.S.end());
+  t.insert(t.end(), b.Sp.begin(), b.Sp.end());
+  t.insert(t.end(), b.M.begin(), b.M.end());
+  t.insert(t.end(), b.dl0.begin(), b.dl0.end());
+  t.insert(t.end(), b.dl1.begin(), b.dl1.end());
+  t.insert(t.end(), b.lg0.begin(), b.lg0.end());
+  t.insert(t.end(), b.lg1.begin(), b.lg1.end());
+  eo_pack(b.S, n, t);
+  eo_pack(transpose(b.S, n), n, t);
+  eo_pack(transpose(b.Sp, n), n, t);
+  eo_pack(b.D, n, t);
+  eo_pack(b.M, n, t);
+  eo_pack(b.K, n, t);
+  return t;
+}
+
 // ------------------------------------------------------------------ mapping
 static const std::vector<double>& q3_nodes() {
   static const std::vector<double> g = gll_nodes(3);
