@@ -10,10 +10,16 @@ and an exact FP64 coarse solve.  `value` is DoFs solved per second
 (N * steps / time).  The FP64 and FP32 operator applies are timed on their
 own with HIP events on the launch stream (operator_apply, roofline).
 
+The plain FP64 solve (the same hierarchy with an FP64 V-cycle) is timed
+after the timed region and reported beside it.  `roofline.traffic` is read
+from the committed counter summary of the FP64 apply kernel when that
+summary was taken on the current kernel source, else null.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline]
+                       [--no-cpu-baseline] [--no-plain-fp64]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -47,6 +53,31 @@ def apply_bytes(nel, k, prec_bytes, curved):
     return b
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "op_kernel_curved_k4_64_f64_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1910_01900_amd", "csrc", "op_kernels.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the FP64 apply kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none for this
+    workload or it was taken on a different kernel source."""
+    if workload != "curved_k4_64" or not os.path.exists(PMC_SUMMARY):
+        return None
+    fields = {}
+    for line in open(PMC_SUMMARY):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def time_applies(L, u, v, reps):
     import torch
     s = torch.cuda.current_stream()
@@ -62,7 +93,7 @@ def time_applies(L, u, v, reps):
     return e0.elapsed_time(e1) / reps  # ms per apply
 
 
-def cpu_baseline(w, u_host, budget_s=20.0):
+def cpu_baseline(w, u_host, budget_s=15.0):
     """The oracle's element-wise apply (O(n^6) dense tabulations) on a
     bounded sample of elements of the same mesh, timed on the host."""
     from threadpoolctl import threadpool_info
@@ -71,16 +102,16 @@ def cpu_baseline(w, u_host, budget_s=20.0):
     k = w["degree"]
     om = BoxMesh(tuple(w["nel"]), deform=w["amp"] if w["deformed"] else 0.0)
     n_el = int(np.prod(w["nel"]))
-    count, elapsed = 64, 0.0
-    sel = None
-    while True:
-        sel = np.arange(count) * (n_el // count)
-        t0 = time.perf_counter()
-        sipg.apply(om, k, u_host, elems=sel)
-        elapsed = time.perf_counter() - t0
-        if elapsed > budget_s / 4 or count >= n_el:
-            break
-        count *= 4
+    # probe on 64 elements, then one run sized to about budget_s seconds
+    probe = np.arange(64) * (n_el // 64)
+    t0 = time.perf_counter()
+    sipg.apply(om, k, u_host, elems=probe)
+    per_elem = (time.perf_counter() - t0) / 64
+    count = int(min(n_el, max(64, budget_s / per_elem)))
+    sel = np.arange(count) * (n_el // count)
+    t0 = time.perf_counter()
+    sipg.apply(om, k, u_host, elems=sel)
+    elapsed = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     dofs = len(sel) * (k + 1) ** 3
     return {"value": dofs / elapsed, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
@@ -96,6 +127,7 @@ def main():
     ap.add_argument("--workload", default="curved_k4_64")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
                     help="only time the operator apply (and a 1 GiB copy used to calibrate "
                          "HBM counters); for profiling")
@@ -159,6 +191,28 @@ def main():
     total = time.perf_counter() - t_start
     ms_per_step = 1e3 * total / a.steps
 
+    del H
+    torch.cuda.empty_cache()
+    plain = None
+    if not a.no_plain_fp64:
+        # plain FP64: the same hierarchy with every level in FP64
+        H64 = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F64)
+        x64 = torch.zeros_like(b)
+        _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)  # warm-up
+        torch.cuda.synchronize()
+        t64 = []
+        for _ in range(max(1, min(a.steps, 3))):
+            x64.zero_()
+            t1 = time.perf_counter()
+            _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)
+            torch.cuda.synchronize()
+            t64.append(time.perf_counter() - t1)
+        plain = {"ns_per_dof": 1e9 * min(t64) / N, "ms": 1e3 * min(t64), "iterations": st64["iters"],
+                 "n10": st64["n10"]}
+        log("plain FP64 solve: %.1f ms, %d iterations" % (plain["ms"], plain["iterations"]))
+        del H64, x64
+        torch.cuda.empty_cache()
+
     # final residual recomputed with the FP64 operator
     L64 = hmg.Level(mesh, prec=hmg.F64)
     r = L64.residual(b, x)
@@ -201,12 +255,15 @@ def main():
         "solve": {"ns_per_dof": 1e9 * (total / a.steps) / N, "iterations": stats["iters"],
                   "n10": stats["n10"], "rho": stats["rho"], "final_rel_residual": rel},
         "operator_apply": {"fp64_dofs_per_s": N / (ms64 * 1e-3), "fp32_dofs_per_s": N / (ms32 * 1e-3),
-                           "fp64_ms": ms64, "fp32_ms": ms32},
-        "roofline": {"kernel": "op_kernel<5,double,curved,DG,APPLY>", "bound": "hbm",
-                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                           "fp64_ms": ms64, "fp32_ms": ms32,
+                           "fp32_achieved_GBs": apply_bytes(w["nel"], k, 4, w["deformed"]) / (ms32 * 1e-3) / 1e9},
+        "roofline": {"kernel": "op_kernel<%d,double,%s,DG,APPLY>" % (k + 1, "curved" if w["deformed"] else "affine"),
+                     "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(a.workload),
                      "algorithmic_bytes_per_launch": bytes64},
     }
+    if plain is not None:
+        out["solve_plain_fp64"] = plain
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, u_host)
