@@ -93,6 +93,28 @@ def time_applies(L, u, v, reps):
     return e0.elapsed_time(e1) / reps  # ms per apply
 
 
+def time_applies_batched(L, nrhs, reps):
+    """ms per batched launch of nrhs vectors (HIP events on the launch stream)."""
+    import torch
+    from paper_1910_01900_amd.inputs import uniform
+    U = L.vectors(nrhs)
+    for r in range(nrhs):
+        U[r, :L.n_dofs] = torch.as_tensor(uniform(100 + r, L.n_dofs), dtype=L.dtype)
+    V = L.vectors(nrhs)
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        L.apply_batched(U, V)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        L.apply_batched(U, V)
+    e1.record(s)
+    e1.synchronize()
+    del U, V
+    return e0.elapsed_time(e1) / reps
+
+
 def cpu_baseline(w, u_host, budget_s=15.0):
     """The oracle's element-wise apply (O(n^6) dense tabulations) on a
     bounded sample of elements of the same mesh, timed on the host."""
@@ -128,6 +150,7 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
+    ap.add_argument("--nrhs", type=int, default=8, help="vectors per batched apply (0: skip)")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
                     help="only time the operator apply (and a 1 GiB copy used to calibrate "
                          "HBM counters); for profiling")
@@ -155,6 +178,7 @@ def main():
         u = L.vector(uniform(1, L.n_dofs))
         v = L.vector()
         ms = time_applies(L, u, v, a.apply_reps)
+        msb = time_applies_batched(L, a.nrhs, max(3, a.apply_reps // 4)) if a.nrhs > 1 else None
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)  # the first copy is the one the counter calibration reads
@@ -170,7 +194,8 @@ def main():
         print(json.dumps({"workload": a.workload, "prec": a.apply_only, "ms_per_apply": ms,
                           "dofs_per_s": L.n_dofs / (ms * 1e-3), "algorithmic_bytes": nb,
                           "achieved_GBs": nb / (ms * 1e-3) / 1e9, "calibration_copy_bytes": 1 << 30,
-                          "device_copy_GBs": copy_gbs}))
+                          "device_copy_GBs": copy_gbs, "nrhs": a.nrhs,
+                          "batched_ms": msb, "batched_dofs_per_s": (a.nrhs * L.n_dofs / (msb * 1e-3)) if msb else None}))
         return
 
     t0 = time.time()
@@ -238,6 +263,16 @@ def main():
     v32 = L32.vector()
     ms32 = time_applies(L32, u32, v32, a.apply_reps)
     del u32, v32
+    batched = None
+    if a.nrhs > 1:
+        msb32 = time_applies_batched(L32, a.nrhs, 5)
+        del L32
+        torch.cuda.empty_cache()
+        msb64 = time_applies_batched(L64, a.nrhs, 5)
+        batched = {"nrhs": a.nrhs, "fp64_ms": msb64, "fp32_ms": msb32,
+                   "fp64_dofs_per_s": a.nrhs * N / (msb64 * 1e-3), "fp32_dofs_per_s": a.nrhs * N / (msb32 * 1e-3)}
+        log("batched apply, %d vectors: FP64 %.3f ms (%.2f GDoF/s), FP32 %.3f ms (%.2f GDoF/s)"
+            % (a.nrhs, msb64, batched["fp64_dofs_per_s"] / 1e9, msb32, batched["fp32_dofs_per_s"] / 1e9))
     bytes64 = apply_bytes(w["nel"], k, 8, w["deformed"])
     achieved = bytes64 / (ms64 * 1e-3) / 1e9
     log("apply FP64 %.3f ms (%.2f GDoF/s, %.0f GB/s), FP32 %.3f ms (%.2f GDoF/s)"
@@ -272,6 +307,8 @@ def main():
     }
     if plain is not None:
         out["solve_plain_fp64"] = plain
+    if batched is not None:
+        out["operator_apply_batched"] = batched
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, u_host)

@@ -116,6 +116,22 @@ int hmg_operator_apply(const hmg_level* L, const void* u, void* v, hipStream_t s
 /* r = b - A u (the residual of Alg. 2).  r must not overlap u. */
 int hmg_residual(const hmg_level* L, const void* b, const void* u, void* r, hipStream_t stream);
 
+/*
+ * The operator of hmg_operator_apply on nrhs vectors in one launch (DG
+ * levels only): v_r = A u_r for r = 0..nrhs-1, where vector r of each
+ * argument starts r*ld values (of the level precision) after its first.
+ * The element geometry is read once for all vectors of an element.
+ * 1 <= nrhs <= 64; ld >= the level's DoF count, ld * value size a multiple
+ * of 256 bytes.  Results equal nrhs separate hmg_operator_apply calls.
+ * The u and v ranges must not overlap.  HMG_ERR_UNSUPPORTED on FE levels.
+ */
+int hmg_operator_apply_batched(const hmg_level* L, int nrhs, const void* u, void* v, int64_t ld,
+                               hipStream_t stream);
+
+/* r_r = b_r - A u_r for nrhs vectors (layout and limits as above). */
+int hmg_residual_batched(const hmg_level* L, int nrhs, const void* b, const void* u, void* r,
+                         int64_t ld, hipStream_t stream);
+
 /* d = diag(A) (Sec. 3.1: the diagonal used by the Chebyshev-Jacobi smoother).
  * The diagonal is setup data: the library evaluates a(phi_i, phi_i) on the
  * host while creating the level (sum-factorized cell part plus own-side face

@@ -370,6 +370,44 @@ extern "C" int hmg_residual(const hmg_level* L, const void* b, const void* u, vo
   return launch_operator(L, OP_RESID, u, r, b, nullptr, 0, 0, nullptr, s);
 }
 
+static int check_batch(const hmg_level* L, int nrhs, int64_t ld) {
+  if (L->space != HMG_DG) return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: DG levels only");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(HMG_ERR_INVALID, "nrhs must be 1..64");
+  if (ld < L->n_dofs) return fail(HMG_ERR_INVALID, "ld must be at least the level's DoF count");
+  if ((ld * (int64_t)L->elem_size()) % 256) return fail(HMG_ERR_INVALID, "ld * element size must be a multiple of 256 bytes");
+  return HMG_OK;
+}
+
+static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+  const char *x = (const char*)a, *y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+extern "C" int hmg_operator_apply_batched(const hmg_level* L, int nrhs, const void* u, void* v, int64_t ld,
+                                          hipStream_t s) {
+  if (!L) return fail(HMG_ERR_INVALID, "level is NULL");
+  TRY(check_batch(L, nrhs, ld));
+  TRY(check_level(L));
+  TRY(check_ptr(u, "u"));
+  TRY(check_ptr(v, "v"));
+  if (ranges_overlap(u, v, (size_t)(ld * (nrhs - 1) + L->n_dofs) * L->elem_size()))
+    return fail(HMG_ERR_INVALID, "u and v must not overlap");
+  return launch_operator_batched(L, OP_APPLY, nrhs, ld, u, v, nullptr, nullptr, 0, 0, nullptr, s);
+}
+
+extern "C" int hmg_residual_batched(const hmg_level* L, int nrhs, const void* b, const void* u, void* r,
+                                    int64_t ld, hipStream_t s) {
+  if (!L) return fail(HMG_ERR_INVALID, "level is NULL");
+  TRY(check_batch(L, nrhs, ld));
+  TRY(check_level(L));
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(u, "u"));
+  TRY(check_ptr(r, "r"));
+  if (ranges_overlap(u, r, (size_t)(ld * (nrhs - 1) + L->n_dofs) * L->elem_size()))
+    return fail(HMG_ERR_INVALID, "u and r must not overlap");
+  return launch_operator_batched(L, OP_RESID, nrhs, ld, u, r, b, nullptr, 0, 0, nullptr, s);
+}
+
 extern "C" int hmg_level_diagonal_host(const hmg_level* L, double* out) {
   if (!L || !out) return fail(HMG_ERR_INVALID, "NULL argument");
   std::copy(L->diag_h.begin(), L->diag_h.end(), out);

@@ -150,6 +150,7 @@ namespace hmg {
 
 constexpr int kPartials = 1024;  // max blocks of a reduction
 constexpr int kTmpVecs = 4;      // level temporaries (Chebyshev, lambda_max)
+constexpr int kMaxRhs = 64;      // vectors per batched launch
 
 // ---------------------------------------------------------------- kernel launchers
 enum OpMode { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2, OP_DOT = 3 };
@@ -159,6 +160,12 @@ enum OpMode { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2, OP_DOT = 3 };
 // OP_DOT : out = A u, partials[blk] = sum u.(A u) (for p^T A p).
 int launch_operator(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, int* nparts, hipStream_t s);
+// The same for nrhs vectors at once (DG levels; OP_APPLY, OP_RESID, OP_CHEB):
+// vector r of u, out, b, xold starts r*ld values after the first; dinv is
+// shared.
+int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
+                            const void* b, const void* xold, double sigma, double theta, int* nparts,
+                            hipStream_t s);
 
 // vectors (type by prec); n elements
 int vec_fill(int prec, void* x, double a, int64_t n, hipStream_t s);

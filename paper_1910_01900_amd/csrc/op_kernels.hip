@@ -71,6 +71,8 @@ struct OpArgs {
   int64_t nel;
   int Nx, Ny, Nz, bcmask;
   int rowchunks, tile_y;  // workgroup order: chunks per x-row (0: linear), y-tile height
+  int nrhs;               // vectors applied at once (work item = element x vector)
+  int64_t ld;             // distance between consecutive vectors, in values
   T h[3];
 };
 
@@ -255,11 +257,11 @@ __device__ __forceinline__ void face_metric(const OpArgs<T>& a, const ElemInfo& 
 // ------------------------------------------------------------------ curved faces
 // Neighbour lines of the two faces of direction d (global memory).
 template <int N, typename T, int d>
-__device__ __forceinline__ void load_nb_lines(const OpArgs<T>& a, const ElemInfo& I, int t, T (&l0)[N],
-                                              T (&l1)[N]) {
+__device__ __forceinline__ void load_nb_lines(const OpArgs<T>& a, const T* ub, const ElemInfo& I, int t,
+                                              T (&l0)[N], T (&l1)[N]) {
   constexpr int N3 = N * N * N;
-  const T* u0 = a.u + nb_elem<d>(a, I, 0) * N3;
-  const T* u1 = a.u + nb_elem<d>(a, I, 1) * N3;
+  const T* u0 = ub + nb_elem<d>(a, I, 0) * N3;
+  const T* u1 = ub + nb_elem<d>(a, I, 1) * N3;
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     l0[m] = u0[lidx<N, d>(t, m)];
@@ -378,8 +380,8 @@ __device__ __forceinline__ void inject(const OpArgs<T>& a, const ElemInfo& I, in
 // and the normal-derivative term -c/2 [u], each taken through the face mass
 // matrix M (x) M.  A: own nodal u; F: LDS scratch of 4 n^2; LT: lane tables.
 template <int N, typename T, int d>
-__device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* A, T* F, const T* LT, bool act,
-                                             int t, const ElemInfo& I, T (&vacc)[N]) {
+__device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, const T* A, T* F, const T* LT,
+                                             bool act, int t, const ElemInfo& I, T (&vacc)[N]) {
   constexpr int NT = N * N;
   constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
   constexpr TabOff O(N);
@@ -387,7 +389,7 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* A, T* 
   if (act) {
     // global loads first: neighbour lines and penalties
     T nl[2][N];
-    load_nb_lines<N, T, d>(a, I, t, nl[0], nl[1]);
+    load_nb_lines<N, T, d>(a, ub, I, t, nl[0], nl[1]);
     const T te = a.tau[I.e];
     const T tn[2] = {a.tau[nb_elem<d>(a, I, 0)], a.tau[nb_elem<d>(a, I, 1)]};
     T line[N];
@@ -469,6 +471,16 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* A, T* 
   wave_sync();
 }
 
+// Offset of the first value of work item `item` (element x vector) in the
+// vectors of a launch.
+template <int N, typename T>
+__device__ __forceinline__ int64_t item_offset(const OpArgs<T>& a, int64_t item) {
+  constexpr int N3 = N * N * N;
+  if (a.nrhs == 1) return item * N3;
+  const int64_t el = item / a.nrhs;
+  return (item - el * a.nrhs) * a.ld + el * N3;
+}
+
 // ------------------------------------------------------------------ operator
 // Phases are separated by wave_sync().  Each phase is one `if (act)` block
 // whose global loads are issued together at its start (clamped addresses,
@@ -482,9 +494,15 @@ op_kernel(const OpArgs<T> a) {
   __shared__ T smem[C::WAVES * (EW * PER + C::LT)];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int le = lane / NT, t = lane - le * NT;
-  const int64_t e0 = block_chunk(a, xcd_block()) * C::EB + (int64_t)wave * EW;  // first element of the wave
-  const int64_t e = e0 + le;
-  const bool act = (le < EW) && (e < a.nel);
+  // work items: (element, vector) pairs, vector fastest; a wavefront owns EW
+  // consecutive items, so with several vectors its slots share one element's
+  // geometry (the same cache lines)
+  const int64_t it0 = block_chunk(a, xcd_block()) * C::EB + (int64_t)wave * EW;  // first item of the wave
+  const int64_t nitems = a.nel * a.nrhs;
+  const int64_t it = it0 + le;
+  const int64_t e = a.nrhs == 1 ? it : it / a.nrhs;
+  const T* const ub = a.u + (a.nrhs == 1 ? 0 : (it - e * a.nrhs) * a.ld);  // this lane's vector
+  const bool act = (le < EW) && (it < nitems);
   T* const W0 = smem + wave * (EW * PER + C::LT);  // this wavefront's LDS
   T* const R = W0 + (le < EW ? le : 0) * PER;
   T* const LT = W0 + EW * PER;
@@ -498,7 +516,7 @@ op_kernel(const OpArgs<T> a) {
       if (lane + 64 * i < C::LT) LT[lane + 64 * i] = lt[i];
   }
   const ElemInfo I = elem_info(a, e);
-  const int64_t left = a.nel - e0;
+  const int64_t left = nitems - it0;
   const int nload = (int)(left <= 0 ? 0 : (left < EW ? left : EW)) * N3;
   const int ta = t % N, tbb = t / N;
 
@@ -507,9 +525,9 @@ op_kernel(const OpArgs<T> a) {
   if constexpr (CURVED && !FE) {
     {  // neighbour lines of all six faces: end value P, normal derivative Q
       T nl[6][N];
-      load_nb_lines<N, T, 0>(a, I, t, nl[0], nl[1]);
-      load_nb_lines<N, T, 1>(a, I, t, nl[2], nl[3]);
-      load_nb_lines<N, T, 2>(a, I, t, nl[4], nl[5]);
+      load_nb_lines<N, T, 0>(a, ub, I, t, nl[0], nl[1]);
+      load_nb_lines<N, T, 1>(a, ub, I, t, nl[2], nl[3]);
+      load_nb_lines<N, T, 2>(a, ub, I, t, nl[4], nl[5]);
       const cptr<T> c = fresh(a.tabs);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
@@ -563,12 +581,12 @@ op_kernel(const OpArgs<T> a) {
 
   // ---- own element data into LDS (coalesced per wavefront)
   if constexpr (!FE) {
-    const T* src = a.u + e0 * N3;
     for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3;
-      W0[li * PER + (idx - li * N3)] = src[idx];
+      W0[li * PER + (idx - li * N3)] = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
     }
   } else {
+    const int64_t e0 = it0;  // continuous FE levels take one vector
     constexpr int k = N - 1;
     const int64_t Mx = (int64_t)a.Nx * k + 1, My = (int64_t)a.Ny * k + 1, Mz = (int64_t)a.Nz * k + 1;
     for (int idx = lane; idx < nload; idx += 64) {
@@ -597,9 +615,9 @@ op_kernel(const OpArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < N; ++i) vacc[i] = 0;
     if constexpr (!FE) {
-      affine_faces<N, T, 0>(a, A, B, LT, act, t, I, vacc);
-      affine_faces<N, T, 1>(a, A, B, LT, act, t, I, vacc);
-      affine_faces<N, T, 2>(a, A, B, LT, act, t, I, vacc);
+      affine_faces<N, T, 0>(a, ub, A, B, LT, act, t, I, vacc);
+      affine_faces<N, T, 1>(a, ub, A, B, LT, act, t, I, vacc);
+      affine_faces<N, T, 2>(a, ub, A, B, LT, act, t, I, vacc);
     }
     const T cx = a.h[1] * a.h[2] / a.h[0], cy = a.h[0] * a.h[2] / a.h[1], cz = a.h[0] * a.h[1] / a.h[2];
     if (act) {  // z: p = M u, q = K u
@@ -782,19 +800,21 @@ op_kernel(const OpArgs<T> a) {
   wave_sync();
 
   // ---- coalesced epilogue over the wavefront's elements
-  const int64_t gbase = e0 * N3;
   double acc = 0.0;
   for (int idx = lane; idx < nload; idx += 64) {
     const int li = idx / N3;
     const T val = W0[li * PER + (idx - li * N3)];
-    const int64_t g = gbase + idx;
+    const int64_t item = it0 + li;
+    const int64_t el = a.nrhs == 1 ? item : item / a.nrhs;
+    const int64_t gv = el * N3 + (idx - li * N3);  // offset inside one vector
+    const int64_t g = gv + (a.nrhs == 1 ? 0 : (item - el * a.nrhs) * a.ld);
     if constexpr (FE || MODE == OP_APPLY) {
       a.out[g] = val;
     } else if constexpr (MODE == OP_RESID) {
       a.out[g] = a.b[g] - val;
     } else if constexpr (MODE == OP_CHEB) {
       const T x = a.u[g];
-      a.out[g] = x + a.sigma * (x - a.xold[g]) + a.theta * a.dinv[g] * (a.b[g] - val);
+      a.out[g] = x + a.sigma * (x - a.xold[g]) + a.theta * a.dinv[gv] * (a.b[g] - val);
     } else {
       a.out[g] = val;
       acc += (double)a.u[g] * (double)val;
@@ -828,6 +848,8 @@ static OpArgs<T> make_args(const hmg_level* L) {
   a.bcmask = L->mesh.bcmask();
   a.rowchunks = 0;
   a.tile_y = 1;
+  a.nrhs = 1;
+  a.ld = L->n_dofs;
   for (int d = 0; d < 3; ++d) a.h[d] = (T)L->mesh.h(d);
   return a;
 }
@@ -837,20 +859,23 @@ static constexpr int kTileY = 4;
 
 template <int N, typename T, bool CURVED, bool FE>
 static int run_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                  const void* xold, double sigma, double theta, int* nparts, hipStream_t s) {
+                  const void* xold, double sigma, double theta, int* nparts, int nrhs, int64_t ld,
+                  hipStream_t s) {
   using C = Cfg<N, CURVED, FE>;
   OpArgs<T> a = make_args<T>(L);
+  a.nrhs = nrhs;
+  a.ld = ld;
   a.u = (const T*)u;
   a.out = (T*)(FE ? L->scratch() : out);
   a.b = (const T*)b;
   a.xold = (const T*)xold;
   a.sigma = (T)sigma;
   a.theta = (T)theta;
-  if (a.Nx % C::EB == 0) {
+  if (nrhs == 1 && a.Nx % C::EB == 0) {
     a.rowchunks = a.Nx / C::EB;
     a.tile_y = kTileY;
   }
-  const int64_t nb = (L->n_el + C::EB - 1) / C::EB;
+  const int64_t nb = (L->n_el * nrhs + C::EB - 1) / C::EB;
   if (nb > INT32_MAX / C::WAVES) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
   // one partial per wavefront; the level's partials buffer holds n_el + 64
   if (nparts) *nparts = (int)nb * C::WAVES;
@@ -881,14 +906,15 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
 
 template <int N, typename T>
 static int dispatch_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                       const void* xold, double sigma, double theta, int* nparts, hipStream_t s) {
+                       const void* xold, double sigma, double theta, int* nparts, int nrhs, int64_t ld,
+                       hipStream_t s) {
   const bool curved = L->mesh.curved, fe = L->space == HMG_FE;
   if (curved) {
-    if (fe) return run_op<N, T, true, true>(L, mode, u, out, b, xold, sigma, theta, nparts, s);
-    return run_op<N, T, true, false>(L, mode, u, out, b, xold, sigma, theta, nparts, s);
+    if (fe) return run_op<N, T, true, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+    return run_op<N, T, true, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
   }
-  if (fe) return run_op<N, T, false, true>(L, mode, u, out, b, xold, sigma, theta, nparts, s);
-  return run_op<N, T, false, false>(L, mode, u, out, b, xold, sigma, theta, nparts, s);
+  if (fe) return run_op<N, T, false, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+  return run_op<N, T, false, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
 }
 
 #define HMG_CAT2(a, b) a##b
@@ -896,10 +922,10 @@ static int dispatch_op(const hmg_level* L, int mode, const void* u, void* out, c
 #ifdef HMG_ONLY_N
 int HMG_CAT(op_launch_n, HMG_ONLY_N)(const hmg_level* L, int mode, const void* u, void* out,
                                       const void* b, const void* xold, double sigma, double theta,
-                                      int* nparts, hipStream_t s) {
+                                      int* nparts, int nrhs, int64_t ld, hipStream_t s) {
   if (L->prec == HMG_F64)
-    return dispatch_op<HMG_ONLY_N, double>(L, mode, u, out, b, xold, sigma, theta, nparts, s);
-  return dispatch_op<HMG_ONLY_N, float>(L, mode, u, out, b, xold, sigma, theta, nparts, s);
+    return dispatch_op<HMG_ONLY_N, double>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+  return dispatch_op<HMG_ONLY_N, float>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
 }
 #endif
 #endif  // HMG_DISPATCH_ONLY
@@ -907,7 +933,7 @@ int HMG_CAT(op_launch_n, HMG_ONLY_N)(const hmg_level* L, int mode, const void* u
 #ifdef HMG_DISPATCH_ONLY
 #define HMG_DECL(N)                                                                          \
   int op_launch_n##N(const hmg_level*, int, const void*, void*, const void*, const void*,    \
-                     double, double, int*, hipStream_t);
+                     double, double, int*, int, int64_t, hipStream_t);
 HMG_DECL(2)
 HMG_DECL(3)
 HMG_DECL(4)
@@ -918,10 +944,18 @@ HMG_DECL(8)
 
 int launch_operator(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, int* nparts, hipStream_t s) {
-  if (L->n_el == 0) return HMG_OK;
+  return launch_operator_batched(L, mode, 1, L->n_dofs, u, out, b, xold, sigma, theta, nparts, s);
+}
+
+int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
+                            const void* b, const void* xold, double sigma, double theta, int* nparts,
+                            hipStream_t s) {
+  if (L->n_el == 0 || nrhs == 0) return HMG_OK;
+  if (nrhs > 1 && (L->space != HMG_DG || mode == OP_DOT))
+    return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: DG levels, apply/residual/Chebyshev only");
   switch (L->n) {
 #define HMG_CASE(N) \
-  case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, s);
+  case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
     HMG_CASE(2) HMG_CASE(3) HMG_CASE(4) HMG_CASE(5) HMG_CASE(6) HMG_CASE(7) HMG_CASE(8)
 #undef HMG_CASE
   }

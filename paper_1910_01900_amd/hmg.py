@@ -68,6 +68,8 @@ def lib():
             "hmg_level_destroy": (None, [_P]),
             "hmg_operator_apply": (C.c_int, [_P, _P, _P, _P]),
             "hmg_residual": (C.c_int, [_P, _P, _P, _P, _P]),
+            "hmg_operator_apply_batched": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
+            "hmg_residual_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int64, _P]),
             "hmg_diagonal": (C.c_int, [_P, _P, _P]),
             "hmg_level_diagonal_host": (C.c_int, [_P, C.POINTER(C.c_double)]),
             "hmg_estimate_lambda_max": (C.c_int, [_P, C.c_int, C.c_uint64, C.POINTER(C.c_double), _P]),
@@ -209,6 +211,28 @@ class Level:
     def residual(self, b, u, r=None):
         r = self.vector() if r is None else r
         check(lib().hmg_residual(self._h, ptr(b), ptr(u), ptr(r), stream()))
+        return r
+
+    def vectors(self, nrhs):
+        """nrhs zero vectors as rows of one [nrhs, ld] tensor, ld padded to 256 bytes."""
+        torch = _torch()
+        per = 256 // (8 if self.prec == F64 else 4)
+        ld = (self.n_dofs + per - 1) // per * per
+        return torch.zeros(nrhs, ld, dtype=self.dtype, device="cuda")
+
+    def apply_batched(self, u, v=None):
+        """v[r, :n] = A u[r, :n] for every row of the 2-D tensors u, v."""
+        v = self.vectors(u.shape[0]) if v is None else v
+        if u.stride(0) != v.stride(0) or u.stride(1) != 1 or v.stride(1) != 1:
+            raise ValueError("u and v need the same row stride and contiguous rows")
+        check(lib().hmg_operator_apply_batched(self._h, u.shape[0], ptr(u), ptr(v), u.stride(0), stream()))
+        return v
+
+    def residual_batched(self, b, u, r=None):
+        r = self.vectors(u.shape[0]) if r is None else r
+        if not (b.stride(0) == u.stride(0) == r.stride(0)):
+            raise ValueError("b, u and r need the same row stride")
+        check(lib().hmg_residual_batched(self._h, u.shape[0], ptr(b), ptr(u), ptr(r), u.stride(0), stream()))
         return r
 
     def diagonal(self):

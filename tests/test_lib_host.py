@@ -135,3 +135,22 @@ def test_host_diagonal_matches_oracle(space, deformed, k):
     hmg.lib().hmg_level_destroy(h)
     ref = sipg.assemble(om, k, ip_factor=2.0).diagonal() if space == hmg.DG else ofe.assemble(om, k).diagonal()
     assert np.abs(d - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_batched_apply_arguments_checked_before_launch():
+    lib = hmg.lib()
+    m = hmg.Mesh((2, 3, 2), 3)
+    _, dg = _create(m)
+    _, fe = _create(m, space=hmg.FE)
+    n = 12 * 64
+    assert lib.hmg_operator_apply_batched(dg, 0, None, None, n, None) == -1
+    assert lib.hmg_operator_apply_batched(dg, 65, None, None, n, None) == -1
+    assert lib.hmg_operator_apply_batched(dg, 2, None, None, n - 1, None) == -1
+    assert lib.hmg_operator_apply_batched(dg, 2, None, None, n + 1, None) == -1  # 256-byte rows
+    assert lib.hmg_operator_apply_batched(fe, 2, None, None, 10 ** 6, None) == -2
+    assert lib.hmg_residual_batched(fe, 2, None, None, None, 10 ** 6, None) == -2
+    # valid arguments on an unbound level: workspace error, still no launch
+    assert lib.hmg_operator_apply_batched(dg, 2, None, None, n, None) == -6
+    assert lib.hmg_residual_batched(dg, 3, None, None, None, n, None) == -6
+    for h in (dg, fe):
+        lib.hmg_level_destroy(h)
