@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
     ap.add_argument("--nrhs", type=int, default=8, help="vectors per batched apply (0: skip)")
+    ap.add_argument("--graph", action="store_true", help="replay PCG iterations from recorded HIP graphs")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
                     help="only time the operator apply (and a 1 GiB copy used to calibrate "
                          "HBM counters); for profiling")
@@ -200,7 +201,7 @@ def main():
 
     t0 = time.time()
     log("setup: hierarchy cph (FP32 V-cycle) for", a.workload)
-    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32)
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32, graph=a.graph)
     log("setup done in %.1f s; levels:" % (time.time() - t0),
         [(l["space"], l["degree"], l["nel"][0]) for l in H.levels()])
     N = H.n_dofs
@@ -229,7 +230,7 @@ def main():
     plain = None
     if not a.no_plain_fp64:
         # plain FP64: the same hierarchy with every level in FP64
-        H64 = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F64)
+        H64 = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F64, graph=a.graph)
         x64 = torch.zeros_like(b)
         _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)  # warm-up
         torch.cuda.synchronize()
@@ -294,7 +295,7 @@ def main():
         "config": {"workload": a.workload, "mesh": "x".join(map(str, w["nel"])), "degree": k,
                    "curved": w["deformed"], "dofs": N, "strategy": "cph", "p_sequence": "floor(p/2)",
                    "smoother": "Chebyshev(5)", "coarse": "exact FP64, FE1 4^3", "rtol": 1e-10,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "graph": a.graph},
         "solve": {"ns_per_dof": 1e9 * (total / a.steps) / N, "iterations": stats["iters"],
                   "n10": stats["n10"], "rho": stats["rho"], "final_rel_residual": rel},
         "operator_apply": {"fp64_dofs_per_s": N / (ms64 * 1e-3), "fp32_dofs_per_s": N / (ms32 * 1e-3),

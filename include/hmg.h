@@ -219,6 +219,19 @@ int hmg_hierarchy_set_lmax(hmg_hierarchy* H, int l, double lmax);
  */
 int hmg_vcycle(hmg_hierarchy* H, const double* b, double* x, hipStream_t stream);
 
+/*
+ * For callers whose meshes are small enough that kernel launch latency
+ * dominates (Sec. 5 strong-scaling regime): with enable != 0, hmg_pcg_solve
+ * records one iteration after the first (V-cycle of Alg. 2, the dot
+ * products and vector updates of Alg. 1, the operator apply) and hmg_vcycle
+ * records its V-cycle, each once as a HIP graph on a stream the library
+ * creates (default priority), and replays it on the caller's stream.  A
+ * recording is redone when the solution (and, for hmg_vcycle, right-hand
+ * side) pointers change or the hierarchy is bound again.  Results are
+ * bitwise identical to enable = 0.  Calls on one hierarchy must not overlap.
+ */
+int hmg_hierarchy_set_graph(hmg_hierarchy* H, int enable);
+
 typedef struct {
   int32_t iters;
   double r0, rn;       /* ||b - A x_0||_2 and final ||r||_2 */

@@ -683,6 +683,18 @@ struct hmg_hierarchy {
   size_t off_f64 = 0, off_c64 = 0, off_ainv = 0, off_cg = 0, off_part = 0, off_scal = 0;
   char* ws = nullptr;
   bool bound = false;
+  // launch graphs (hmg_hierarchy_set_graph): one PCG iteration and one
+  // V-cycle, recorded on a library stream, keyed by the caller's vectors
+  bool use_graph = false;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t it_exec = nullptr, vc_exec = nullptr;
+  const void *it_x = nullptr, *vc_b = nullptr, *vc_x = nullptr;
+  void drop_graphs() {
+    if (it_exec) (void)hipGraphExecDestroy(it_exec);
+    if (vc_exec) (void)hipGraphExecDestroy(vc_exec);
+    it_exec = vc_exec = nullptr;
+    it_x = vc_b = vc_x = nullptr;
+  }
   void* b(int l) const { return ws + off_b[l]; }
   void* x(int l) const { return ws + off_x[l]; }
   void* r(int l) const { return ws + off_r[l]; }
@@ -691,6 +703,8 @@ struct hmg_hierarchy {
   double* scal() const { return (double*)(ws + off_scal); }
   double* ainv() const { return (double*)(ws + off_ainv); }
   ~hmg_hierarchy() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
     for (auto* t : tr) delete t;
     if (own_fine64) delete fine64;
     if (own_coarse64) delete coarse64;
@@ -905,6 +919,7 @@ extern "C" int hmg_hierarchy_bind(hmg_hierarchy* H, void* ws, size_t bytes, hipS
   if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
   if (!ws || (((uintptr_t)ws) & 255)) return fail(HMG_ERR_WORKSPACE, "workspace NULL or misaligned");
   if (bytes < H->ws_bytes) return fail(HMG_ERR_WORKSPACE, "workspace too small");
+  H->drop_graphs();  // recorded launches point into the previous workspace
   H->ws = (char*)ws;
   for (size_t l = 0; l < H->lv.size(); ++l)
     TRY(hmg_level_bind(H->lv[l], H->ws + H->off_lv[l], H->lv[l]->ws_bytes, s));
@@ -959,6 +974,39 @@ static int vcycle(hmg_hierarchy* H, size_t l, hipStream_t s) {
   return chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax[l], 0.06, 1.2, 0, s);
 }
 
+// Record body(stream) once as a HIP graph on the hierarchy's own stream
+// (default priority; nothing is executed while recording) and instantiate it.
+template <class Body>
+static int record(hmg_hierarchy* H, hipGraphExec_t* exec, Body&& body) {
+  if (!H->cap) HMG_HIP(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
+  if (*exec) {
+    (void)hipGraphExecDestroy(*exec);
+    *exec = nullptr;
+  }
+  HMG_HIP(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
+  const int rc = body(H->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(H->cap, &g);
+  if (rc != HMG_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != HMG_OK ? rc : fail(HMG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    *exec = nullptr;
+    return fail(HMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_set_graph(hmg_hierarchy* H, int enable) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  H->use_graph = enable != 0;
+  if (!H->use_graph) H->drop_graphs();
+  return HMG_OK;
+}
+
 static int precondition(hmg_hierarchy* H, const double* b, double* x, hipStream_t s) {
   const int pr = H->mg_prec;
   const int64_t n = H->lv[0]->n_dofs;
@@ -972,7 +1020,40 @@ extern "C" int hmg_vcycle(hmg_hierarchy* H, const double* b, double* x, hipStrea
   TRY(check_ptr(b, "b"));
   TRY(check_ptr(x, "x"));
   if ((const void*)b == (void*)x) return fail(HMG_ERR_INVALID, "b and x must not overlap");
-  return precondition(H, b, x, s);
+  if (!H->use_graph) return precondition(H, b, x, s);
+  if (!H->vc_exec || H->vc_b != b || H->vc_x != x) {
+    TRY(record(H, &H->vc_exec, [&](hipStream_t cs) { return precondition(H, b, x, cs); }));
+    H->vc_b = b;
+    H->vc_x = x;
+  }
+  HMG_HIP(hipGraphLaunch(H->vc_exec, s));
+  return HMG_OK;
+}
+
+// The second half of a PCG iteration (Alg. 1): v = A p, p.Ap -> sc[2],
+// alpha = sc[1] / sc[2], x += alpha p, r -= alpha v, r.r -> sc[3], and the
+// current delta kept in sc[0] for the next beta.
+static int pcg_update(hmg_hierarchy* H, double* x, hipStream_t s) {
+  const hmg_level* A = H->fine64;
+  const int64_t n = A->n_dofs;
+  double *r = H->cg(0), *p = H->cg(1), *v = H->cg(2), *sc = H->scal(), *part = H->part();
+  int nparts = 0;
+  TRY(launch_operator(A, OP_DOT, p, v, nullptr, nullptr, 0, 0, &nparts, s));
+  TRY(reduce_partials(A->partials(), nparts, sc + 2, s));
+  const int g = cg_update_xr(x, r, p, v, sc + 1, sc + 2, n, part, s, sc + 0);
+  if (g < 0) return g;
+  return reduce_partials(part, g, sc + 3, s);
+}
+
+// A full PCG iteration after the first: z = M^{-1} r (V-cycle), delta =
+// r.z -> sc[1], p = z + (sc[1] / sc[0]) p, then pcg_update.
+static int pcg_iteration(hmg_hierarchy* H, double* x, hipStream_t s) {
+  const int64_t n = H->fine64->n_dofs;
+  double *r = H->cg(0), *p = H->cg(1), *z = H->cg(3), *sc = H->scal(), *part = H->part();
+  TRY(precondition(H, r, z, s));
+  TRY(vec_dot(HMG_F64, r, z, n, part, sc + 1, s));
+  TRY(cg_update_p(p, z, sc + 1, sc + 0, n, s));
+  return pcg_update(H, x, s);
 }
 
 extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, double atol,
@@ -983,8 +1064,8 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   if (maxit < 0) return fail(HMG_ERR_INVALID, "maxit < 0");
   const hmg_level* A = H->fine64;
   const int64_t n = A->n_dofs;
-  double *r = H->cg(0), *p = H->cg(1), *v = H->cg(2), *z = H->cg(3);
-  double* sc = H->scal();  // 0,1: delta ping-pong, 2: p.Ap, 3: r.r
+  double *r = H->cg(0), *p = H->cg(1), *z = H->cg(3);
+  double* sc = H->scal();  // 0: previous delta, 1: delta = r.z, 2: p.Ap, 3: r.r
   double* part = H->part();
   hmg_solve_stats stats{0, 0, 0, 0, 0};
   auto finish = [&](int code) {
@@ -1003,17 +1084,20 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   if (r0 == 0.0 || nr <= atol) return finish(HMG_OK);
   TRY(precondition(H, r, z, s));
   TRY(vec_copy(HMG_F64, z, p, n, s));
-  TRY(vec_dot(HMG_F64, r, z, n, part, sc + 0, s));
+  TRY(vec_dot(HMG_F64, r, z, n, part, sc + 1, s));
   int it = 0;
   while (nr / r0 > rtol && nr > atol && it < maxit) {
-    double* dcur = sc + (it & 1);
-    double* dnew = sc + ((it + 1) & 1);
-    int nparts = 0;
-    TRY(launch_operator(A, OP_DOT, p, v, nullptr, nullptr, 0, 0, &nparts, s));
-    TRY(reduce_partials(A->partials(), nparts, sc + 2, s));
-    int g = cg_update_xr(x, r, p, v, dcur, sc + 2, n, part, s);
-    if (g < 0) return finish(g);
-    TRY(reduce_partials(part, g, sc + 3, s));
+    if (it == 0) {
+      TRY(pcg_update(H, x, s));
+    } else if (H->use_graph) {
+      if (!H->it_exec || H->it_x != x) {
+        TRY(record(H, &H->it_exec, [&](hipStream_t cs) { return pcg_iteration(H, x, cs); }));
+        H->it_x = x;
+      }
+      HMG_HIP(hipGraphLaunch(H->it_exec, s));
+    } else {
+      TRY(pcg_iteration(H, x, s));
+    }
     double hs[2];
     HMG_HIP(hipMemcpyAsync(hs, sc + 2, 16, hipMemcpyDeviceToHost, s));
     HMG_HIP(hipStreamSynchronize(s));
@@ -1023,10 +1107,6 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
     stats.rn = nr;
     if (!(hs[0] > 0)) return finish(fail(HMG_ERR_BREAKDOWN, "p^T A p <= 0: operator not SPD"));
     if (!std::isfinite(nr)) return finish(fail(HMG_ERR_NONFINITE, "residual is not finite"));
-    if (!(nr / r0 > rtol && nr > atol)) break;
-    TRY(precondition(H, r, z, s));
-    TRY(vec_dot(HMG_F64, r, z, n, part, dnew, s));
-    TRY(cg_update_p(p, z, dnew, dcur, n, s));
   }
   if (it > 0) {
     stats.rho = std::pow(nr / r0, 1.0 / it);

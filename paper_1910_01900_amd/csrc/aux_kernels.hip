@@ -79,8 +79,10 @@ __global__ void k_splitmix(uint64_t seed, T* x, int64_t n) {
 
 // CG (Alg. 1): omega = delta / (p^T v); x += omega p; r -= omega v; partials of r.r
 __global__ void k_cg_xr(double* x, double* r, const double* p, const double* v, const double* num,
-                        const double* den, int64_t n, double* partials) {
+                        const double* den, int64_t n, double* partials, double* save) {
   const double omega = *num / *den;
+  // keep delta = *num for the next iteration's beta (save != num, den)
+  if (save && blockIdx.x == 0 && threadIdx.x == 0) *save = *num;
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += omega * p[i];
@@ -170,9 +172,9 @@ int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials,
   return reduce_partials(partials, (int)g, out, s);
 }
 int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
-                 const double* den, int64_t n, double* partials, hipStream_t s) {
+                 const double* den, int64_t n, double* partials, hipStream_t s, double* save) {
   const unsigned g = dot_grid(n);
-  hipLaunchKernelGGL(k_cg_xr, g, kBlock, 0, s, x, r, p, v, num, den, n, partials);
+  hipLaunchKernelGGL(k_cg_xr, g, kBlock, 0, s, x, r, p, v, num, den, n, partials, save);
   int rc = check_launch("cg_xr");
   if (rc) return rc;
   return (int)g;  // caller reduces g partials
@@ -190,38 +192,41 @@ int vec_splitmix(int prec, uint64_t seed, void* x, int64_t n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ FE node sums
-// The elements sharing global node g along one direction: up to two
-// (element coordinate, local index) pairs.
-struct NodeDir {
-  int cnt;
-  int e[2], loc[2];
+// Along one axis, node g lies in element q = g / k at local index g - q k;
+// a node on an element boundary (local 0) is shared by q - 1 (local k) and q.
+// Candidates are listed lower element first; `two` marks a shared node.
+// Index arithmetic is 32-bit (node and DoF counts checked on the host).
+struct Axis {
+  int e0, l0, e1, l1;
+  bool two;
 };
-__device__ __forceinline__ NodeDir node_dir(int64_t g, int k, int Nd) {
-  NodeDir r;
-  const int q = (int)(g / k), rem = (int)(g - (int64_t)q * k);
+__device__ __forceinline__ Axis node_axis(int g, int k, int Nd) {
+  const int q = g / k, rem = g - q * k;
+  Axis A;
+  A.two = false;
   if (rem != 0) {
-    r.cnt = 1;
-    r.e[0] = q;
-    r.loc[0] = rem;
+    A.e0 = q;
+    A.l0 = rem;
+  } else if (q == 0) {
+    A.e0 = 0;
+    A.l0 = 0;
+  } else if (q == Nd) {
+    A.e0 = Nd - 1;
+    A.l0 = k;
   } else {
-    r.cnt = 0;
-    if (q >= 1) {
-      r.e[r.cnt] = q - 1;
-      r.loc[r.cnt] = k;
-      ++r.cnt;
-    }
-    if (q < Nd) {
-      r.e[r.cnt] = q;
-      r.loc[r.cnt] = 0;
-      ++r.cnt;
-    }
+    A.e0 = q - 1;
+    A.l0 = k;
+    A.two = true;
   }
-  return r;
+  A.e1 = A.two ? q : A.e0;
+  A.l1 = A.two ? 0 : A.l0;
+  return A;
 }
 
 struct FeGeo {
   int Nx, Ny, Nz, k, bcmask;
-  int64_t Mx, My, Mz, nnodes;
+  int Mx, My, Mz;
+  int64_t nnodes;
 };
 static FeGeo fe_geo(const Mesh& m, int k) {
   FeGeo g;
@@ -230,83 +235,101 @@ static FeGeo fe_geo(const Mesh& m, int k) {
   g.Nz = m.N[2];
   g.k = k;
   g.bcmask = m.bcmask();
-  g.Mx = (int64_t)m.N[0] * k + 1;
-  g.My = (int64_t)m.N[1] * k + 1;
-  g.Mz = (int64_t)m.N[2] * k + 1;
-  g.nnodes = g.Mx * g.My * g.Mz;
+  g.Mx = m.N[0] * k + 1;
+  g.My = m.N[1] * k + 1;
+  g.Mz = m.N[2] * k + 1;
+  g.nnodes = (int64_t)g.Mx * g.My * g.Mz;
   return g;
 }
-__device__ __forceinline__ bool node_fixed(const FeGeo& G, int64_t gx, int64_t gy, int64_t gz) {
+__device__ __forceinline__ bool node_fixed(const FeGeo& G, int gx, int gy, int gz) {
   const int m = G.bcmask;
   return (gx == 0 && !(m & 1)) || (gx == G.Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
          (gy == G.My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == G.Mz - 1 && !(m & 32));
 }
 
-// sum of a DG-layout vector over the elements sharing each node; returns the
-// multiplicity in *mult
+// Sum of a DG-layout vector over the elements sharing node (gx, gy, gz), in
+// a fixed order (z, then y, then x candidates, lower first); *mult is the
+// number of elements.
 template <typename T>
-__device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int64_t gx, int64_t gy,
-                                             int64_t gz, int* mult) {
+__device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int gx, int gy, int gz, int* mult) {
   const int n = G.k + 1, n3 = n * n * n;
-  NodeDir X = node_dir(gx, G.k, G.Nx), Y = node_dir(gy, G.k, G.Ny), Z = node_dir(gz, G.k, G.Nz);
+  const Axis X = node_axis(gx, G.k, G.Nx), Y = node_axis(gy, G.k, G.Ny), Z = node_axis(gz, G.k, G.Nz);
   T s = 0;
-  for (int c = 0; c < Z.cnt; ++c)
-    for (int b = 0; b < Y.cnt; ++b)
-      for (int a = 0; a < X.cnt; ++a) {
-        const int64_t e = X.e[a] + (int64_t)G.Nx * (Y.e[b] + (int64_t)G.Ny * Z.e[c]);
-        s += dg[e * n3 + X.loc[a] + n * (Y.loc[b] + n * Z.loc[c])];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c == 1 && !Z.two) break;
+    const int ez = c ? Z.e1 : Z.e0, lz = c ? Z.l1 : Z.l0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (b == 1 && !Y.two) break;
+      const int ey = b ? Y.e1 : Y.e0, ly = b ? Y.l1 : Y.l0;
+      const int64_t row = (int64_t)G.Nx * (ey + G.Ny * ez);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        if (a == 1 && !X.two) break;
+        const int ex = a ? X.e1 : X.e0, lx = a ? X.l1 : X.l0;
+        s += dg[(row + ex) * n3 + lx + n * (ly + n * lz)];
       }
-  *mult = X.cnt * Y.cnt * Z.cnt;
+    }
+  }
+  *mult = (1 + X.two) * (1 + Y.two) * (1 + Z.two);
   return s;
 }
 
+// Launch shape of the node kernels: x along gx (64 lanes), y along gy,
+// z along gz; one node per thread.
+constexpr int kNodeBx = 64, kNodeBy = 4;
+static dim3 node_grid(const FeGeo& G) {
+  return dim3((unsigned)((G.Mx + kNodeBx - 1) / kNodeBx), (unsigned)((G.My + kNodeBy - 1) / kNodeBy),
+              (unsigned)G.Mz);
+}
+
 template <typename T, int MODE>
-__global__ void k_fe_sum(FeGeo G, const T* dg, const T* u, T* out, const T* b, const T* dinv,
-                         const T* xold, T sigma, T theta) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.nnodes; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gx = i % G.Mx, r = i / G.Mx, gy = r % G.My, gz = r / G.My;
-    int mult;
-    T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
-    if (node_fixed(G, gx, gy, gz)) v = u[i];
-    if (MODE == OP_APPLY) {
-      out[i] = v;
-    } else if (MODE == OP_RESID) {
-      out[i] = b[i] - v;
-    } else {
-      const T x = u[i];
-      out[i] = x + sigma * (x - xold[i]) + theta * dinv[i] * (b[i] - v);
-    }
+__global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* dg, const T* u, T* out, const T* b,
+                                                              const T* dinv, const T* xold, T sigma, T theta) {
+  const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
+  if (gx >= G.Mx || gy >= G.My) return;
+  const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
+  int mult;
+  T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
+  if (node_fixed(G, gx, gy, gz)) v = u[i];
+  if (MODE == OP_APPLY) {
+    out[i] = v;
+  } else if (MODE == OP_RESID) {
+    out[i] = b[i] - v;
+  } else {
+    const T x = u[i];
+    out[i] = x + sigma * (x - xold[i]) + theta * dinv[i] * (b[i] - v);
   }
 }
 // fe (+)= free * w * E^T dg
 template <typename T>
-__global__ void k_c_sum(FeGeo G, const T* dg, T* fe, int weight_mult, int add) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.nnodes; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gx = i % G.Mx, r = i / G.Mx, gy = r % G.My, gz = r / G.My;
-    int mult;
-    T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
-    if (weight_mult) v /= (T)mult;
-    if (node_fixed(G, gx, gy, gz)) v = 0;
-    fe[i] = add ? fe[i] + v : v;
-  }
+__global__ void __launch_bounds__(kNodeBx * kNodeBy) k_c_sum(FeGeo G, const T* dg, T* fe, int weight_mult, int add) {
+  const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
+  if (gx >= G.Mx || gy >= G.My) return;
+  const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
+  int mult;
+  T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
+  if (weight_mult) v /= (T)mult;
+  if (node_fixed(G, gx, gy, gz)) v = 0;
+  fe[i] = add ? fe[i] + v : v;
 }
-// dg (+)= E (free * w * fe)
+// dg (+)= E (free * w * fe); one thread per DG value (count < 2^31)
 template <typename T>
 __global__ void k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add) {
-  const int n = G.k + 1, n3 = n * n * n;
-  const int64_t ndg = (int64_t)G.Nx * G.Ny * G.Nz * n3;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ndg; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = i / n3;
-    const int p = (int)(i - e * n3);
-    const int64_t gx = (e % G.Nx) * G.k + p % n;
-    const int64_t er = e / G.Nx;
-    const int64_t gy = (er % G.Ny) * G.k + (p / n) % n;
-    const int64_t gz = (er / G.Ny) * G.k + p / (n * n);
+  const int n = G.k + 1, n2 = n * n, n3 = n2 * n;
+  const unsigned ndg = (unsigned)G.Nx * G.Ny * G.Nz * n3;
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < ndg; i += gridDim.x * blockDim.x) {
+    const unsigned e = i / n3, p = i - e * n3;
+    const unsigned er = e / G.Nx, ex = e - er * G.Nx, ez = er / G.Ny, ey = er - ez * G.Ny;
+    const unsigned pz = p / n2, pr = p - pz * n2, py = pr / n, px = pr - py * n;
+    const int gx = ex * G.k + px, gy = ey * G.k + py, gz = ez * G.k + pz;
     T v = 0;
     if (!node_fixed(G, gx, gy, gz)) {
-      v = fe[gx + G.Mx * (gy + G.My * gz)];
+      v = fe[gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz)];
       if (weight_mult) {
-        int mult = node_dir(gx, G.k, G.Nx).cnt * node_dir(gy, G.k, G.Ny).cnt * node_dir(gz, G.k, G.Nz).cnt;
+        const int mult = (1 + node_axis(gx, G.k, G.Nx).two) * (1 + node_axis(gy, G.k, G.Ny).two) *
+                         (1 + node_axis(gz, G.k, G.Nz).two);
         v /= (T)mult;
       }
     }
@@ -318,20 +341,21 @@ template <typename T>
 static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, hipStream_t s) {
   FeGeo G = fe_geo(L->mesh, L->k);
-  const unsigned g = grid_for(G.nnodes);
+  if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
+  const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
   const T* dg = (const T*)L->scratch();
   const T* di = (const T*)L->dinv();
   switch (mode) {
     case OP_RESID:
-      hipLaunchKernelGGL((k_fe_sum<T, OP_RESID>), g, kBlock, 0, s, G, dg, (const T*)u, (T*)out,
+      hipLaunchKernelGGL((k_fe_sum<T, OP_RESID>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
                          (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
       break;
     case OP_CHEB:
-      hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB>), g, kBlock, 0, s, G, dg, (const T*)u, (T*)out,
+      hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
                          (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
       break;
     default:
-      hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY>), g, kBlock, 0, s, G, dg, (const T*)u, (T*)out,
+      hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
                          (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
   }
   return check_launch("fe_sum");
@@ -345,6 +369,7 @@ int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int we
                 hipStream_t s) {
   FeGeo G = fe_geo(m, k);
   const int64_t ndg = m.n_el() * (int64_t)(k + 1) * (k + 1) * (k + 1);
+  if (ndg >= (int64_t)1 << 31) return fail(HMG_ERR_UNSUPPORTED, "DG vector too long for the injection kernel");
   const unsigned g = grid_for(ndg);
   PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_inject<double>, g, kBlock, 0, s, G, (const double*)fe, (double*)dg, weight_mult, add),
                 hipLaunchKernelGGL(k_c_inject<float>, g, kBlock, 0, s, G, (const float*)fe, (float*)dg, weight_mult, add));
@@ -353,9 +378,10 @@ int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int we
 int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
              hipStream_t s) {
   FeGeo G = fe_geo(m, k);
-  const unsigned g = grid_for(G.nnodes);
-  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_sum<double>, g, kBlock, 0, s, G, (const double*)dg, (double*)fe, weight_mult, add),
-                hipLaunchKernelGGL(k_c_sum<float>, g, kBlock, 0, s, G, (const float*)dg, (float*)fe, weight_mult, add));
+  if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
+  const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
+  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_sum<double>, g, blk, 0, s, G, (const double*)dg, (double*)fe, weight_mult, add),
+                hipLaunchKernelGGL(k_c_sum<float>, g, blk, 0, s, G, (const float*)dg, (float*)fe, weight_mult, add));
   return check_launch("c_sum");
 }
 

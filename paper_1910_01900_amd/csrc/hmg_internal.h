@@ -181,10 +181,10 @@ int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials,
             hipStream_t s);
 int reduce_partials(const double* partials, int nparts, double* out, hipStream_t s);
 // CG updates with device scalars (all FP64): see kernels for formulas
-// omega = *num / *den; x += omega p; r -= omega v; returns the number of
-// partials of r.r written (>0) or an error (<0)
+// omega = *num / *den; x += omega p; r -= omega v; *save = *num if save;
+// returns the number of partials of r.r written (>0) or an error (<0)
 int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
-                 const double* den, int64_t n, double* partials, hipStream_t s);
+                 const double* den, int64_t n, double* partials, hipStream_t s, double* save = nullptr);
 // p = z + (*num / *den) p
 int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
                 hipStream_t s);

@@ -586,20 +586,21 @@ op_kernel(const OpArgs<T> a) {
       W0[li * PER + (idx - li * N3)] = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
     }
   } else {
-    const int64_t e0 = it0;  // continuous FE levels take one vector
+    // continuous FE levels take one vector; element and node indices fit
+    // in 32 bits (the level's node count is checked on the host)
+    const unsigned e0 = (unsigned)it0;
     constexpr int k = N - 1;
-    const int64_t Mx = (int64_t)a.Nx * k + 1, My = (int64_t)a.Ny * k + 1, Mz = (int64_t)a.Nz * k + 1;
+    const int Mx = a.Nx * k + 1, My = a.Ny * k + 1, Mz = a.Nz * k + 1;
     for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3, p = idx - li * N3;
-      const int64_t ee = e0 + li;
-      const int64_t gx = (ee % a.Nx) * k + p % N;
-      const int64_t rr = ee / a.Nx;
-      const int64_t gy = (rr % a.Ny) * k + (p / N) % N;
-      const int64_t gz = (rr / a.Ny) * k + p / NT;
+      const unsigned ee = e0 + li, rr = ee / (unsigned)a.Nx, ez = rr / (unsigned)a.Ny;
+      const int gx = (int)(ee - rr * a.Nx) * k + p % N;
+      const int gy = (int)(rr - ez * a.Ny) * k + (p / N) % N;
+      const int gz = (int)ez * k + p / NT;
       const int m = a.bcmask;
       const bool fixed = (gx == 0 && !(m & 1)) || (gx == Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
                          (gy == My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == Mz - 1 && !(m & 32));
-      W0[li * PER + p] = fixed ? T(0) : a.u[gx + Mx * (gy + My * gz)];
+      W0[li * PER + p] = fixed ? T(0) : a.u[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
     }
   }
   wave_sync();

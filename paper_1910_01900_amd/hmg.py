@@ -90,6 +90,7 @@ def lib():
             "hmg_hierarchy_level_info": (C.c_int, [_P, C.c_int, C.POINTER(LevelInfo)]),
             "hmg_hierarchy_set_lmax": (C.c_int, [_P, C.c_int, C.c_double]),
             "hmg_vcycle": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_hierarchy_set_graph": (C.c_int, [_P, C.c_int]),
             "hmg_pcg_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int,
                                         C.POINTER(SolveStats), _P]),
             "hmg_rhs_sine": (C.c_int, [_P, C.c_double, _P, _P]),
@@ -290,7 +291,7 @@ class Hierarchy:
     """Hybrid multigrid hierarchy + FP64 PCG (hmg_hierarchy)."""
 
     def __init__(self, mesh, strategy="cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=F64,
-                 lmax_seed=1):
+                 lmax_seed=1, graph=False):
         self.mesh = mesh
         self._h = C.c_void_p()
         desc = mesh.desc()
@@ -301,6 +302,11 @@ class Hierarchy:
         self.n_dofs, self.ws_bytes = n.value, ws.value
         self.ws = _workspace(ws.value)
         check(lib().hmg_hierarchy_bind(self._h, ptr(self.ws), ws.value, stream()))
+        self.set_graph(graph)
+
+    def set_graph(self, enable):
+        """Replay PCG iterations / V-cycles from recorded HIP graphs (hmg_hierarchy_set_graph)."""
+        check(lib().hmg_hierarchy_set_graph(self._h, 1 if enable else 0))
 
     def levels(self):
         n = C.c_int()
