@@ -2,6 +2,8 @@
 // multigrid transfers and the coarse-level dense solve for gfx950.
 #include "hmg_internal.h"
 
+#include <algorithm>
+
 namespace hmg {
 
 static constexpr int kBlock = 256;
@@ -394,99 +396,130 @@ struct TrArgs {
   int nf, nc, kind;  // kind 0: p, 1: h
   int Nf[3];
   int64_t nel_f, nel_c;
+  int W;  // output elements per wavefront
 };
 
-// out[o0,o1,o2] = sum M2[o2,i2] M1[o1,i1] M0[o0,i0] in[i0,i1,i2] in LDS
-// (x fastest); trans selects M^T (M stored nf x nc).
-template <typename T>
-__device__ void tensor3(const TrArgs<T>& a, const T* in, T* t1, T* t2, T* out, int ni, int no,
-                        const int child[3], bool trans) {
+// Wavefront-local transfer kernel: a wavefront takes W output elements
+// (W = min(64 / no^3, kTrLds / ni^3), at least 1), stages each input element
+// in its own LDS slot, and every lane computes whole output values with the
+// factorized sums
+//   out[o0,o1,o2] = sum_i2 M[o2,i2] sum_i1 M[o1,i1] sum_i0 M[o0,i0] in[i0,i1,i2]
+// (x fastest), M = P_child for prolongation and P_child^T for restriction;
+// the h-restriction adds the 8 children in a fixed order.  No workgroup
+// barrier: four independent wavefronts per workgroup.
+constexpr int kTrLds = 1024;  // staged input values per wavefront
+constexpr int kTrOut = 8;     // output values per lane (n^3 <= 512)
+
+template <typename T, bool RESTRICT>
+__global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* out, int add) {
+  __shared__ T buf[4][kTrLds];
+  __shared__ T Pl[4][2 * kMaxN * kMaxN];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nf = a.nf, nc = a.nc;
-  auto M = [&](int d, int o, int i) -> T {
-    const T* P = a.P[child[d]];
-    return trans ? P[i * nc + o] : P[o * nc + i];
-  };
-  for (int p = threadIdx.x; p < no * ni * ni; p += blockDim.x) {
-    const int o0 = p % no, i1 = (p / no) % ni, i2 = p / (no * ni);
-    T s = 0;
-    for (int i0 = 0; i0 < ni; ++i0) s += M(0, o0, i0) * in[i0 + ni * (i1 + ni * i2)];
-    t1[p] = s;
+  const int ni = RESTRICT ? nf : nc, no = RESTRICT ? nc : nf;
+  const int ni3 = ni * ni * ni, no3 = no * no * no;
+  const int W = a.W;
+  const int64_t nel_out = RESTRICT ? a.nel_c : a.nel_f;
+  const int64_t eb = ((int64_t)blockIdx.x * 4 + wave) * W;  // first output element of the wavefront
+  T* const B = buf[wave];
+  T* const P = Pl[wave];
+  for (int i = lane; i < 2 * nf * nc; i += 64) {
+    const int c = i / (nf * nc);
+    P[i] = a.P[c][i - c * nf * nc];
   }
-  __syncthreads();
-  for (int p = threadIdx.x; p < no * no * ni; p += blockDim.x) {
-    const int o0 = p % no, o1 = (p / no) % no, i2 = p / (no * no);
-    T s = 0;
-    for (int i1 = 0; i1 < ni; ++i1) s += M(1, o1, i1) * t1[o0 + no * (i1 + ni * i2)];
-    t2[p] = s;
-  }
-  __syncthreads();
-  for (int p = threadIdx.x; p < no * no * no; p += blockDim.x) {
-    const int o0 = p % no, o1 = (p / no) % no, o2 = p / (no * no);
-    T s = 0;
-    for (int i2 = 0; i2 < ni; ++i2) s += M(2, o2, i2) * t2[o0 + no * (o1 + no * i2)];
-    out[p] = s;
-  }
-  __syncthreads();
-  (void)nf;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_tr_prolong(TrArgs<T> a, const T* coarse, T* fine, int add) {
-  __shared__ T in[512], t1[512], t2[512], out[512];
-  const int64_t e = blockIdx.x;
-  const int nf = a.nf, nc = a.nc, nf3 = nf * nf * nf, nc3 = nc * nc * nc;
-  int child[3] = {0, 0, 0};
-  int64_t ec = e;
-  if (a.kind == 1) {
-    const int ex = (int)(e % a.Nf[0]), ey = (int)((e / a.Nf[0]) % a.Nf[1]),
-              ez = (int)(e / ((int64_t)a.Nf[0] * a.Nf[1]));
-    child[0] = ex & 1;
-    child[1] = ey & 1;
-    child[2] = ez & 1;
-    const int Cx = a.Nf[0] / 2, Cy = a.Nf[1] / 2;
-    ec = (ex >> 1) + (int64_t)Cx * ((ey >> 1) + (int64_t)Cy * (ez >> 1));
-  }
-  for (int p = threadIdx.x; p < nc3; p += blockDim.x) in[p] = coarse[ec * nc3 + p];
-  __syncthreads();
-  tensor3(a, in, t1, t2, out, nc, nf, child, false);
-  for (int p = threadIdx.x; p < nf3; p += blockDim.x) {
-    const int64_t g = e * nf3 + p;
-    fine[g] = add ? fine[g] + out[p] : out[p];
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_tr_restrict(TrArgs<T> a, const T* fine, T* coarse) {
-  __shared__ T in[512], t1[512], t2[512], out[512];
-  const int64_t ec = blockIdx.x;
-  const int nf = a.nf, nc = a.nc, nf3 = nf * nf * nf, nc3 = nc * nc * nc;
-  T acc[2] = {0, 0};  // nc3 <= 512 -> at most 2 points per thread
-  const int nchild = a.kind == 1 ? 8 : 1;
+  // output element coordinates (h-transfers) with 32-bit arithmetic
+  const int Fx = a.Nf[0], Fy = a.Nf[1];
+  const int Cx = Fx / 2, Cy = Fy / 2;
+  const int nchild = (RESTRICT && a.kind == 1) ? 8 : 1;
+  T acc[kTrOut];
+#pragma unroll
+  for (int j = 0; j < kTrOut; ++j) acc[j] = 0;
+  const int opl = W == 1 ? (no3 + 63) / 64 : 1;  // outputs per lane
   for (int c = 0; c < nchild; ++c) {
-    int child[3] = {0, 0, 0};
-    int64_t ef = ec;
-    if (a.kind == 1) {
-      const int Cx = a.Nf[0] / 2, Cy = a.Nf[1] / 2;
-      const int cx = (int)(ec % Cx), cy = (int)((ec / Cx) % Cy), cz = (int)(ec / ((int64_t)Cx * Cy));
-      child[0] = c & 1;
-      child[1] = (c >> 1) & 1;
-      child[2] = (c >> 2) & 1;
-      ef = (2 * cx + child[0]) + (int64_t)a.Nf[0] * ((2 * cy + child[1]) + (int64_t)a.Nf[1] * (2 * cz + child[2]));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int idx = lane; idx < W * ni3; idx += 64) {
+      const int le = idx / ni3, p = idx - le * ni3;
+      const int64_t eo = eb + le;
+      if (eo >= nel_out) continue;
+      int64_t ei = eo;
+      if (a.kind == 1) {
+        const unsigned u = (unsigned)eo;
+        if (RESTRICT) {  // coarse eo -> child c
+          const unsigned r = u / Cx, cz = r / Cy, cy = r - cz * Cy, cx = u - r * Cx;
+          ei = (2 * cx + (c & 1)) + (int64_t)Fx * ((2 * cy + ((c >> 1) & 1)) + (int64_t)Fy * (2 * cz + (c >> 2)));
+        } else {  // fine eo -> parent
+          const unsigned r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
+          ei = (ex >> 1) + (int64_t)Cx * ((ey >> 1) + (int64_t)Cy * (ez >> 1));
+        }
+      }
+      B[idx] = in[ei * ni3 + p];
     }
-    for (int p = threadIdx.x; p < nf3; p += blockDim.x) in[p] = fine[ef * nf3 + p];
-    __syncthreads();
-    tensor3(a, in, t1, t2, out, nf, nc, child, true);
-    int slot = 0;
-    for (int p = threadIdx.x; p < nc3; p += blockDim.x, ++slot) acc[slot] += out[p];
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = 0; j < opl; ++j) {
+      const int le = W == 1 ? 0 : lane / no3;
+      const int o = W == 1 ? lane + 64 * j : lane - le * no3;
+      const int64_t eo = eb + le;
+      if (le >= W || o >= no3 || eo >= nel_out) continue;
+      // child (matrix) per direction
+      int ch[3] = {0, 0, 0};
+      if (a.kind == 1) {
+        if (RESTRICT) {
+          ch[0] = c & 1;
+          ch[1] = (c >> 1) & 1;
+          ch[2] = c >> 2;
+        } else {
+          const unsigned u = (unsigned)eo, r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
+          ch[0] = ex & 1;
+          ch[1] = ey & 1;
+          ch[2] = ez & 1;
+        }
+      }
+      const int o0 = o % no, o1 = (o / no) % no, o2 = o / (no * no);
+      const T* M0 = P + ch[0] * nf * nc;
+      const T* M1 = P + ch[1] * nf * nc;
+      const T* M2 = P + ch[2] * nf * nc;
+      // M(o, i) = P[o][i] (prolongation, P is nf x nc) or P[i][o] (restriction)
+      T m0[kMaxN];
+      for (int i0 = 0; i0 < ni; ++i0) m0[i0] = RESTRICT ? M0[i0 * nc + o0] : M0[o0 * nc + i0];
+      const T* Bl = B + le * ni3;
+      T s = 0;
+      for (int i2 = 0; i2 < ni; ++i2) {
+        T s1 = 0;
+        for (int i1 = 0; i1 < ni; ++i1) {
+          const T* line = Bl + ni * (i1 + ni * i2);
+          T s0 = 0;
+          for (int i0 = 0; i0 < ni; ++i0) s0 += m0[i0] * line[i0];
+          s1 += (RESTRICT ? M1[i1 * nc + o1] : M1[o1 * nc + i1]) * s0;
+        }
+        s += (RESTRICT ? M2[i2 * nc + o2] : M2[o2 * nc + i2]) * s1;
+      }
+      acc[j] += s;
+    }
   }
-  int slot = 0;
-  for (int p = threadIdx.x; p < nc3; p += blockDim.x, ++slot) coarse[ec * nc3 + p] = acc[slot];
+  for (int j = 0; j < opl; ++j) {
+    const int le = W == 1 ? 0 : lane / no3;
+    const int o = W == 1 ? lane + 64 * j : lane - le * no3;
+    const int64_t eo = eb + le;
+    if (le >= W || o >= no3 || eo >= nel_out) continue;
+    const int64_t g = eo * no3 + o;
+    out[g] = (!RESTRICT && add) ? out[g] + acc[j] : acc[j];
+  }
 }
 
 template <typename T>
-static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double* P0, const double* P1) {
+static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double* P0, const double* P1,
+                         bool restrict_) {
   TrArgs<T> a;
+  {
+    const int ni = restrict_ ? nf : nc, no = restrict_ ? nc : nf;
+    const int ni3 = ni * ni * ni, no3 = no * no * no;
+    int W = std::min(64 / no3, kTrLds / ni3);
+    a.W = W < 1 ? 1 : W;
+  }
   a.nf = nf;
   a.nc = nc;
   a.kind = kind;
@@ -504,12 +537,15 @@ int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const 
                      const double* P1, const void* coarse, void* fine, int add, hipStream_t s) {
   const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
   if (nel_f == 0) return HMG_OK;
+  if (nel_f >= ((int64_t)1 << 31)) return fail(HMG_ERR_UNSUPPORTED, "too many elements for one transfer launch");
   if (prec == HMG_F64) {
-    auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1);
-    hipLaunchKernelGGL(k_tr_prolong<double>, (unsigned)nel_f, 256, 0, s, a, (const double*)coarse, (double*)fine, add);
+    auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1, false);
+    const unsigned g = (unsigned)((nel_f + 4 * a.W - 1) / (4 * a.W));
+    hipLaunchKernelGGL((k_transfer<double, false>), g, 256, 0, s, a, (const double*)coarse, (double*)fine, add);
   } else {
-    auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1);
-    hipLaunchKernelGGL(k_tr_prolong<float>, (unsigned)nel_f, 256, 0, s, a, (const float*)coarse, (float*)fine, add);
+    auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1, false);
+    const unsigned g = (unsigned)((nel_f + 4 * a.W - 1) / (4 * a.W));
+    hipLaunchKernelGGL((k_transfer<float, false>), g, 256, 0, s, a, (const float*)coarse, (float*)fine, add);
   }
   return check_launch("tr_prolong");
 }
@@ -518,12 +554,15 @@ int tr_dg_restrict(int prec, int kind, int nf, int nc, const int Nf[3], const do
   const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
   const int64_t nel_c = kind == 1 ? nel_f / 8 : nel_f;
   if (nel_c == 0) return HMG_OK;
+  if (nel_f >= ((int64_t)1 << 31)) return fail(HMG_ERR_UNSUPPORTED, "too many elements for one transfer launch");
   if (prec == HMG_F64) {
-    auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1);
-    hipLaunchKernelGGL(k_tr_restrict<double>, (unsigned)nel_c, 256, 0, s, a, (const double*)fine, (double*)coarse);
+    auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1, true);
+    const unsigned g = (unsigned)((nel_c + 4 * a.W - 1) / (4 * a.W));
+    hipLaunchKernelGGL((k_transfer<double, true>), g, 256, 0, s, a, (const double*)fine, (double*)coarse, 0);
   } else {
-    auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1);
-    hipLaunchKernelGGL(k_tr_restrict<float>, (unsigned)nel_c, 256, 0, s, a, (const float*)fine, (float*)coarse);
+    auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1, true);
+    const unsigned g = (unsigned)((nel_c + 4 * a.W - 1) / (4 * a.W));
+    hipLaunchKernelGGL((k_transfer<float, true>), g, 256, 0, s, a, (const float*)fine, (float*)coarse, 0);
   }
   return check_launch("tr_restrict");
 }

@@ -108,15 +108,13 @@ template <typename T>
 __device__ __forceinline__ int64_t block_chunk(const OpArgs<T>& a, int b) {
   const int R = a.rowchunks;
   if (R == 0) return b;
-  const int TY = a.tile_y;
-  const int64_t full = (int64_t)R * a.Nz * TY;
-  const int ty = (int)(b / full);
-  const int th = min(TY, a.Ny - ty * TY);
-  const int64_t bp = b - ty * full;
-  const int cx = (int)(bp % R);
-  const int64_t r = bp / R;
-  const int yi = (int)(r % th);
-  const int z = (int)(r / th);
+  // 32-bit: chunk counts are below 2^31 (checked at launch)
+  const unsigned TY = a.tile_y, full = (unsigned)R * a.Nz * TY;
+  const unsigned ty = (unsigned)b / full;
+  const unsigned th = min(TY, a.Ny - ty * TY);
+  const unsigned bp = (unsigned)b - ty * full;
+  const unsigned r = bp / R, cx = bp - r * R;
+  const unsigned z = r / th, yi = r - z * th;
   return cx + (int64_t)R * ((ty * TY + yi) + (int64_t)a.Ny * z);
 }
 
@@ -214,9 +212,9 @@ template <typename T>
 __device__ __forceinline__ ElemInfo elem_info(const OpArgs<T>& a, int64_t e) {
   ElemInfo I;
   I.e = e < a.nel ? e : a.nel - 1;
-  const int ex = (int)(I.e % a.Nx);
-  const int64_t r = I.e / a.Nx;
-  const int ey = (int)(r % a.Ny), ez = (int)(r / a.Ny);
+  // element counts are below 2^31 (checked at level creation): 32-bit division
+  const unsigned ue = (unsigned)I.e, r = ue / (unsigned)a.Nx, uz = r / (unsigned)a.Ny;
+  const int ex = (int)(ue - r * a.Nx), ey = (int)(r - uz * a.Ny), ez = (int)uz;
   I.hb = (ex > 0) | ((ex + 1 < a.Nx) << 1) | ((ey > 0) << 2) | ((ey + 1 < a.Ny) << 3) | ((ez > 0) << 4) |
          ((ez + 1 < a.Nz) << 5);
   // faces of direction d are numbered (pos_d) + (N_d + 1) (pos_a + N_a pos_b)
