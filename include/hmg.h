@@ -258,6 +258,75 @@ int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, dou
  */
 int hmg_rhs_sine(const hmg_level* L, double freq, void* b, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent DG meshes of uneven size and degree, nrhs
+ * vectors each, under one schedule of launches.  The operator of every mesh
+ * is the one of hmg_operator_apply (Sec. 4, eq:MatrixFreeAbstractNotation);
+ * the Chebyshev smoother is Alg. 3 on every mesh with its own lambda_max.
+ *
+ * Packed multi-vectors: one device buffer of total_values values (level
+ * precision, 256-byte aligned) holds, for mesh i, vector r (0 <= r < nrhs)
+ * at offset_i + r * ld_i (hmg_batch_layout; ld_i is the mesh's DoF count
+ * rounded up to 256 bytes, values between n_dofs and ld_i are not read
+ * and are left unchanged).
+ *
+ * The levels stay owned by the caller; they must share the precision, be DG
+ * levels, outlive the batch and be bound before the batch is bound (bind
+ * the batch again after re-binding a level).  Calls on one batch must not
+ * overlap.
+ */
+typedef struct hmg_batch hmg_batch;
+
+/* HMG_ERR_INVALID: NULL levels, count < 1, nrhs outside 1..64, mixed
+ * precision; HMG_ERR_UNSUPPORTED: an FE level or a mesh too large. */
+int hmg_batch_create(const hmg_level* const* levels, int count, int nrhs, hmg_batch** out);
+int hmg_batch_query(const hmg_batch* B, int64_t* total_values, size_t* workspace_bytes);
+int hmg_batch_layout(const hmg_batch* B, int i, int64_t* offset, int64_t* ld);
+/* Uploads the mesh tables into ws (device, 256-byte aligned, at least
+ * workspace_bytes) and selects the default schedule (one launch per
+ * degree group, one workgroup per tile).  Blocks. */
+int hmg_batch_bind(hmg_batch* B, void* dev_workspace, size_t bytes, hipStream_t stream);
+void hmg_batch_destroy(hmg_batch* B);
+
+/*
+ * Schedule.  single = 1: one launch over all meshes (Cartesian meshes only,
+ * else HMG_ERR_UNSUPPORTED); single = 0: one launch per (degree, geometry)
+ * group.  persistent = 1: at most blocks_per_cu workgroups per CU loop over
+ * tiles of chunks_per_tile (1, 2 or 4) workgroup chunks; persistent = 0:
+ * one workgroup per tile, chunks_per_tile must be 1.  Results do not depend
+ * on the schedule.
+ */
+int hmg_batch_set_schedule(hmg_batch* B, int single, int persistent, int chunks_per_tile,
+                           int blocks_per_cu);
+/* Times every candidate schedule of each launch with `reps` applies of u
+ * into v (packed vectors, v is overwritten) on `stream` and keeps the
+ * fastest; *best_ms (may be NULL) receives the time of one batch apply.
+ * Blocks. */
+int hmg_batch_autotune(hmg_batch* B, const void* u, void* v, int reps, hipStream_t stream,
+                       double* best_ms);
+int hmg_batch_schedule(const hmg_batch* B, int* single, int* units);
+/* Launch u of the schedule: nodes per direction n (0 for the single
+ * launch), geometry kind, mesh count, persistent, chunks per tile,
+ * workgroups per CU, grid size and its autotuned time (-1 if not tuned). */
+int hmg_batch_unit_info(const hmg_batch* B, int u, int* n, int* curved, int* meshes, int* persistent,
+                        int* chunks_per_tile, int* blocks_per_cu, unsigned* grid, double* ms);
+
+/* v = A u for every mesh and vector (packed vectors; u and v must not
+ * overlap). */
+int hmg_batch_apply(const hmg_batch* B, const void* u, void* v, hipStream_t stream);
+/* r = b - A u (u and r must not overlap). */
+int hmg_batch_residual(const hmg_batch* B, const void* b, const void* u, void* r, hipStream_t stream);
+/* Chebyshev coefficients (Alg. 3, classical three-term recurrence on
+ * [lo_frac, hi_frac] * lmax[i]) for every mesh i: lmax has count values.
+ * Blocks. */
+int hmg_batch_set_chebyshev(hmg_batch* B, const double* lmax, int degree, double lo_frac, double hi_frac,
+                            hipStream_t stream);
+/* degree Chebyshev steps on every mesh and vector, each one operator
+ * launch fused with the update; x holds the start vector on entry and the
+ * result on exit; tmp is a second packed vector; b, x, tmp must not
+ * overlap. */
+int hmg_batch_chebyshev_smooth(const hmg_batch* B, const void* b, void* x, void* tmp, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

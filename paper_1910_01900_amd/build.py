@@ -28,7 +28,7 @@ DEGREES = range(1, 8)
 def _units():
     """(output object, compile command) for every translation unit."""
     units = []
-    for src in ("setup.cpp", "api.cpp"):
+    for src in ("setup.cpp", "api.cpp", "batch.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         units.append((obj, [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + COMMON +
                       ["-c", os.path.join(CSRC, src), "-o", obj]))
@@ -38,6 +38,8 @@ def _units():
         obj = os.path.join(BUILD, "op_kernels_k%d.o" % k)
         units.append((obj, [HIPCC] + DEVICE + COMMON + ["-DHMG_ONLY_N=%d" % (k + 1), "-c",
                                                          os.path.join(CSRC, "op_kernels.hip"), "-o", obj]))
+    obj = os.path.join(BUILD, "op_fused.o")
+    units.append((obj, [HIPCC] + DEVICE + COMMON + ["-c", os.path.join(CSRC, "op_fused.hip"), "-o", obj]))
     obj = os.path.join(BUILD, "op_dispatch.o")
     units.append((obj, [HIPCC] + DEVICE + COMMON + ["-DHMG_DISPATCH_ONLY", "-c",
                                                      os.path.join(CSRC, "op_kernels.hip"), "-o", obj]))

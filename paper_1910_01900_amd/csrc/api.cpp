@@ -49,16 +49,11 @@ static int to_mesh(const hmg_mesh_desc* d, Mesh& m) {
   return HMG_OK;
 }
 
-static int check_ptr(const void* p, const char* what) {
+int check_ptr(const void* p, const char* what) {
   if (!p) return fail(HMG_ERR_INVALID, std::string(what) + " is NULL");
   if (((uintptr_t)p) & 255) return fail(HMG_ERR_INVALID, std::string(what) + " is not 256-byte aligned");
   return HMG_OK;
 }
-#define TRY(x)             \
-  do {                     \
-    int rc_ = (x);         \
-    if (rc_ < 0) return rc_; \
-  } while (0)
 
 // ------------------------------------------------------------------ dense Cholesky
 // In-place lower Cholesky (row-major), blocked, trailing updates threaded.
@@ -199,7 +194,7 @@ static double tridiag_max_eig(const std::vector<double>& a, const std::vector<do
 }
 
 // Classical Chebyshev iteration coefficients (Saad, Alg. 12.1) on [lo, hi]*lmax.
-static void cheb_coeffs(int ns, double lmax, double lof, double hif, std::vector<double>& sig,
+void cheb_coeffs(int ns, double lmax, double lof, double hif, std::vector<double>& sig,
                         std::vector<double>& th) {
   const double a = lof * lmax, b = hif * lmax;
   const double c = 0.5 * (b + a), delta = 0.5 * (b - a), s1 = c / delta;

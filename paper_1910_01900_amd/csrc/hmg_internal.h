@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -23,6 +24,17 @@ int fail(int code, const std::string& msg);
       return ::hmg::fail(HMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 int check_launch(const char* what);
+// HMG_ERR_INVALID unless p is non-null and 256-byte aligned
+int check_ptr(const void* p, const char* what);
+#define TRY(x)               \
+  do {                       \
+    int rc_ = (x);           \
+    if (rc_ < 0) return rc_; \
+  } while (0)
+// Classical Chebyshev iteration coefficients on [lof, hif] * lmax (step j:
+// x_{j+1} = x_j + sig[j] (x_j - x_{j-1}) + th[j] D^{-1} (b - A x_j); sig[0] = 0).
+void cheb_coeffs(int ns, double lmax, double lof, double hif, std::vector<double>& sig,
+                 std::vector<double>& th);
 
 // ---------------------------------------------------------------- 1-D bases
 // Sec. 2: Lagrange basis on the k+1 GLL nodes of [0,1], Gauss rule with k+1
@@ -154,6 +166,105 @@ constexpr int kMaxRhs = 64;      // vectors per batched launch
 
 // ---------------------------------------------------------------- kernel launchers
 enum OpMode { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2, OP_DOT = 3 };
+
+// Arguments of the operator kernels (one mesh).
+template <typename T>
+struct OpArgs {
+  const T* u;
+  T* out;
+  const T* b;
+  const T* dinv;
+  const T* xold;
+  T sigma, theta;
+  double* partials;
+  const T* metric;
+  const T* face[3];
+  const T* tau;
+  const T* tabs;  // op_tables() in device memory
+  int64_t nel;
+  int Nx, Ny, Nz, bcmask;
+  int rowchunks, tile_y;  // workgroup order: chunks per x-row (0: linear), y-tile height
+  int nrhs;               // vectors applied at once (work item = element x vector)
+  int64_t ld;             // distance between consecutive vectors, in values
+  T h[3];
+};
+
+// The level's constant arguments (vectors unset, one vector, linear order).
+template <typename T>
+inline OpArgs<T> make_args(const hmg_level* L) {
+  OpArgs<T> a;
+  a.u = nullptr;
+  a.out = nullptr;
+  a.b = nullptr;
+  a.dinv = (const T*)L->dinv();
+  a.xold = nullptr;
+  a.sigma = a.theta = 0;
+  a.partials = L->partials();
+  a.metric = (const T*)L->metric();
+  for (int d = 0; d < 3; ++d) a.face[d] = (const T*)L->face(d);
+  a.tau = (const T*)L->tau();
+  a.tabs = (const T*)L->tabs();
+  a.nel = L->n_el;
+  a.Nx = L->mesh.N[0];
+  a.Ny = L->mesh.N[1];
+  a.Nz = L->mesh.N[2];
+  a.bcmask = L->mesh.bcmask();
+  a.rowchunks = 0;
+  a.tile_y = 1;
+  a.nrhs = 1;
+  a.ld = L->n_dofs;
+  for (int d = 0; d < 3; ++d) a.h[d] = (T)L->mesh.h(d);
+  return a;
+}
+
+// Workgroup geometry of the DG operator kernels: 4 wavefronts of
+// 64 / n^2 elements (at least one).
+constexpr int kOpWaves = 4;
+constexpr int op_elems_per_wave(int n) { return 64 / (n * n) >= 1 ? 64 / (n * n) : 1; }
+constexpr int op_elems_per_block(int n) { return kOpWaves * op_elems_per_wave(n); }
+
+// One mesh of a multi-mesh launch (device table entry).  The work of a
+// launch is a list of tiles; a tile is q consecutive workgroup chunks
+// (op_elems_per_block(n) work items each) of one mesh.
+template <typename T>
+struct MeshEntry {
+  OpArgs<T> a;     // the level's arguments; vector pointers unset
+  int64_t off;     // first value of the mesh's block in the packed vectors
+  int64_t tile0;   // first tile of the mesh in its launch
+  int64_t chunks;  // workgroup chunks of the mesh
+  int n;           // nodes per direction
+  int id;          // mesh index in the batch (Chebyshev coefficient row)
+};
+// The host writes the table that the kernels read: the layout must agree in
+// the host and the device compilation.
+static_assert(sizeof(MeshEntry<double>) == 216 && sizeof(MeshEntry<float>) == 200, "MeshEntry layout");
+static_assert(offsetof(MeshEntry<double>, off) == 184 && offsetof(MeshEntry<float>, off) == 168, "MeshEntry layout");
+static_assert(offsetof(OpArgs<double>, ld) == 152 && offsetof(OpArgs<float>, h) == 152, "OpArgs layout");
+
+// One multi-mesh launch: meshes table[0..count) (device memory, vector
+// pointers resolved by multi_resolve), tiles split over the 8 XCDs at
+// xcd[0..8] (device memory), `grid` workgroups (a multiple of 8).
+struct MultiLaunch {
+  const void* table;
+  int count;
+  int q;             // chunks per tile (1 unless persistent)
+  const int64_t* xcd;
+  unsigned grid;
+  bool persist;      // workgroups loop over tiles (else one tile each)
+};
+// Set the vector pointers of table[0..count) for one launch: mesh i works on
+// u + off_i, out + off_i, b + off_i, xold + off_i, and in Chebyshev mode
+// takes sigma, theta = coef[id_i * cstride + 2 step + {0, 1}].
+int multi_resolve(int prec, void* table, int count, const void* u, void* out, const void* b,
+                  const void* xold, const void* coef, int cstride, int step, hipStream_t s);
+// Launch over meshes that share n (nodes per direction), precision and
+// geometry kind; modes OP_APPLY, OP_RESID, OP_CHEB.
+int multi_launch(int n, int prec, bool curved, int mode, const MultiLaunch& m, hipStream_t s);
+// Launch over Cartesian meshes of any degree in one kernel.
+int fused_launch(int prec, int mode, const MultiLaunch& m, hipStream_t s);
+// Resident workgroups per CU of those kernels (0 on error).
+int multi_occupancy(int n, int prec, bool curved, int mode);
+int fused_occupancy(int prec, int mode);
 
 // DG: out = f(A u); FE: cell part into scratch, then node sum with the mode.
 // OP_CHEB: out = u + sigma (u - xold) + theta dinv (b - A u)  (out may alias xold)

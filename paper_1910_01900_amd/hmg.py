@@ -94,6 +94,21 @@ def lib():
             "hmg_pcg_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int,
                                         C.POINTER(SolveStats), _P]),
             "hmg_rhs_sine": (C.c_int, [_P, C.c_double, _P, _P]),
+            "hmg_batch_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_int, C.POINTER(_P)]),
+            "hmg_batch_query": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+            "hmg_batch_layout": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "hmg_batch_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
+            "hmg_batch_destroy": (None, [_P]),
+            "hmg_batch_set_schedule": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int]),
+            "hmg_batch_autotune": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_double)]),
+            "hmg_batch_schedule": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "hmg_batch_unit_info": (C.c_int, [_P, C.c_int] + [C.POINTER(C.c_int)] * 6 +
+                                    [C.POINTER(C.c_uint), C.POINTER(C.c_double)]),
+            "hmg_batch_apply": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_batch_residual": (C.c_int, [_P, _P, _P, _P, _P]),
+            "hmg_batch_set_chebyshev": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.c_double,
+                                                  C.c_double, _P]),
+            "hmg_batch_chebyshev_smooth": (C.c_int, [_P, _P, _P, _P, _P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -284,6 +299,86 @@ class Transfer:
     def __del__(self):
         if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.hmg_transfer_destroy(self._h)
+            self._h = C.c_void_p()
+
+
+class Batch:
+    """Many DG levels (bound Level objects), nrhs vectors each (hmg_batch).
+
+    Vectors are packed: one 1-D tensor of `total` values; vector r of mesh i
+    is view(v, i, r) (offset[i] + r * ld[i], n_dofs[i] values).
+    """
+
+    def __init__(self, levels, nrhs=1, bind=True):
+        self.levels, self.nrhs = list(levels), nrhs
+        self._h = C.c_void_p()
+        arr = (_P * len(self.levels))(*[L._h for L in self.levels])
+        check(lib().hmg_batch_create(arr, len(self.levels), nrhs, C.byref(self._h)))
+        n, ws = C.c_int64(), C.c_size_t()
+        check(lib().hmg_batch_query(self._h, C.byref(n), C.byref(ws)))
+        self.total, self.ws_bytes = n.value, ws.value
+        self.offset, self.ld = [], []
+        for i in range(len(self.levels)):
+            o, l = C.c_int64(), C.c_int64()
+            check(lib().hmg_batch_layout(self._h, i, C.byref(o), C.byref(l)))
+            self.offset.append(o.value)
+            self.ld.append(l.value)
+        self.dtype = self.levels[0].dtype
+        if bind:
+            self.ws = _workspace(ws.value)
+            check(lib().hmg_batch_bind(self._h, ptr(self.ws), ws.value, stream()))
+
+    def vector(self):
+        return _torch().zeros(self.total, dtype=self.dtype, device="cuda")
+
+    def view(self, v, i, r):
+        o = self.offset[i] + r * self.ld[i]
+        return v[o:o + self.levels[i].n_dofs]
+
+    def set_schedule(self, single=False, persistent=False, chunks_per_tile=1, blocks_per_cu=1):
+        check(lib().hmg_batch_set_schedule(self._h, int(single), int(persistent), chunks_per_tile,
+                                           blocks_per_cu))
+
+    def autotune(self, u, v, reps=5):
+        ms = C.c_double()
+        check(lib().hmg_batch_autotune(self._h, ptr(u), ptr(v), reps, stream(), C.byref(ms)))
+        return ms.value
+
+    def schedule(self):
+        single, units = C.c_int(), C.c_int()
+        check(lib().hmg_batch_schedule(self._h, C.byref(single), C.byref(units)))
+        out = []
+        for u in range(units.value):
+            v = [C.c_int() for _ in range(6)]
+            g, ms = C.c_uint(), C.c_double()
+            check(lib().hmg_batch_unit_info(self._h, u, *[C.byref(x) for x in v], C.byref(g), C.byref(ms)))
+            out.append({"n": v[0].value, "curved": v[1].value, "meshes": v[2].value,
+                        "persistent": v[3].value, "chunks_per_tile": v[4].value,
+                        "blocks_per_cu": v[5].value, "grid": g.value, "ms": ms.value})
+        return {"single": bool(single.value), "units": out}
+
+    def apply(self, u, v=None):
+        v = self.vector() if v is None else v
+        check(lib().hmg_batch_apply(self._h, ptr(u), ptr(v), stream()))
+        return v
+
+    def residual(self, b, u, r=None):
+        r = self.vector() if r is None else r
+        check(lib().hmg_batch_residual(self._h, ptr(b), ptr(u), ptr(r), stream()))
+        return r
+
+    def set_chebyshev(self, lmax, degree, lo=0.06, hi=1.2):
+        arr = (C.c_double * len(lmax))(*[float(x) for x in lmax])
+        check(lib().hmg_batch_set_chebyshev(self._h, arr, degree, lo, hi, stream()))
+
+    def chebyshev(self, b, x, tmp=None):
+        tmp = self.vector() if tmp is None else tmp
+        check(lib().hmg_batch_chebyshev_smooth(self._h, ptr(b), ptr(x), ptr(tmp), stream()))
+        return x
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.hmg_batch_destroy(self._h)
             self._h = C.c_void_p()
 
 

@@ -9,6 +9,8 @@ amp * prod_j sin(pi s_j) and use a degree-3 mapping):
   curved_k4_64   curvilinear 64^3, k = 4 (32,768,000 DoFs), amp 0.05
   curved_k7_48   curvilinear 48^3, k = 7 (56,623,104 DoFs), amp 0.05,
                  per-element penalty scale ~ U[1, 10]
+  multi_64       64 Cartesian unit cubes of N_i^3 elements, N_i ~ U{4..24},
+                 degree k_i ~ U{2..7} (stream 4), 4 vectors U[-1,1] each
 """
 import numpy as np
 
@@ -34,3 +36,11 @@ WORKLOADS = {
 def tau_scale(seed_index, n_el):
     """Per-element penalty factors ~ U[1, 10]."""
     return rng(seed_index).uniform(1.0, 10.0, int(n_el))
+
+
+def multi_meshes(count=64, seed_index=4, n_range=(4, 24), k_range=(2, 7)):
+    """(N_i, k_i) of a batch of unit cubes: N_i ~ U{n_range}, k_i ~ U{k_range}."""
+    g = rng(seed_index)
+    N = g.integers(n_range[0], n_range[1] + 1, int(count))
+    k = g.integers(k_range[0], k_range[1] + 1, int(count))
+    return [(int(a), int(b)) for a, b in zip(N, k)]

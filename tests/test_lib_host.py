@@ -154,3 +154,45 @@ def test_batched_apply_arguments_checked_before_launch():
     assert lib.hmg_residual_batched(dg, 3, None, None, None, n, None) == -6
     for h in (dg, fe):
         lib.hmg_level_destroy(h)
+
+
+def test_batch_layout_and_arguments_host():
+    lib = hmg.lib()
+    meshes = [hmg.Mesh((3, 2, 2), 2), hmg.Mesh((2, 2, 1), 5, deformed=True, amp=0.05), hmg.Mesh((1, 1, 1), 1)]
+    hs = [_create(m)[1] for m in meshes]
+    arr = (C.c_void_p * 3)(*hs)
+    b = C.c_void_p()
+    assert lib.hmg_batch_create(arr, 3, 0, C.byref(b)) == -1
+    assert lib.hmg_batch_create(arr, 3, 65, C.byref(b)) == -1
+    assert lib.hmg_batch_create(arr, 0, 2, C.byref(b)) == -1
+    assert lib.hmg_batch_create(None, 3, 2, C.byref(b)) == -1
+    assert lib.hmg_batch_create(arr, 3, 2, C.byref(b)) == 0
+    total, ws = C.c_int64(), C.c_size_t()
+    assert lib.hmg_batch_query(b, C.byref(total), C.byref(ws)) == 0
+    # packed layout: per mesh nrhs vectors of ld values, ld = n_dofs rounded up to 256 bytes
+    expect, off = 0, []
+    for m in meshes:
+        nd = m.n_el * (m.degree + 1) ** 3
+        ld = -(-nd // 32) * 32
+        off.append((expect, ld))
+        expect += 2 * ld
+    assert total.value == expect and ws.value > 0
+    for i, (o, ld) in enumerate(off):
+        oo, ll = C.c_int64(), C.c_int64()
+        assert lib.hmg_batch_layout(b, i, C.byref(oo), C.byref(ll)) == 0
+        assert (oo.value, ll.value) == (o, ld)
+    assert lib.hmg_batch_layout(b, 3, None, None) == -1
+    # unbound levels / batch: workspace errors, no launch
+    assert lib.hmg_batch_bind(b, None, 0, None) == -6
+    assert lib.hmg_batch_apply(b, None, None, None) == -6
+    assert lib.hmg_batch_set_schedule(b, 0, 0, 1, 1) == -6
+    assert lib.hmg_batch_autotune(b, None, None, 3, None, None) == -6
+    lib.hmg_batch_destroy(b)
+    # mixed precision, FE levels, NULL entries
+    _, f32 = _create(meshes[0], prec=hmg.F32)
+    _, fe = _create(meshes[0], space=hmg.FE)
+    for bad, code in (([hs[0], f32], -1), ([hs[0], fe], -2), ([hs[0], None], -1)):
+        a = (C.c_void_p * 2)(*bad)
+        assert lib.hmg_batch_create(a, 2, 1, C.byref(b)) == code
+    for h in hs + [f32, fe]:
+        lib.hmg_level_destroy(h)
