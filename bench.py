@@ -15,8 +15,13 @@ after the timed region and reported beside it.  `roofline.traffic` is read
 from the committed counter summary of the FP64 apply kernel when that
 summary was taken on the current kernel source, else null.
 
+After the timed region, the 64-mesh batch multi_64 (64 Cartesian unit cubes
+with N_i^3 elements, N_i ~ U{4..24}, degree k_i ~ U{2..7}, 4 vectors each)
+is applied under several launch schedules and reported as multi_mesh.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-plain-fp64]
+                       [--no-cpu-baseline] [--no-plain-fp64] [--no-multi]
+                       [--multi-only]
 """
 import argparse
 import hashlib
@@ -115,6 +120,81 @@ def time_applies_batched(L, nrhs, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _event_ms(fn, reps, warm=2):
+    """ms per call of fn() (HIP events on the current stream)."""
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def multi_mesh_bench(prec, nrhs=4, reps=10, cheb_degree=5):
+    """The multi_64 batch (64 Cartesian unit cubes, N ~ U{4..24}, k ~ U{2..7},
+    nrhs vectors each): one batch apply under the default schedule (one
+    launch per degree), the single launch over all meshes, the autotuned
+    schedule, one batched launch per mesh and one launch per mesh and
+    vector; the batched Chebyshev smoother against per-vector smoothing."""
+    import ctypes as C
+    import torch
+    from paper_1910_01900_amd import hmg
+    from paper_1910_01900_amd.inputs import multi_meshes
+    spec = multi_meshes()
+    levels = [hmg.Level(hmg.Mesh((N, N, N), k), prec=prec) for N, k in spec]
+    B = hmg.Batch(levels, nrhs)
+    g = torch.Generator(device="cuda").manual_seed(4)
+    U = B.vector().uniform_(-1, 1, generator=g)
+    V = B.vector()
+    dofs = nrhs * sum(L.n_dofs for L in levels)
+    lib, st = hmg.lib(), hmg.stream()
+    es = U.element_size()
+    out = {"meshes": len(levels), "nrhs": nrhs, "dofs": dofs}
+    B.apply(U, V)
+    out["default_ms"] = _event_ms(lambda: B.apply(U, V), reps)
+    B.set_schedule(single=True)
+    out["single_launch_ms"] = _event_ms(lambda: B.apply(U, V), reps)
+    B.autotune(U, V, reps=3)
+    out["autotuned_ms"] = _event_ms(lambda: B.apply(U, V), reps)
+    out["schedule"] = B.schedule()
+
+    def per_mesh():
+        for i, L in enumerate(levels):
+            o = B.offset[i] * es
+            hmg.check(lib.hmg_operator_apply_batched(L._h, nrhs, C.c_void_p(U.data_ptr() + o),
+                                                     C.c_void_p(V.data_ptr() + o), B.ld[i], st))
+
+    def per_vector():
+        for i, L in enumerate(levels):
+            for r in range(nrhs):
+                L.apply(B.view(U, i, r), B.view(V, i, r))
+    out["per_mesh_batched_ms"] = _event_ms(per_mesh, reps)
+    out["per_vector_ms"] = _event_ms(per_vector, max(2, reps // 2))
+    for key in ("default_ms", "single_launch_ms", "autotuned_ms", "per_mesh_batched_ms", "per_vector_ms"):
+        out[key.replace("_ms", "_dofs_per_s")] = dofs / (out[key] * 1e-3)
+    # Chebyshev(degree) smoothing of every vector: batch vs per-vector calls
+    lmax = [L.lambda_max() for L in levels]
+    B.set_chebyshev(lmax, cheb_degree)
+    X, T = B.vector(), B.vector()
+    out["chebyshev_degree"] = cheb_degree
+    out["chebyshev_batch_ms"] = _event_ms(lambda: B.chebyshev(U, X, T), max(2, reps // 2))
+
+    def cheb_per_vector():
+        for i, L in enumerate(levels):
+            for r in range(nrhs):
+                L.chebyshev(B.view(U, i, r), B.view(X, i, r), cheb_degree, lmax[i])
+    out["chebyshev_per_vector_ms"] = _event_ms(cheb_per_vector, 2, warm=1)
+    del B, U, V, X, T, levels
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, u_host, budget_s=15.0):
     """The oracle's element-wise apply (O(n^6) dense tabulations) on a
     bounded sample of elements of the same mesh, timed on the host."""
@@ -152,6 +232,8 @@ def main():
     ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
     ap.add_argument("--nrhs", type=int, default=8, help="vectors per batched apply (0: skip)")
     ap.add_argument("--graph", action="store_true", help="replay PCG iterations from recorded HIP graphs")
+    ap.add_argument("--no-multi", action="store_true", help="skip the 64-mesh batch (multi_64)")
+    ap.add_argument("--multi-only", action="store_true", help="only time the 64-mesh batch (multi_64)")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
                     help="only time the operator apply (and a 1 GiB copy used to calibrate "
                          "HBM counters); for profiling")
@@ -172,6 +254,14 @@ def main():
     ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
     mesh = hmg.Mesh(tuple(w["nel"]), k, deformed=w["deformed"], amp=w["amp"], tau_scale=ts)
     torch.cuda.set_device(0)
+
+    if a.multi_only:
+        res = {}
+        for name, prec in (("fp64", hmg.F64), ("fp32", hmg.F32)):
+            res[name] = multi_mesh_bench(prec)
+            log("multi_64 %s:" % name, json.dumps(res[name]))
+        print(json.dumps({"workload": "multi_64", **res}), flush=True)
+        return
 
     if a.apply_only:
         prec = hmg.F64 if a.apply_only == "f64" else hmg.F32
@@ -310,6 +400,21 @@ def main():
         out["solve_plain_fp64"] = plain
     if batched is not None:
         out["operator_apply_batched"] = batched
+    if not a.no_multi:
+        del L64
+        torch.cuda.empty_cache()
+        multi = {}
+        for name, prec in (("fp64", hmg.F64), ("fp32", hmg.F32)):
+            multi[name] = multi_mesh_bench(prec)
+            m = multi[name]
+            log("multi_64 %s: %d meshes x %d vectors, %.1f M DoFs: default %.2f ms, single launch %.2f ms, "
+                "autotuned %.2f ms (%.1f GDoF/s), per mesh %.2f ms, per vector %.2f ms; Chebyshev(%d) batch "
+                "%.2f ms vs per vector %.2f ms"
+                % (name, m["meshes"], m["nrhs"], m["dofs"] / 1e6, m["default_ms"], m["single_launch_ms"],
+                   m["autotuned_ms"], m["autotuned_dofs_per_s"] / 1e9, m["per_mesh_batched_ms"],
+                   m["per_vector_ms"], m["chebyshev_degree"], m["chebyshev_batch_ms"],
+                   m["chebyshev_per_vector_ms"]))
+        out["multi_mesh"] = {"workload": "multi_64", **multi}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, u_host)
