@@ -259,6 +259,74 @@ int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, dou
 int hmg_rhs_sine(const hmg_level* L, double freq, void* b, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Learned coarse-grid correction.  A U-Net (3x3x3 convolutions on a G^3
+ * grid, G a multiple of 8; levels G, G/2, G/4, G/8 with 16, 32, 48, 48
+ * channels; 2x2x2 average pooling, nearest upsampling with skip addition;
+ * ReLU except the last layer; about 181k parameters) maps the coarse
+ * residual of a continuous Q1 coarsest level (its nodes placed at the grid
+ * points, input channels: residual / its RMS, free-node mask) to the
+ * correction (times RMS times the scale of hmg_hierarchy_coarse_info).
+ * Convolutions run on the BF16 matrix cores with FP32 accumulation; the
+ * parameters, Adam state and activations are FP32.  Parameters are packed
+ * per layer as w[cout][27][cin] (tap t = (dx+1) + 3 (dy+1) + 9 (dz+1))
+ * followed by b[cout].  Training pairs come from the method's own exact
+ * FP64 coarse solves (hmg_hierarchy_capture, _coarse_solve_batch,
+ * _learned_data).  Inputs in[batch][G^3][2], outputs / targets
+ * [batch][G^3] (FP32, device, 256-byte aligned).
+ */
+typedef struct hmg_net hmg_net;
+/* grid 8..64 (multiple of 8), max_batch 1..4096; weights He-uniform from
+ * SplitMix64(seed) at bind, biases 0. */
+int hmg_net_create(int grid, int max_batch, uint64_t seed, hmg_net** out);
+int hmg_net_query(const hmg_net* N, int64_t* n_params, size_t* workspace_bytes);
+int hmg_net_bind(hmg_net* N, void* dev_workspace, size_t bytes, hipStream_t stream);
+void hmg_net_destroy(hmg_net* N);
+/* Copy the n_params FP32 parameters out of / into the network (device). */
+int hmg_net_get_params(const hmg_net* N, float* dst, hipStream_t stream);
+int hmg_net_set_params(hmg_net* N, const float* src, hipStream_t stream);
+int hmg_net_forward(hmg_net* N, const float* in, float* out, int batch, hipStream_t stream);
+/* Loss (mean over the masked points of (out - target)^2, FP64 device
+ * scalar) and its gradient with respect to every parameter (device, FP32,
+ * packed like the parameters); nothing is updated. */
+int hmg_net_gradient(hmg_net* N, const float* in, const float* target, int batch, float* grad,
+                     double* loss, hipStream_t stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr; *loss
+ * (device, may be NULL) receives the loss before the step. */
+int hmg_net_train_step(hmg_net* N, const float* in, const float* target, int batch, double lr,
+                       double* loss, hipStream_t stream);
+
+enum { HMG_COARSE_EXACT = 0, HMG_COARSE_SMOOTH = 1, HMG_COARSE_LEARNED = 2 };
+/*
+ * Coarsest-level solve of the V-cycle: EXACT (dense FP64 inverse),
+ * SMOOTH (Chebyshev smoothing only, the V-cycle without a coarse solve) or
+ * LEARNED: x = network(b), judged on the GPU by |b - A x| <= accept |b|
+ * (finite), else the exact solve (fallbacks counted, hmg_hierarchy_coarse_stats).
+ * LEARNED needs a continuous Q1 coarsest level whose node grid fits the
+ * network's grid and switches hmg_pcg_solve to flexible CG.
+ */
+int hmg_hierarchy_set_coarse(hmg_hierarchy* H, int mode, hmg_net* net, double accept);
+/* Flexible CG (beta = -(z_{k+1} . A p_k) / (p_k . A p_k)); equal to PCG in
+ * exact arithmetic for a fixed symmetric preconditioner. */
+int hmg_hierarchy_set_flexible(hmg_hierarchy* H, int enable);
+/* Coarse unknowns n, node grid (0 for a DG coarsest level) and the output
+ * scale of the learned correction (1 / mean free diagonal). */
+int hmg_hierarchy_coarse_info(const hmg_hierarchy* H, int64_t* n, int* Mx, int* My, int* Mz, double* scale);
+/* Copy the coarsest right-hand side of every following V-cycle (FP64, n
+ * values each, at most capacity) to buf; capacity 0 stops.  V-cycles run
+ * without recorded graphs while capturing. */
+int hmg_hierarchy_capture(hmg_hierarchy* H, double* buf, int capacity);
+int hmg_hierarchy_captured(const hmg_hierarchy* H, int* count);
+/* E[s] = A_c^{-1} R[s] for count coarse vectors (FP64, n values each). */
+int hmg_hierarchy_coarse_solve_batch(const hmg_hierarchy* H, const double* R, double* E, int count,
+                                     hipStream_t stream);
+/* Network inputs (and targets if target != NULL) of count <= 1024 coarse
+ * vectors R (and exact corrections E) for a grid of `grid` points. */
+int hmg_hierarchy_learned_data(const hmg_hierarchy* H, int grid, const double* R, const double* E, int count,
+                               float* in, float* target, hipStream_t stream);
+/* Number of learned coarse solves replaced by the exact one since bind. Blocks. */
+int hmg_hierarchy_coarse_stats(const hmg_hierarchy* H, int* fallbacks, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many independent DG meshes of uneven size and degree, nrhs
  * vectors each, under one schedule of launches.  The operator of every mesh
  * is the one of hmg_operator_apply (Sec. 4, eq:MatrixFreeAbstractNotation);

@@ -28,12 +28,13 @@ DEGREES = range(1, 8)
 def _units():
     """(output object, compile command) for every translation unit."""
     units = []
-    for src in ("setup.cpp", "api.cpp", "batch.cpp"):
+    for src in ("setup.cpp", "api.cpp", "batch.cpp", "net.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         units.append((obj, [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + COMMON +
                       ["-c", os.path.join(CSRC, src), "-o", obj]))
-    obj = os.path.join(BUILD, "aux_kernels.o")
-    units.append((obj, [HIPCC] + DEVICE + COMMON + ["-c", os.path.join(CSRC, "aux_kernels.hip"), "-o", obj]))
+    for src in ("aux_kernels", "net_kernels"):
+        obj = os.path.join(BUILD, src + ".o")
+        units.append((obj, [HIPCC] + DEVICE + COMMON + ["-c", os.path.join(CSRC, src + ".hip"), "-o", obj]))
     for k in DEGREES:
         obj = os.path.join(BUILD, "op_kernels_k%d.o" % k)
         units.append((obj, [HIPCC] + DEVICE + COMMON + ["-DHMG_ONLY_N=%d" % (k + 1), "-c",

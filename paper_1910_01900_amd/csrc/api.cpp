@@ -5,7 +5,7 @@
 #include <cstring>
 #include <thread>
 
-#include "hmg_internal.h"
+#include "net_internal.h"
 
 namespace hmg {
 
@@ -681,6 +681,18 @@ struct hmg_hierarchy {
   // launch graphs (hmg_hierarchy_set_graph): one PCG iteration and one
   // V-cycle, recorded on a library stream, keyed by the caller's vectors
   bool use_graph = false;
+  // coarsest-level solve: exact (dense inverse), Chebyshev smoothing only, or
+  // the learned correction judged by its coarse residual (exact fallback)
+  int coarse_mode = HMG_COARSE_EXACT;
+  hmg_net* net = nullptr;
+  double accept = 0.0;
+  double c0 = 1.0;   // output scale of the network: 1 / mean free diagonal of the coarse operator
+  double lmax_c = 0.0;
+  bool flexible = false;
+  int64_t net_version = -1;  // network parameters the recorded graphs saw
+  // coarse right-hand sides of eager V-cycles copied to a caller buffer (FP64)
+  double* cap_buf = nullptr;
+  int cap_capacity = 0, cap_count = 0;
   hipStream_t cap = nullptr;
   hipGraphExec_t it_exec = nullptr, vc_exec = nullptr;
   const void *it_x = nullptr, *vc_b = nullptr, *vc_x = nullptr;
@@ -910,6 +922,8 @@ static int coarse_setup(hmg_hierarchy* H, hipStream_t s) {
   return HMG_OK;
 }
 
+static NodeGrid coarse_nodes(const hmg_hierarchy* H);
+
 extern "C" int hmg_hierarchy_bind(hmg_hierarchy* H, void* ws, size_t bytes, hipStream_t s) {
   if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
   if (!ws || (((uintptr_t)ws) & 255)) return fail(HMG_ERR_WORKSPACE, "workspace NULL or misaligned");
@@ -926,7 +940,33 @@ extern "C" int hmg_hierarchy_bind(hmg_hierarchy* H, void* ws, size_t bytes, hipS
   }
   for (size_t l = 0; l + 1 < H->lv.size(); ++l)
     TRY(estimate_lmax(H->lv[l], 20, H->seed + l, &H->lmax[l], s));
+  TRY(estimate_lmax(H->lv.back(), 20, H->seed + H->lv.size(), &H->lmax_c, s));
   TRY(coarse_setup(H, s));
+  {  // network output scale: 1 / mean diagonal over the free coarse unknowns
+    const hmg_level* C = H->coarse64;
+    const NodeGrid ng = coarse_nodes(H);
+    double sd = 0;
+    int64_t nd = 0;
+    for (int64_t i = 0; i < (int64_t)C->diag_h.size(); ++i) {
+      bool fixed = false;
+      if (C->space == HMG_FE) {
+        const int x = (int)(i % ng.Mx), y = (int)((i / ng.Mx) % ng.My), z = (int)(i / ((int64_t)ng.Mx * ng.My));
+        const int m = ng.bcmask;
+        fixed = (x == 0 && !(m & 1)) || (x == ng.Mx - 1 && !(m & 2)) || (y == 0 && !(m & 4)) ||
+                (y == ng.My - 1 && !(m & 8)) || (z == 0 && !(m & 16)) || (z == ng.Mz - 1 && !(m & 32));
+      }
+      if (!fixed) {
+        sd += C->diag_h[i];
+        ++nd;
+      }
+    }
+    H->c0 = nd > 0 && sd > 0 ? nd / sd : 1.0;
+  }
+  {
+    int zero[2] = {0, 0};
+    HMG_HIP(hipMemcpyAsync(H->scal() + 10, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    HMG_HIP(hipStreamSynchronize(s));
+  }
   H->bound = true;
   return HMG_OK;
 }
@@ -958,9 +998,48 @@ extern "C" int hmg_hierarchy_set_lmax(hmg_hierarchy* H, int l, double lmax) {
 }
 
 // Alg. 2 on level l with x^(l) = 0; b(l) holds the right-hand side.
+static NodeGrid coarse_nodes(const hmg_hierarchy* H) {
+  const hmg_level* C = H->lv.back();
+  NodeGrid ng;
+  ng.Mx = C->mesh.N[0] * C->k + 1;
+  ng.My = C->mesh.N[1] * C->k + 1;
+  ng.Mz = C->mesh.N[2] * C->k + 1;
+  ng.bcmask = C->mesh.bcmask();
+  return ng;
+}
+
+// Coarsest level: x(l) from b(l) by the selected coarse solve.
+static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
+  hmg_level* L = H->lv[l];
+  if (H->cap_buf && H->cap_count < H->cap_capacity) {
+    TRY(vec_convert(L->prec, H->b(l), HMG_F64, H->cap_buf + (size_t)H->cap_count * H->nc, H->nc, s));
+    H->cap_count++;
+  }
+  switch (H->coarse_mode) {
+    case HMG_COARSE_SMOOTH:
+      return chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax_c, 0.06, 1.2, 1, s);
+    case HMG_COARSE_LEARNED: {
+      hmg_net* N = H->net;
+      const NodeGrid ng = coarse_nodes(H);
+      TRY(net_pack(L->prec, H->b(l), nullptr, H->nc, 1, ng, N->G, H->c0, net_hsigma(N), net_hin(N), nullptr, s));
+      TRY(net_forward(N, net_hin(N), net_hout(N), 1, s));
+      TRY(net_unpack(L->prec, net_hout(N), ng, N->G, net_hsigma(N), H->c0, H->x(l), s));
+      // judge: |b - A x| against accept |b|, else the exact solve
+      double* gate = H->scal() + 8;
+      TRY(launch_operator(L, OP_RESID, H->x(l), H->r(l), H->b(l), nullptr, 0, 0, nullptr, s));
+      TRY(vec_dot(L->prec, H->r(l), H->r(l), H->nc, H->part(), gate, s));
+      TRY(vec_dot(L->prec, H->b(l), H->b(l), H->nc, H->part(), gate + 1, s));
+      return coarse_gemv_gated(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, gate, H->accept,
+                               (int*)(H->scal() + 10), s);
+    }
+    default:
+      return coarse_gemv(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, s);
+  }
+}
+
 static int vcycle(hmg_hierarchy* H, size_t l, hipStream_t s) {
   hmg_level* L = H->lv[l];
-  if (l + 1 == H->lv.size()) return coarse_gemv(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, s);
+  if (l + 1 == H->lv.size()) return coarse_solve(H, l, s);
   TRY(chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax[l], 0.06, 1.2, 1, s));
   TRY(launch_operator(L, OP_RESID, H->x(l), H->r(l), H->b(l), nullptr, 0, 0, nullptr, s));
   TRY(restrict_(H->tr[l], H->r(l), H->b(l + 1), s));
@@ -1002,6 +1081,19 @@ extern "C" int hmg_hierarchy_set_graph(hmg_hierarchy* H, int enable) {
   return HMG_OK;
 }
 
+// Before a solve or V-cycle with the learned coarse solve: BF16 weights up
+// to date (outside any recording) and recordings made with older
+// parameters dropped.
+static int learned_ready(hmg_hierarchy* H, hipStream_t s) {
+  if (H->coarse_mode != HMG_COARSE_LEARNED) return HMG_OK;
+  TRY(net_prepare(H->net, s));
+  if (H->net->version != H->net_version) {
+    H->drop_graphs();
+    H->net_version = H->net->version;
+  }
+  return HMG_OK;
+}
+
 static int precondition(hmg_hierarchy* H, const double* b, double* x, hipStream_t s) {
   const int pr = H->mg_prec;
   const int64_t n = H->lv[0]->n_dofs;
@@ -1015,7 +1107,8 @@ extern "C" int hmg_vcycle(hmg_hierarchy* H, const double* b, double* x, hipStrea
   TRY(check_ptr(b, "b"));
   TRY(check_ptr(x, "x"));
   if ((const void*)b == (void*)x) return fail(HMG_ERR_INVALID, "b and x must not overlap");
-  if (!H->use_graph) return precondition(H, b, x, s);
+  TRY(learned_ready(H, s));
+  if (!H->use_graph || H->cap_buf) return precondition(H, b, x, s);
   if (!H->vc_exec || H->vc_b != b || H->vc_x != x) {
     TRY(record(H, &H->vc_exec, [&](hipStream_t cs) { return precondition(H, b, x, cs); }));
     H->vc_b = b;
@@ -1042,12 +1135,20 @@ static int pcg_update(hmg_hierarchy* H, double* x, hipStream_t s) {
 
 // A full PCG iteration after the first: z = M^{-1} r (V-cycle), delta =
 // r.z -> sc[1], p = z + (sc[1] / sc[0]) p, then pcg_update.
+// Flexible variant (a preconditioner that changes between iterations, such
+// as the learned coarse correction): beta = z_{k+1}.(r_{k+1} - r_k) /
+// (r_k.z_k) = -(z_{k+1}.A p_k) / (p_k.A p_k), with A p_k still in v.
 static int pcg_iteration(hmg_hierarchy* H, double* x, hipStream_t s) {
   const int64_t n = H->fine64->n_dofs;
-  double *r = H->cg(0), *p = H->cg(1), *z = H->cg(3), *sc = H->scal(), *part = H->part();
+  double *r = H->cg(0), *p = H->cg(1), *v = H->cg(2), *z = H->cg(3), *sc = H->scal(), *part = H->part();
   TRY(precondition(H, r, z, s));
   TRY(vec_dot(HMG_F64, r, z, n, part, sc + 1, s));
-  TRY(cg_update_p(p, z, sc + 1, sc + 0, n, s));
+  if (H->flexible) {
+    TRY(vec_dot(HMG_F64, z, v, n, part, sc + 4, s));
+    TRY(cg_update_p(p, z, sc + 4, sc + 2, n, s, true));
+  } else {
+    TRY(cg_update_p(p, z, sc + 1, sc + 0, n, s));
+  }
   return pcg_update(H, x, s);
 }
 
@@ -1057,6 +1158,7 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   TRY(check_ptr(b, "b"));
   TRY(check_ptr(x, "x"));
   if (maxit < 0) return fail(HMG_ERR_INVALID, "maxit < 0");
+  TRY(learned_ready(H, s));
   const hmg_level* A = H->fine64;
   const int64_t n = A->n_dofs;
   double *r = H->cg(0), *p = H->cg(1), *z = H->cg(3);
@@ -1084,7 +1186,7 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   while (nr / r0 > rtol && nr > atol && it < maxit) {
     if (it == 0) {
       TRY(pcg_update(H, x, s));
-    } else if (H->use_graph) {
+    } else if (H->use_graph && !H->cap_buf) {
       if (!H->it_exec || H->it_x != x) {
         TRY(record(H, &H->it_exec, [&](hipStream_t cs) { return pcg_iteration(H, x, cs); }));
         H->it_x = x;
@@ -1109,4 +1211,98 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   }
   if (nr / r0 > rtol && nr > atol) return finish(HMG_NOT_CONVERGED);
   return finish(HMG_OK);
+}
+
+extern "C" int hmg_hierarchy_set_coarse(hmg_hierarchy* H, int mode, hmg_net* net, double accept) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (mode != HMG_COARSE_EXACT && mode != HMG_COARSE_SMOOTH && mode != HMG_COARSE_LEARNED)
+    return fail(HMG_ERR_INVALID, "unknown coarse mode");
+  if (mode == HMG_COARSE_LEARNED) {
+    if (!net || !net->bound) return fail(HMG_ERR_INVALID, "learned coarse solve needs a bound network");
+    if (H->lv.back()->space != HMG_FE || H->lv.back()->k != 1)
+      return fail(HMG_ERR_UNSUPPORTED, "learned coarse solve needs a continuous Q1 coarsest level");
+    const NodeGrid ng = coarse_nodes(H);
+    if (ng.Mx > net->G || ng.My > net->G || ng.Mz > net->G)
+      return fail(HMG_ERR_UNSUPPORTED, "network grid smaller than the coarse node grid");
+    if (!(accept > 0)) return fail(HMG_ERR_INVALID, "accept must be positive");
+  }
+  H->coarse_mode = mode;
+  H->net = mode == HMG_COARSE_LEARNED ? net : nullptr;
+  H->accept = accept;
+  H->flexible = mode == HMG_COARSE_LEARNED ? true : H->flexible;
+  H->drop_graphs();
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_set_flexible(hmg_hierarchy* H, int enable) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  H->flexible = enable != 0;
+  H->drop_graphs();
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_coarse_info(const hmg_hierarchy* H, int64_t* n, int* Mx, int* My, int* Mz,
+                                         double* scale) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (n) *n = H->nc;
+  const hmg_level* C = H->lv.back();
+  const bool fe = C->space == HMG_FE;
+  if (Mx) *Mx = fe ? C->mesh.N[0] * C->k + 1 : 0;
+  if (My) *My = fe ? C->mesh.N[1] * C->k + 1 : 0;
+  if (Mz) *Mz = fe ? C->mesh.N[2] * C->k + 1 : 0;
+  if (scale) *scale = H->c0;
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_capture(hmg_hierarchy* H, double* buf, int capacity) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (capacity < 0 || (capacity > 0 && !buf)) return fail(HMG_ERR_INVALID, "need a buffer for capacity > 0");
+  if (buf) TRY(check_ptr(buf, "buf"));
+  H->cap_buf = capacity > 0 ? buf : nullptr;
+  H->cap_capacity = capacity;
+  H->cap_count = 0;
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_captured(const hmg_hierarchy* H, int* count) {
+  if (!H || !count) return fail(HMG_ERR_INVALID, "NULL argument");
+  *count = H->cap_count;
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_coarse_solve_batch(const hmg_hierarchy* H, const double* R, double* E, int count,
+                                                hipStream_t s) {
+  if (!H || !H->bound) return fail(HMG_ERR_WORKSPACE, "hierarchy missing or not bound");
+  if (count < 0) return fail(HMG_ERR_INVALID, "count < 0");
+  if (count == 0) return HMG_OK;
+  TRY(check_ptr(R, "R"));
+  TRY(check_ptr(E, "E"));
+  if ((const void*)R == (void*)E) return fail(HMG_ERR_INVALID, "R and E must not overlap");
+  return coarse_gemm(H->ainv(), R, E, (int)H->nc, count, s);
+}
+
+extern "C" int hmg_hierarchy_learned_data(const hmg_hierarchy* H, int grid, const double* R, const double* E,
+                                          int count, float* in, float* target, hipStream_t s) {
+  if (!H || !H->bound) return fail(HMG_ERR_WORKSPACE, "hierarchy missing or not bound");
+  const hmg_level* C = H->lv.back();
+  if (C->space != HMG_FE || C->k != 1) return fail(HMG_ERR_UNSUPPORTED, "needs a continuous Q1 coarsest level");
+  const NodeGrid ng = coarse_nodes(H);
+  if (grid < ng.Mx || grid < ng.My || grid < ng.Mz) return fail(HMG_ERR_INVALID, "grid smaller than the node grid");
+  if (count < 1) return fail(HMG_ERR_INVALID, "count < 1");
+  TRY(check_ptr(R, "R"));
+  TRY(check_ptr(in, "in"));
+  if (target) {
+    TRY(check_ptr(E, "E"));
+  }
+  // per-sample sigma in the caller's input buffer would clash: use the
+  // hierarchy's reduction scratch (count <= kPartials samples per call)
+  if (count > kPartials) return fail(HMG_ERR_INVALID, "at most 1024 samples per call");
+  return net_pack(HMG_F64, R, target ? E : nullptr, H->nc, count, ng, grid, H->c0, H->part(), in, target, s);
+}
+
+extern "C" int hmg_hierarchy_coarse_stats(const hmg_hierarchy* H, int* fallbacks, hipStream_t s) {
+  if (!H || !H->bound || !fallbacks) return fail(HMG_ERR_INVALID, "hierarchy not bound or NULL argument");
+  HMG_HIP(hipMemcpyAsync(fallbacks, H->scal() + 10, sizeof(int), hipMemcpyDeviceToHost, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  return HMG_OK;
 }

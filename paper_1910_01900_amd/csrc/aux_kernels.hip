@@ -95,9 +95,9 @@ __global__ void k_cg_xr(double* x, double* r, const double* p, const double* v, 
   double s = block_reduce(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
-// p = z + (delta_new / delta_old) p
-__global__ void k_cg_p(double* p, const double* z, const double* num, const double* den, int64_t n) {
-  const double beta = *num / *den;
+// p = z + beta p, beta = (+-) *num / *den
+__global__ void k_cg_p(double* p, const double* z, const double* num, const double* den, int64_t n, int neg) {
+  const double beta = (neg ? -*num : *num) / *den;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
 }
@@ -182,8 +182,8 @@ int cg_update_xr(double* x, double* r, const double* p, const double* v, const d
   return (int)g;  // caller reduces g partials
 }
 int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_p, grid_for(n), kBlock, 0, s, p, z, num, den, n);
+                hipStream_t s, bool negate) {
+  hipLaunchKernelGGL(k_cg_p, grid_for(n), kBlock, 0, s, p, z, num, den, n, negate ? 1 : 0);
   return check_launch("cg_p");
 }
 int vec_splitmix(int prec, uint64_t seed, void* x, int64_t n, hipStream_t s) {

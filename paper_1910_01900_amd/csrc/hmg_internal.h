@@ -296,9 +296,9 @@ int reduce_partials(const double* partials, int nparts, double* out, hipStream_t
 // returns the number of partials of r.r written (>0) or an error (<0)
 int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
                  const double* den, int64_t n, double* partials, hipStream_t s, double* save = nullptr);
-// p = z + (*num / *den) p
+// p = z + beta p, beta = *num / *den (negated if `negate`)
 int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
-                hipStream_t s);
+                hipStream_t s, bool negate = false);
 
 // transfers (element-local tensor-product kernels)
 // DG p / h: fine += P coarse, coarse = P^T fine

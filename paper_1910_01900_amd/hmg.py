@@ -94,6 +94,25 @@ def lib():
             "hmg_pcg_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int,
                                         C.POINTER(SolveStats), _P]),
             "hmg_rhs_sine": (C.c_int, [_P, C.c_double, _P, _P]),
+            "hmg_net_create": (C.c_int, [C.c_int, C.c_int, C.c_uint64, C.POINTER(_P)]),
+            "hmg_net_query": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+            "hmg_net_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
+            "hmg_net_destroy": (None, [_P]),
+            "hmg_net_get_params": (C.c_int, [_P, _P, _P]),
+            "hmg_net_set_params": (C.c_int, [_P, _P, _P]),
+            "hmg_net_forward": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+            "hmg_net_gradient": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P]),
+            "hmg_net_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, _P, _P]),
+            "hmg_hierarchy_set_coarse": (C.c_int, [_P, C.c_int, _P, C.c_double]),
+            "hmg_hierarchy_set_flexible": (C.c_int, [_P, C.c_int]),
+            "hmg_hierarchy_coarse_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                                                    C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                                    C.POINTER(C.c_double)]),
+            "hmg_hierarchy_capture": (C.c_int, [_P, _P, C.c_int]),
+            "hmg_hierarchy_captured": (C.c_int, [_P, C.POINTER(C.c_int)]),
+            "hmg_hierarchy_coarse_solve_batch": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+            "hmg_hierarchy_learned_data": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P, _P, _P]),
+            "hmg_hierarchy_coarse_stats": (C.c_int, [_P, C.POINTER(C.c_int), _P]),
             "hmg_batch_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_int, C.POINTER(_P)]),
             "hmg_batch_query": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
             "hmg_batch_layout": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -382,6 +401,56 @@ class Batch:
             self._h = C.c_void_p()
 
 
+COARSE_EXACT, COARSE_SMOOTH, COARSE_LEARNED = 0, 1, 2
+
+
+class Net:
+    """Learned coarse-grid correction network (hmg_net): U-Net on a grid^3 grid."""
+
+    def __init__(self, grid=16, max_batch=64, seed=1):
+        self.grid, self.max_batch = grid, max_batch
+        self._h = C.c_void_p()
+        check(lib().hmg_net_create(grid, max_batch, seed, C.byref(self._h)))
+        n, ws = C.c_int64(), C.c_size_t()
+        check(lib().hmg_net_query(self._h, C.byref(n), C.byref(ws)))
+        self.n_params, self.ws_bytes = n.value, ws.value
+        self.ws = _workspace(ws.value)
+        check(lib().hmg_net_bind(self._h, ptr(self.ws), ws.value, stream()))
+        torch = _torch()
+        self._loss = torch.zeros(32, dtype=torch.float64, device="cuda")
+
+    def params(self):
+        t = _torch().empty(self.n_params, dtype=_torch().float32, device="cuda")
+        check(lib().hmg_net_get_params(self._h, ptr(t), stream()))
+        return t
+
+    def set_params(self, t):
+        check(lib().hmg_net_set_params(self._h, ptr(t.contiguous()), stream()))
+
+    def forward(self, inp):
+        B = inp.shape[0]
+        out = _torch().empty((B,) + tuple(inp.shape[1:-1]), dtype=_torch().float32, device="cuda")
+        check(lib().hmg_net_forward(self._h, ptr(inp), ptr(out), B, stream()))
+        return out
+
+    def gradient(self, inp, target):
+        g = _torch().empty(self.n_params, dtype=_torch().float32, device="cuda")
+        check(lib().hmg_net_gradient(self._h, ptr(inp), ptr(target), inp.shape[0], ptr(g), ptr(self._loss),
+                                     stream()))
+        return float(self._loss[0]), g
+
+    def train_step(self, inp, target, lr):
+        """One Adam step; returns the loss as a device scalar (no sync)."""
+        check(lib().hmg_net_train_step(self._h, ptr(inp), ptr(target), inp.shape[0], lr, ptr(self._loss),
+                                       stream()))
+        return self._loss[0]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.hmg_net_destroy(self._h)
+            self._h = C.c_void_p()
+
+
 class Hierarchy:
     """Hybrid multigrid hierarchy + FP64 PCG (hmg_hierarchy)."""
 
@@ -417,6 +486,54 @@ class Hierarchy:
 
     def set_lmax(self, l, lmax):
         check(lib().hmg_hierarchy_set_lmax(self._h, l, lmax))
+
+    def set_coarse(self, mode, net=None, accept=0.5):
+        """Coarsest-level solve: COARSE_EXACT, COARSE_SMOOTH or COARSE_LEARNED (with net)."""
+        self._net = net
+        check(lib().hmg_hierarchy_set_coarse(self._h, mode, net._h if net is not None else None, accept))
+
+    def set_flexible(self, enable):
+        check(lib().hmg_hierarchy_set_flexible(self._h, 1 if enable else 0))
+
+    def coarse_info(self):
+        n, mx, my, mz, sc = C.c_int64(), C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        check(lib().hmg_hierarchy_coarse_info(self._h, C.byref(n), C.byref(mx), C.byref(my), C.byref(mz),
+                                              C.byref(sc)))
+        return {"n": n.value, "nodes": (mx.value, my.value, mz.value), "scale": sc.value}
+
+    def capture(self, buf):
+        """Copy the coarse right-hand side of following V-cycles into rows of buf [cap, n] (FP64)."""
+        self._cap = buf
+        check(lib().hmg_hierarchy_capture(self._h, ptr(buf) if buf is not None else None,
+                                          0 if buf is None else buf.shape[0]))
+
+    def captured(self):
+        c = C.c_int()
+        check(lib().hmg_hierarchy_captured(self._h, C.byref(c)))
+        return c.value
+
+    def coarse_solve_batch(self, R):
+        E = _torch().empty_like(R)
+        check(lib().hmg_hierarchy_coarse_solve_batch(self._h, ptr(R), ptr(E), R.shape[0], stream()))
+        return E
+
+    def learned_data(self, grid, R, E=None):
+        """Network inputs [count, grid, grid, grid, 2] (and targets) of coarse vectors R (and E)."""
+        torch = _torch()
+        cnt = R.shape[0]
+        inp = torch.empty((cnt, grid, grid, grid, 2), dtype=torch.float32, device="cuda")
+        tgt = torch.empty((cnt, grid, grid, grid), dtype=torch.float32, device="cuda") if E is not None else None
+        for a in range(0, cnt, 1024):
+            b = min(cnt, a + 1024)
+            check(lib().hmg_hierarchy_learned_data(self._h, grid, ptr(R[a:b]), ptr(E[a:b]) if E is not None else None,
+                                                   b - a, ptr(inp[a:b]), ptr(tgt[a:b]) if tgt is not None else None,
+                                                   stream()))
+        return inp, tgt
+
+    def coarse_stats(self):
+        f = C.c_int()
+        check(lib().hmg_hierarchy_coarse_stats(self._h, C.byref(f), stream()))
+        return f.value
 
     def vcycle(self, b, x=None):
         torch = _torch()

@@ -1,0 +1,205 @@
+"""GPU parity of the learned coarse-grid correction: the network's BF16
+matrix-core forward and backward kernels against the FP64 oracle (with the
+same BF16 operand rounding, tightly, and without it, at the BF16 bound), the
+Adam step against its definition, the batched exact coarse solve against
+the oracle's assembled Q1 matrix, and the solver with the learned coarse
+solve: flexible CG converges, needs no more iterations than the V-cycle
+without a coarse solve, and falls back to the exact solve (same iteration
+count) when the network is poisoned."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import meshes
+from oracle import fe as ofe
+from oracle import unet
+from paper_1910_01900_amd import hmg
+from paper_1910_01900_amd.inputs import rng, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _theta(seed):
+    g = rng(seed)
+    return np.concatenate([np.concatenate([g.standard_normal(co * 27 * ci) * np.sqrt(2.0 / (27 * ci)),
+                                           0.1 * g.standard_normal(co)]) for ci, co, _, _ in unet.LAYERS])
+
+
+def _inputs(seed, B, G):
+    g = rng(seed)
+    inp = np.zeros((B, G, G, G, 2))
+    mask = np.zeros((G, G, G))
+    mask[1:G - 3, 1:G - 2, 1:G - 1] = 1.0  # a ragged node block, as for a coarse level smaller than the grid
+    inp[..., 0] = g.standard_normal((B, G, G, G)) * mask
+    inp[..., 1] = mask
+    tgt = g.standard_normal((B, G, G, G)) * mask
+    return inp, tgt
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _net_with(theta, G, B):
+    net = hmg.Net(grid=G, max_batch=B, seed=3)
+    net.set_params(_dev(theta))
+    return net
+
+
+@pytest.mark.parametrize("G,B", [(8, 3), (16, 2)])
+def test_forward_matches_oracle(G, B):
+    print("net forward G=%d B=%d" % (G, B), flush=True)
+    theta = _theta(30)
+    inp, _ = _inputs(31, B, G)
+    # the oracle sees the FP32 parameters the GPU holds
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    net = _net_with(theta, G, B)
+    out = net.forward(_dev(inp)).cpu().numpy().astype(np.float64)
+    ref_bf16, _ = unet.forward(theta32, inp.astype(np.float32).astype(np.float64), bf16=True)
+    ref, _ = unet.forward(theta32, inp)
+    scale = np.abs(ref).max()
+    assert np.abs(out - ref_bf16).max() <= 2e-3 * scale
+    assert np.abs(out - ref).max() <= 3e-2 * scale
+
+
+def test_gradient_matches_oracle():
+    G, B = 8, 3
+    theta = _theta(40)
+    inp, tgt = _inputs(41, B, G)
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    inp32, tgt32 = inp.astype(np.float32).astype(np.float64), tgt.astype(np.float32).astype(np.float64)
+    net = _net_with(theta, G, B)
+    loss, g = net.gradient(_dev(inp), _dev(tgt))
+    g = g.cpu().numpy().astype(np.float64)
+    L_bf, g_bf = unet.backward(theta32, inp32, tgt32, bf16=True)
+    L_64, g_64 = unet.backward(theta32, inp32, tgt32)
+    assert abs(loss - L_bf) <= 1e-3 * L_bf
+    o = 0
+    for ci, co, _, _ in unet.LAYERS:
+        n = co * 27 * ci + co
+        s = slice(o, o + n)
+        e_bf = np.linalg.norm(g[s] - g_bf[s]) / np.linalg.norm(g_bf[s])
+        e_64 = np.linalg.norm(g[s] - g_64[s]) / np.linalg.norm(g_64[s])
+        print("layer %d->%d: rel err vs BF16-emulating oracle %.2e, vs FP64 oracle %.2e" % (ci, co, e_bf, e_64))
+        assert e_bf <= 1e-3, (ci, co, e_bf)
+        # BF16 operands (8-bit significand) in every product: a few percent
+        assert e_64 <= 0.15, (ci, co, e_64)
+        o += n
+
+
+def test_adam_step_matches_definition():
+    G, B = 8, 2
+    theta = _theta(50)
+    inp, tgt = _inputs(51, B, G)
+    net = _net_with(theta, G, B)
+    _, g = net.gradient(_dev(inp), _dev(tgt))
+    net.train_step(_dev(inp), _dev(tgt), 1e-3)
+    after = net.params().cpu().numpy().astype(np.float64)
+    t32 = theta.astype(np.float32).astype(np.float64)
+    ref, _, _ = unet.adam(t32, g.cpu().numpy().astype(np.float64), np.zeros_like(t32), np.zeros_like(t32), 1, 1e-3)
+    np.testing.assert_allclose(after, ref, rtol=1e-5, atol=1e-7)
+
+
+def test_training_reduces_loss():
+    """A fixed linear target (local average of the input) is learned."""
+    G, B = 8, 16
+    inp, _ = _inputs(60, B, G)
+    x = inp[..., 0]
+    tgt = np.zeros_like(x)
+    for d in range(3):
+        tgt += np.roll(x, 1, axis=1 + d) + np.roll(x, -1, axis=1 + d)
+    tgt = (x + tgt / 6.0) * inp[..., 1]
+    net = hmg.Net(grid=G, max_batch=B, seed=7)
+    di, dt = _dev(inp), _dev(tgt)
+    l0 = float(net.train_step(di, dt, 2e-3))
+    for _ in range(150):
+        net.train_step(di, dt, 2e-3)
+    l1, _ = net.gradient(di, dt)
+    print("loss %.4e -> %.4e" % (l0, l1))
+    assert l1 < l0 / 3
+
+
+def _hierarchy(seed_mesh=True):
+    hm, om = meshes((16, 16, 16), 3, True, amp=0.05)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=8, smoother_degree=5, mg_prec=hmg.F32)
+    return H, hm
+
+
+def test_coarse_solve_batch_is_exact():
+    H, _ = _hierarchy()
+    info = H.coarse_info()
+    assert info["nodes"] == (9, 9, 9) and info["n"] == 729 and info["scale"] > 0
+    # the coarsest level: Q1 on the 8^3 mesh with the same deformation
+    _, oc = meshes((8, 8, 8), 1, True, amp=0.05)
+    A = ofe.assemble(oc, 1).toarray()
+    free = ofe.free_mask(oc, 1)
+    R = np.stack([uniform(70 + i, 729) * free for i in range(5)])
+    E = H.coarse_solve_batch(torch.as_tensor(R, device="cuda")).cpu().numpy()
+    for i in range(5):
+        assert np.linalg.norm(R[i] - A @ E[i]) <= 1e-10 * np.linalg.norm(R[i])
+
+
+def _train(H, net, samples=600, steps=300, batch=32, lr=2e-3):
+    n = H.coarse_info()["n"]
+    buf = torch.zeros((samples, n), dtype=torch.float64, device="cuda")
+    H.capture(buf)
+    N = H.n_dofs
+    k = 0
+    while H.captured() < samples:
+        b = torch.as_tensor(uniform(200 + k, N), device="cuda")
+        H.solve(b, rtol=1e-6, maxit=50, allow_not_converged=True)
+        k += 1
+    H.capture(None)
+    E = H.coarse_solve_batch(buf)
+    inp, tgt = H.learned_data(net.grid, buf, E)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    for _ in range(steps):
+        idx = torch.randint(0, samples, (batch,), device="cuda", generator=g)
+        net.train_step(inp[idx].contiguous(), tgt[idx].contiguous(), lr)
+    loss, _ = net.gradient(inp[:batch].contiguous(), tgt[:batch].contiguous())
+    return loss
+
+
+def test_learned_coarse_solve():
+    H, hm = _hierarchy()
+    b = torch.as_tensor(uniform(3, H.n_dofs), device="cuda")
+    _, st_exact = H.solve(b, rtol=1e-10)
+    H.set_coarse(hmg.COARSE_SMOOTH)
+    _, st_smooth = H.solve(b, rtol=1e-10, maxit=200)
+    net = hmg.Net(grid=16, max_batch=32, seed=5)
+    H.set_coarse(hmg.COARSE_EXACT)
+    loss = _train(H, net)
+    H.set_coarse(hmg.COARSE_LEARNED, net, accept=0.5)
+    f0 = H.coarse_stats()
+    x, st = H.solve(b, rtol=1e-10, maxit=200)
+    fb = H.coarse_stats() - f0
+    print("train loss %.3e; iterations exact %d, smoothing only %d, learned %d (%d fallbacks)"
+          % (loss, st_exact["iters"], st_smooth["iters"], st["iters"], fb))
+    assert st["status"] == "HMG_OK" and st["rn"] <= 1e-10 * st["r0"]
+    assert st["iters"] <= st_smooth["iters"]
+    # the final residual, recomputed with the FP64 operator
+    L64 = hmg.Level(hm)
+    r = L64.residual(b, x)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 2e-10
+    # graph replays give the same iterates
+    H.set_graph(True)
+    x2, st2 = H.solve(b, rtol=1e-10, maxit=200)
+    H.set_graph(False)
+    assert st2["iters"] == st["iters"] and torch.equal(x, x2)
+    # poisoned weights: every coarse solve falls back to the exact one
+    bad = torch.full((net.n_params,), float("nan"), dtype=torch.float32, device="cuda")
+    net.set_params(bad)
+    f1 = H.coarse_stats()
+    _, st_bad = H.solve(b, rtol=1e-10, maxit=200)
+    assert H.coarse_stats() - f1 == st_bad["iters"]  # one V-cycle per iteration
+    assert abs(st_bad["iters"] - st_exact["iters"]) <= 1
+
+
+def test_flexible_cg_equals_pcg_with_exact_coarse():
+    H, _ = _hierarchy()
+    b = torch.as_tensor(uniform(4, H.n_dofs), device="cuda")
+    x1, s1 = H.solve(b, rtol=1e-10)
+    H.set_flexible(True)
+    x2, s2 = H.solve(b, rtol=1e-10)
+    assert abs(s1["iters"] - s2["iters"]) <= 1
+    assert float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1)) <= 1e-8
