@@ -195,6 +195,93 @@ def multi_mesh_bench(prec, nrhs=4, reps=10, cheb_degree=5):
     return out
 
 
+def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16):
+    """Learned coarse-grid correction on the curvilinear 48^3 mesh, k = 5
+    (23.9M DoFs), hierarchy cph down to Q1 on 12^3 (2,197 coarse nodes), FP32
+    V-cycle: PCG with the exact coarse solve, with Chebyshev smoothing only
+    on the coarsest level, and flexible CG with the learned correction
+    (judge: coarse residual <= 0.5, else exact).  Training pairs: the coarse
+    right-hand sides of the V-cycles of seeded solves and their exact
+    solves."""
+    import torch
+    from paper_1910_01900_amd import hmg
+    from paper_1910_01900_amd.inputs import uniform
+    mesh = hmg.Mesh((48, 48, 48), 5, deformed=True, amp=0.05)
+    t0 = time.time()
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=12, smoother_degree=5, mg_prec=hmg.F32)
+    info = H.coarse_info()
+    log("learned: hierarchy in %.1f s, coarse nodes %s" % (time.time() - t0, info["nodes"]))
+    N = H.n_dofs
+    b = torch.as_tensor(uniform(3, N), device="cuda")
+
+    def solve_ms(reps=3):
+        x = torch.zeros_like(b)
+        H.solve(b, x, rtol=1e-10, maxit=200)
+        best, st = 1e30, None
+        for _ in range(reps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, st = H.solve(b, x, rtol=1e-10, maxit=200)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return 1e3 * best, st
+
+    def vcycle_ms(reps=10):
+        x = torch.zeros_like(b)
+        return _event_ms(lambda: H.vcycle(b, x), reps)
+
+    out = {"workload": "curved_k5_48", "dofs": N, "coarse_nodes": list(info["nodes"]), "coarse_unknowns": info["n"]}
+    res = {}
+    for name, mode in (("exact", hmg.COARSE_EXACT), ("smooth", hmg.COARSE_SMOOTH)):
+        H.set_coarse(mode)
+        ms, st = solve_ms()
+        res[name] = {"solve_ms": ms, "iterations": st["iters"], "vcycle_ms": vcycle_ms()}
+        log("learned: %s coarse solve: %.1f ms, %d iterations" % (name, ms, st["iters"]))
+    H.set_coarse(hmg.COARSE_EXACT)
+    # training pairs from the method's own V-cycles and exact coarse solves
+    t0 = time.time()
+    R = torch.zeros((samples, info["n"]), dtype=torch.float64, device="cuda")
+    H.capture(R)
+    k = 0
+    while H.captured() < samples:
+        H.solve(torch.as_tensor(uniform(1000 + k, N), device="cuda"), rtol=1e-10, maxit=200)
+        k += 1
+    H.capture(None)
+    E = H.coarse_solve_batch(R)
+    inp, tgt = H.learned_data(grid, R, E)
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    net = hmg.Net(grid=grid, max_batch=batch, seed=1)
+    g = torch.Generator(device="cuda").manual_seed(2)
+    ntrain = samples * 7 // 8
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        idx = torch.randint(0, ntrain, (batch,), device="cuda", generator=g)
+        net.train_step(inp[idx].contiguous(), tgt[idx].contiguous(), lr if i < steps * 3 // 4 else lr / 4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    val, _ = net.gradient(inp[ntrain:ntrain + batch].contiguous(), tgt[ntrain:ntrain + batch].contiguous())
+    one = inp[:1].contiguous()
+    infer = _event_ms(lambda: net.forward(one), 20)
+    H.set_coarse(hmg.COARSE_LEARNED, net, accept=0.5)
+    f0 = H.coarse_stats()
+    ms, st = solve_ms()
+    fb = H.coarse_stats() - f0
+    res["learned"] = {"solve_ms": ms, "iterations": st["iters"], "vcycle_ms": vcycle_ms(),
+                      "fallbacks_in_timed_solves": fb, "solves": 4}
+    log("learned: learned coarse solve: %.1f ms, %d iterations, %d fallbacks over 4 solves"
+        % (ms, st["iters"], fb))
+    out.update(res)
+    out["training"] = {"pairs": samples, "data_s": t_data, "steps": steps, "batch": batch,
+                       "ms_per_step": 1e3 * t_train / steps, "validation_loss": val,
+                       "inference_ms": infer}
+    del H, net, R, E, inp, tgt
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, u_host, budget_s=15.0):
     """The oracle's element-wise apply (O(n^6) dense tabulations) on a
     bounded sample of elements of the same mesh, timed on the host."""
@@ -234,6 +321,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay PCG iterations from recorded HIP graphs")
     ap.add_argument("--no-multi", action="store_true", help="skip the 64-mesh batch (multi_64)")
     ap.add_argument("--multi-only", action="store_true", help="only time the 64-mesh batch (multi_64)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the learned coarse-grid correction on curved_k5_48")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
                     help="only time the operator apply (and a 1 GiB copy used to calibrate "
                          "HBM counters); for profiling")
@@ -254,6 +343,10 @@ def main():
     ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
     mesh = hmg.Mesh(tuple(w["nel"]), k, deformed=w["deformed"], amp=w["amp"], tau_scale=ts)
     torch.cuda.set_device(0)
+
+    if a.learned_only:
+        print(json.dumps(learned_bench()), flush=True)
+        return
 
     if a.multi_only:
         res = {}
