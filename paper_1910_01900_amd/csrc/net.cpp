@@ -11,7 +11,7 @@ using namespace hmg;
 
 namespace {
 
-constexpr int kChunk = 2048;  // points per weight-gradient chunk
+constexpr int kChunk = 16;  // bricks (of 64 points) per weight-gradient chunk
 constexpr int kLossParts = 256;
 
 int pad16(int x) { return (x + 15) / 16 * 16; }
@@ -94,6 +94,7 @@ int wgrad(const hmg_net* N, int li, const float* x, const float* dz, int batch, 
   a.x = x;
   a.dz = dz;
   a.part = N->f(N->off_part);
+  a.bpart = N->f(N->off_bpart);
   a.P = (int)points(N, batch, l.level);
   a.g = N->G >> l.level;
   a.cin = l.cin;
@@ -101,7 +102,7 @@ int wgrad(const hmg_net* N, int li, const float* x, const float* dz, int batch, 
   a.cout_pad = l.cout_pad;
   a.kpad = l.kpad_f;
   a.chunk = kChunk;
-  a.nchunk = (a.P + kChunk - 1) / kChunk;
+  a.nchunk = (int)((net_bricks(batch, a.g) + kChunk - 1) / kChunk);
   return net_wgrad(a, N->f(N->off_g) + l.off_w, N->f(N->off_g) + l.off_b, s);
 }
 
@@ -239,11 +240,12 @@ extern "C" int hmg_net_create(int grid, int max_batch, uint64_t seed, hmg_net** 
   for (auto& l : N->L) {
     l.off_wf = take((size_t)l.cout_pad * l.kpad_f * 2);
     l.off_wt = take((size_t)l.cin_pad * l.kpad_t * 2);
-    const int64_t P = points(N, max_batch, l.level);
-    part = std::max<int64_t>(part, (P + kChunk - 1) / kChunk * l.cout_pad * l.kpad_f);
+    const int64_t nch = (net_bricks(max_batch, N->G >> l.level) + kChunk - 1) / kChunk;
+    part = std::max<int64_t>(part, nch * l.cout_pad * l.kpad_f);
   }
   N->part_floats = part;
   N->off_part = take(part * 4);
+  N->off_bpart = take((size_t)((points(N, max_batch, 0) + 255) / 256) * 48 * 4);
   for (int i = 0; i < NACT; ++i) {
     const size_t bytes = (size_t)points(N, max_batch, kBuf[i].level) * kBuf[i].ch * 4;
     N->off_act[i] = take(bytes);

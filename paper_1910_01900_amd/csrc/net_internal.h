@@ -17,13 +17,20 @@ struct ConvArgs {
   int P, g, cin, cout, cout_pad, kpad;
   int relu, accumulate;  // y = relu(..) ; y += .. instead of y = ..
 };
-// Weight gradient by point chunks: part[c][co][kk] (cout_pad x kpad per chunk).
+// Weight gradient by chunks of 4x4x4-point bricks: part[c][co][kk]
+// (cout_pad x kpad per chunk of `chunk` bricks).
 struct WgradArgs {
   const float* x;   // layer input [P][cin]
   const float* dz;  // gradient of the layer's pre-activation [P][cout]
   float* part;
+  float* bpart;  // bias partials: ceil(P / 256) x cout
   int P, g, cin, cout, cout_pad, kpad, chunk, nchunk;
 };
+// 4x4x4-point bricks of `batch` samples on a g^3 grid
+inline int64_t net_bricks(int64_t batch, int g) {
+  const int64_t nb = (g + 3) / 4;
+  return batch * nb * nb * nb;
+}
 
 int net_conv(const ConvArgs& a, hipStream_t s);
 int net_wgrad(const WgradArgs& a, float* gw, float* gb, hipStream_t s);
@@ -94,7 +101,7 @@ struct hmg_net {
   char* ws = nullptr;
   bool bound = false;
   // workspace offsets (bytes)
-  size_t off_w = 0, off_g = 0, off_m = 0, off_v = 0, off_part = 0, off_lpart = 0, off_loss = 0;
+  size_t off_w = 0, off_g = 0, off_m = 0, off_v = 0, off_part = 0, off_bpart = 0, off_lpart = 0, off_loss = 0;
   size_t off_act[16] = {}, off_grad[16] = {};
   size_t off_hin = 0, off_hout = 0, off_hsig = 0;
   int64_t part_floats = 0;

@@ -19,98 +19,184 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// Neighbour of point p (index inside one sample's g^3 grid, x fastest) at
-// tap t = (dx+1) + 3 (dy+1) + 9 (dz+1); -1 outside the grid.
-__device__ __forceinline__ int tap_point(int p, int t, int g) {
-  const int x = p % g, y = (p / g) % g, z = p / (g * g);
-  const int xx = x + t % 3 - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
-  if (xx < 0 || yy < 0 || zz < 0 || xx >= g || yy >= g || zz >= g) return -1;
-  return xx + g * (yy + g * zz);
-}
-
-// Column kk = t cin + ci of the implicit im2col matrix at point P (global
-// index b g^3 + p): x[neighbour][ci], 0 outside the grid or past K.
-__device__ __forceinline__ float im2col(const float* x, int P, int kk, int K, int cin, int g) {
-  if (kk >= K) return 0.f;
-  const int t = kk / cin, ci = kk - t * cin;
-  const int g3 = g * g * g, b = P / g3, p = P - b * g3;
-  const int q = tap_point(p, t, g);
-  return q < 0 ? 0.f : x[((int64_t)b * g3 + q) * cin + ci];
-}
-
 // ------------------------------------------------------------------ convolution
-// y[P][co] (+)= act(sum_kk im2col(x)[P][kk] w[co][kk] + bias[co]).  One
-// wavefront computes 16 points x 16 output channels; the MFMA operand
-// layout: lane l holds A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16]
-// and D[4 (l / 16) + j][l % 16], j = 0..3.
-__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int ntn = a.cout_pad / 16;
-  const int64_t npt = ((int64_t)a.P + 15) / 16;
-  if (wid >= npt * ntn) return;
-  const int pt = (int)(wid / ntn), nt = (int)(wid - (int64_t)pt * ntn);
-  const int r = lane & 15, kq = 4 * (lane >> 4);
-  const int P = pt * 16 + r;  // this lane's A row
-  const int K = 27 * a.cin;
-  const uint16_t* wrow = a.w + (int64_t)(nt * 16 + r) * a.kpad;  // this lane's B column
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < a.kpad; k0 += 16) {
-    bf16x4 av, bv;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float v = P < a.P ? im2col(a.x, P, k0 + kq + j, K, a.cin, a.g) : 0.f;
-      av[j] = (short)to_bf16(v);
-      bv[j] = (short)wrow[k0 + kq + j];
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-  }
-  const int co = nt * 16 + r;
-  if (co >= a.cout) return;
-  const float bias = a.bias ? a.bias[co] : 0.f;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int Pj = pt * 16 + kq + j;
-    if (Pj >= a.P) continue;
-    float v = acc[j] + bias;
-    if (a.relu) v = v > 0.f ? v : 0.f;
-    float* dst = a.y + (int64_t)Pj * a.cout + co;
-    *dst = a.accumulate ? *dst + v : v;
+// Work is split into bricks of 4x4x4 points of one sample.  A workgroup
+// stages its brick's 6x6x6 input halo (zero outside the grid) in LDS as
+// BF16, so the 27 taps are LDS reads without bounds checks; wavefront w
+// takes the 16 points of brick layer z = w.
+constexpr int kHalo = 216;     // 6^3 halo points
+constexpr int kMaxCin = 64;    // channels a halo holds
+
+struct Brick {
+  int b, x0, y0, z0;
+};
+__device__ __forceinline__ Brick brick_of(int64_t id, int g) {
+  const int nb = (g + 3) / 4;
+  Brick r;
+  r.x0 = 4 * (int)(id % nb);
+  r.y0 = 4 * (int)((id / nb) % nb);
+  r.z0 = 4 * (int)((id / ((int64_t)nb * nb)) % nb);
+  r.b = (int)(id / ((int64_t)nb * nb * nb));
+  return r;
+}
+
+// halo[h * cp + c] = bf16(x[b][point of halo h][c]), cp = cin rounded up to 4
+__device__ __forceinline__ void stage_halo(const float* x, const Brick& B, int g, int cin, int cp, uint16_t* halo) {
+  const int64_t g3 = (int64_t)g * g * g;
+  for (int i = threadIdx.x; i < kHalo * cp; i += blockDim.x) {
+    const int h = i / cp, c = i - h * cp;
+    const int xx = B.x0 + h % 6 - 1, yy = B.y0 + (h / 6) % 6 - 1, zz = B.z0 + h / 36 - 1;
+    float v = 0.f;
+    if (c < cin && xx >= 0 && yy >= 0 && zz >= 0 && xx < g && yy < g && zz < g)
+      v = x[((int64_t)B.b * g3 + xx + (int64_t)g * (yy + (int64_t)g * zz)) * cin + c];
+    halo[i] = to_bf16(v);
   }
 }
 
-// Weight gradient, split over point chunks: part[c][co][kk] =
-// sum_{P in chunk c} dz[P][co] im2col(x)[P][kk].  MFMA with M = output
-// channels, N = columns kk, inner dimension = points.
-__global__ void __launch_bounds__(256) k_conv_wgrad(WgradArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int ntm = a.cout_pad / 16, ntk = a.kpad / 16;
-  const int64_t per_chunk = (int64_t)ntm * ntk;
-  if (wid >= per_chunk * a.nchunk) return;
-  const int c = (int)(wid / per_chunk);
-  const int rem = (int)(wid - (int64_t)c * per_chunk);
-  const int mt = rem / ntk, kt = rem - mt * ntk;
-  const int r = lane & 15, pq = 4 * (lane >> 4);
-  const int K = 27 * a.cin;
-  const int co_a = mt * 16 + r;  // A row (output channel)
-  const int kk_b = kt * 16 + r;  // B column
-  const int p0 = c * a.chunk, p1 = min(a.P, p0 + a.chunk);
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int pb = p0; pb < p1; pb += 16) {
-    bf16x4 av, bv;
+// halo index of brick-local point (x, y, z) at tap t
+__device__ __forceinline__ int halo_at(int x, int y, int z, int t) {
+  return (z + t / 9) * 36 + (y + (t / 3) % 3) * 6 + (x + t % 3);
+}
+
+// y[P][co] (+)= act(sum_kk im2col(x)[P][kk] w[co][kk] + bias[co]).  MFMA
+// operand layout: lane l holds A[l % 16][4 (l / 16) + j], B[4 (l / 16) +
+// j][l % 16] and D[4 (l / 16) + j][l % 16], j = 0..3; A rows are points,
+// B columns output channels (up to three tiles of 16 per wavefront).
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+  __shared__ __align__(16) uint16_t halo[kHalo * kMaxCin];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const Brick B = brick_of(blockIdx.x, a.g);
+  const int cp = (a.cin + 3) & ~3;
+  stage_halo(a.x, B, a.g, a.cin, cp, halo);
+  __syncthreads();
+  const int r = lane & 15, q = lane >> 4;
+  const int px = r & 3, py = r >> 2, pz = w;  // this lane's A row: brick point (px, py, pz)
+  const int ntn = a.cout_pad / 16;            // 1..3
+  f32x4 acc[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  const uint16_t* w0 = a.w + (int64_t)r * a.kpad;  // B column r of tile 0
+  const int64_t tstride = (int64_t)16 * a.kpad;
+  if ((a.cin & 15) == 0) {
+    // every 16-column step stays inside one tap: 4 channels per lane, one 8-byte read
+    for (int t = 0; t < 27; ++t) {
+      const uint16_t* hp = halo + halo_at(px, py, pz, t) * cp + 4 * q;
+      const int kt = t * a.cin + 4 * q;
+      for (int c0 = 0; c0 < a.cin; c0 += 16) {
+        const bf16x4 av = *(const bf16x4*)(hp + c0);
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+          if (n < ntn) {
+            const bf16x4 bv = *(const bf16x4*)(w0 + n * tstride + kt + c0);
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[n], 0, 0, 0);
+          }
+      }
+    }
+  } else {
+    // few channels (K = 27 cin <= kpad): column kk = t cin + ci element by element
+    const int K = 27 * a.cin;
+    for (int k0 = 0; k0 < a.kpad; k0 += 16) {
+      bf16x4 av;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k0 + 4 * q + j;
+        const int t = kk < K ? kk / a.cin : 0, ci = kk - t * a.cin;
+        av[j] = kk < K ? (short)halo[halo_at(px, py, pz, t) * cp + ci] : (short)0;
+      }
+#pragma unroll
+      for (int n = 0; n < 3; ++n)
+        if (n < ntn) {
+          const bf16x4 bv = *(const bf16x4*)(w0 + n * tstride + k0 + 4 * q);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[n], 0, 0, 0);
+        }
+    }
+  }
+  // D rows 4q + j are brick points (x = (4q+j) & 3, y = (4q+j) >> 2, z = w)
+  const int64_t g3 = (int64_t)a.g * a.g * a.g;
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    if (n >= ntn) break;
+    const int co = n * 16 + r;
+    if (co >= a.cout) continue;
+    const float bias = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int Pj = pb + pq + j;
-      const bool in = Pj < p1;
-      av[j] = (short)to_bf16(in && co_a < a.cout ? a.dz[(int64_t)Pj * a.cout + co_a] : 0.f);
-      bv[j] = (short)to_bf16(in ? im2col(a.x, Pj, kk_b, K, a.cin, a.g) : 0.f);
+      const int row = 4 * q + j;
+      const int xx = B.x0 + (row & 3), yy = B.y0 + (row >> 2), zz = B.z0 + w;
+      if (xx >= a.g || yy >= a.g || zz >= a.g) continue;
+      float v = acc[n][j] + bias;
+      if (a.relu) v = v > 0.f ? v : 0.f;
+      float* dst = a.y + ((int64_t)B.b * g3 + xx + (int64_t)a.g * (yy + (int64_t)a.g * zz)) * a.cout + co;
+      *dst = a.accumulate ? *dst + v : v;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
   }
-  float* dst = a.part + (int64_t)c * a.cout_pad * a.kpad;
+}
+
+// Weight gradient by chunks of bricks: part[c][co][kk] = sum over the
+// points P of chunk c of dz[P][co] im2col(x)[P][kk].  MFMA with M = output
+// channels, N = columns kk, inner dimension = points (one brick layer of 16
+// per step).  A workgroup owns 32 (co, kk) tiles (8 per wavefront) and
+// walks the bricks of its chunk, staging the input halo and dz^T in LDS.
+constexpr int kWgTiles = 8;  // tiles per wavefront
+__global__ void __launch_bounds__(256) k_conv_wgrad(WgradArgs a) {
+  __shared__ __align__(16) uint16_t halo[kHalo * kMaxCin];
+  __shared__ __align__(16) uint16_t dzt[48 * 64];  // [co][brick point]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int ntk = a.kpad / 16, ntiles = (a.cout_pad / 16) * ntk;
+  const int cp = (a.cin + 3) & ~3;
+  const int K = 27 * a.cin;
+  const int tile0 = (blockIdx.x * 4 + w) * kWgTiles;  // this wavefront's first tile
+  f32x4 acc[kWgTiles];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) dst[(int64_t)(mt * 16 + pq + j) * a.kpad + kt * 16 + r] = acc[j];
+  for (int i = 0; i < kWgTiles; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nb = (a.g + 3) / 4;
+  const int64_t nbricks = (int64_t)(a.P / ((int64_t)a.g * a.g * a.g)) * nb * nb * nb;
+  const int64_t b0 = (int64_t)blockIdx.y * a.chunk, b1 = min(nbricks, b0 + a.chunk);
+  const int64_t g3 = (int64_t)a.g * a.g * a.g;
+  for (int64_t bid = b0; bid < b1; ++bid) {
+    const Brick B = brick_of(bid, a.g);
+    __syncthreads();  // the previous brick's LDS reads are done
+    stage_halo(a.x, B, a.g, a.cin, cp, halo);
+    for (int i = threadIdx.x; i < 64 * a.cout; i += blockDim.x) {
+      const int pnt = i / a.cout, co = i - pnt * a.cout;
+      const int xx = B.x0 + (pnt & 3), yy = B.y0 + ((pnt >> 2) & 3), zz = B.z0 + (pnt >> 4);
+      float v = 0.f;
+      if (xx < a.g && yy < a.g && zz < a.g)
+        v = a.dz[((int64_t)B.b * g3 + xx + (int64_t)a.g * (yy + (int64_t)a.g * zz)) * a.cout + co];
+      dzt[co * 64 + pnt] = to_bf16(v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kWgTiles; ++i) {
+      // tile (mt, kt) and this lane's column kk = t cin + ci, recomputed per
+      // brick (cheap) instead of being held in registers
+      const int tile = tile0 + i;
+      if (tile >= ntiles) break;
+      const int mt = tile / ntk, kt = tile - mt * ntk;
+      const int kk = kt * 16 + r;
+      const int tap = kk < K ? kk / a.cin : -1, ci = kk - (kk < K ? tap : 0) * a.cin;
+      const int co = mt * 16 + r;
+      for (int z = 0; z < 4; ++z) {  // 16 points per step: brick layer z
+        bf16x4 av = {0, 0, 0, 0}, bv = {0, 0, 0, 0};
+        if (co < a.cout) av = *(const bf16x4*)(dzt + co * 64 + 16 * z + 4 * q);
+        if (tap >= 0)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int pnt = 4 * q + j;  // point (pnt & 3, pnt >> 2, z) of the brick
+            bv[j] = (short)halo[halo_at(pnt & 3, pnt >> 2, z, tap) * cp + ci];
+          }
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[i], 0, 0, 0);
+      }
+    }
+  }
+  float* dst = a.part + (int64_t)blockIdx.y * a.cout_pad * a.kpad;
+#pragma unroll
+  for (int i = 0; i < kWgTiles; ++i) {
+    const int tile = tile0 + i;
+    if (tile >= ntiles) break;
+    const int mt = tile / ntk, kt = tile - mt * ntk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[(int64_t)(mt * 16 + 4 * q + j) * a.kpad + kt * 16 + r] = acc[i][j];
+  }
 }
 
 // grad_w[co][kk] = sum over chunks (fixed order); grad_b[co] = sum_P dz[P][co].
@@ -123,18 +209,29 @@ __global__ void k_wgrad_reduce(const float* part, int nchunk, int cout, int cout
   for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * cout_pad + co) * kpad + kk];
   gw[i] = s;
 }
-__global__ void k_bias_grad(const float* dz, int P, int cout, float* gb) {
-  __shared__ float red[256];
-  const int co = blockIdx.x;
-  float s = 0.f;
-  for (int p = threadIdx.x; p < P; p += blockDim.x) s += dz[(int64_t)p * cout + co];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+// Bias gradient in two fixed-order stages: part[blk][co] = sum of dz over
+// the 256 points of block blk (tile staged in LDS, coalesced), then
+// gb[co] = sum over blocks.
+__global__ void __launch_bounds__(256) k_bias_part(const float* dz, int P, int cout, float* part) {
+  __shared__ float tile[256 * 48];
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  for (int i = threadIdx.x; i < 256 * cout; i += 256) {
+    const int64_t p = p0 + i / cout;
+    tile[i] = p < P ? dz[p0 * cout + i] : 0.f;
   }
-  if (threadIdx.x == 0) gb[co] = red[0];
+  __syncthreads();
+  if ((int)threadIdx.x < cout) {
+    float s = 0.f;
+    for (int r = 0; r < 256; ++r) s += tile[r * cout + threadIdx.x];
+    part[(int64_t)blockIdx.x * cout + threadIdx.x] = s;
+  }
+}
+__global__ void k_bias_reduce(const float* part, int nb, int cout, float* gb) {
+  const int co = threadIdx.x;
+  if (co >= cout) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * cout + co];
+  gb[co] = s;
 }
 
 // BF16 weight matrices from the FP32 parameters w[co][t][ci]:
@@ -232,17 +329,25 @@ __global__ void k_copy_f(const float* x, float* y, int64_t n) {
 // Masked mean squared error over B samples of g^3 points, averaged over
 // the points whose input mask (channel 1) is set: loss partials and
 // d loss / d out = 2 mask (out - t) / count.
-__global__ void k_mask_count(const float* in, int64_t n, double* inv_count) {
-  __shared__ double red[1024];
+__global__ void k_mask_count(const float* in, int64_t n, double* part) {
+  __shared__ double red[256];
   double c = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) c += in[2 * i + 1] != 0.f ? 1.0 : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += in[2 * i + 1] != 0.f ? 1.0 : 0.0;
   red[threadIdx.x] = c;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *inv_count = red[0] > 0 ? 1.0 / red[0] : 0.0;
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_inv_count(const double* part, int n, double* inv) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double c = 0.0;
+    for (int i = 0; i < n; ++i) c += part[i];
+    *inv = c > 0 ? 1.0 / c : 0.0;
+  }
 }
 __global__ void k_mse(const float* out, const float* tgt, const float* in, int64_t n, const double* inv_count,
                       float* dout, double* partials) {
@@ -287,17 +392,24 @@ __global__ void k_adam(float* w, const float* gw, float* m, float* v, int64_t n,
 static unsigned blocks(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 int net_conv(const ConvArgs& a, hipStream_t s) {
-  const int64_t waves = ((int64_t)a.P + 15) / 16 * (a.cout_pad / 16);
-  hipLaunchKernelGGL(k_conv, blocks(waves, 4), 256, 0, s, a);
+  if (a.cin > kMaxCin || a.cout_pad > 48) return fail(HMG_ERR_UNSUPPORTED, "convolution: cin <= 64, cout <= 48");
+  const int64_t nb = (a.g + 3) / 4;
+  const int64_t bricks = (int64_t)(a.P / ((int64_t)a.g * a.g * a.g)) * nb * nb * nb;
+  hipLaunchKernelGGL(k_conv, (unsigned)bricks, 256, 0, s, a);
   return check_launch("k_conv");
 }
 int net_wgrad(const WgradArgs& a, float* gw, float* gb, hipStream_t s) {
-  const int64_t waves = (int64_t)(a.cout_pad / 16) * (a.kpad / 16) * a.nchunk;
-  hipLaunchKernelGGL(k_conv_wgrad, blocks(waves, 4), 256, 0, s, a);
+  if (a.cin > kMaxCin || a.cout_pad > 48) return fail(HMG_ERR_UNSUPPORTED, "convolution: cin <= 64, cout <= 48");
+  const int ntiles = (a.cout_pad / 16) * (a.kpad / 16);
+  const int per_wg = 4 * kWgTiles;
+  hipLaunchKernelGGL(k_conv_wgrad, dim3((unsigned)((ntiles + per_wg - 1) / per_wg), (unsigned)a.nchunk), 256, 0, s,
+                     a);
   const int K = 27 * a.cin;
   hipLaunchKernelGGL(k_wgrad_reduce, blocks((int64_t)a.cout * K), 256, 0, s, a.part, a.nchunk, a.cout, a.cout_pad,
                      a.kpad, K, gw);
-  hipLaunchKernelGGL(k_bias_grad, a.cout, 256, 0, s, a.dz, a.P, a.cout, gb);
+  const unsigned nb = (unsigned)((a.P + 255) / 256);
+  hipLaunchKernelGGL(k_bias_part, nb, 256, 0, s, a.dz, a.P, a.cout, a.bpart);
+  hipLaunchKernelGGL(k_bias_reduce, 1, 64, 0, s, a.bpart, (int)nb, a.cout, gb);
   return check_launch("k_conv_wgrad");
 }
 int net_weight_prep(const float* w, int cin, int cout, uint16_t* wf, int cout_pad, int kpad_f, uint16_t* wt,
@@ -335,8 +447,9 @@ int net_copy(const float* x, float* y, int64_t n, hipStream_t s) {
 int net_mse(const float* out, const float* tgt, const float* in, int B, int g3, float* dout, double* partials,
             int nparts, double* loss, hipStream_t s) {
   const int64_t n = (int64_t)B * g3;
-  // partials[nparts] holds 1 / count
-  hipLaunchKernelGGL(k_mask_count, 1, 1024, 0, s, in, n, partials + nparts);
+  // partials[nparts] holds 1 / count (the partials are reused for the loss)
+  hipLaunchKernelGGL(k_mask_count, nparts, 256, 0, s, in, n, partials);
+  hipLaunchKernelGGL(k_inv_count, 1, 64, 0, s, partials, nparts, partials + nparts);
   hipLaunchKernelGGL(k_mse, nparts, 256, 0, s, out, tgt, in, n, (const double*)(partials + nparts), dout, partials);
   hipLaunchKernelGGL(k_sum_partials, 1, 64, 0, s, partials, nparts, loss);
   return check_launch("k_mse");
