@@ -399,46 +399,62 @@ struct TrArgs {
   int W;  // output elements per wavefront
 };
 
-// Wavefront-local transfer kernel: a wavefront takes W output elements
-// (W = min(64 / no^3, kTrLds / ni^3), at least 1), stages each input element
-// in its own LDS slot, and every lane computes whole output values with the
-// factorized sums
-//   out[o0,o1,o2] = sum_i2 M[o2,i2] sum_i1 M[o1,i1] sum_i0 M[o0,i0] in[i0,i1,i2]
-// (x fastest), M = P_child for prolongation and P_child^T for restriction;
-// the h-restriction adds the 8 children in a fixed order.  No workgroup
+// Wavefront-local transfer kernel, sum-factorized: a wavefront takes W
+// output elements (W n-point lines per lane pass fit in 64 lanes), stages
+// each input element in LDS and applies the 1-D matrix M (M = P_child for
+// prolongation, P_child^T for restriction) direction by direction, one
+// line per lane:
+//   T1[o0, i1, i2] = sum_i0 M0[o0, i0] in[i0, i1, i2]
+//   T2[o0, o1, i2] = sum_i1 M1[o1, i1] T1[o0, i1, i2]
+//   out[o0, o1, o2] = sum_i2 M2[o2, i2] T2[o0, o1, i2]   (x fastest)
+// The h-restriction adds the 8 children in a fixed order.  No workgroup
 // barrier: four independent wavefronts per workgroup.
-constexpr int kTrLds = 1024;  // staged input values per wavefront
-constexpr int kTrOut = 8;     // output values per lane (n^3 <= 512)
+constexpr int kTrBuf = 512;  // values per LDS buffer and wavefront (64 lanes x 8)
+
+__device__ __forceinline__ void tr_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T, bool RESTRICT>
 __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* out, int add) {
-  __shared__ T buf[4][kTrLds];
+  __shared__ T buf[4][2][kTrBuf];
   __shared__ T Pl[4][2 * kMaxN * kMaxN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nf = a.nf, nc = a.nc;
   const int ni = RESTRICT ? nf : nc, no = RESTRICT ? nc : nf;
-  const int ni3 = ni * ni * ni, no3 = no * no * no;
+  const int ni2 = ni * ni, ni3 = ni2 * ni, no2 = no * no, no3 = no2 * no;
   const int W = a.W;
   const int64_t nel_out = RESTRICT ? a.nel_c : a.nel_f;
   const int64_t eb = ((int64_t)blockIdx.x * 4 + wave) * W;  // first output element of the wavefront
-  T* const B = buf[wave];
+  T* const B = buf[wave][0];   // input element(s), later T2
+  T* const T1 = buf[wave][1];
   T* const P = Pl[wave];
   for (int i = lane; i < 2 * nf * nc; i += 64) {
     const int c = i / (nf * nc);
     P[i] = a.P[c][i - c * nf * nc];
   }
-  // output element coordinates (h-transfers) with 32-bit arithmetic
   const int Fx = a.Nf[0], Fy = a.Nf[1];
   const int Cx = Fx / 2, Cy = Fy / 2;
   const int nchild = (RESTRICT && a.kind == 1) ? 8 : 1;
-  T acc[kTrOut];
+  // M_d(o, i) of child bit b: P[i][o] (restriction) or P[o][i] (prolongation)
+  auto M = [&](int bit, int o, int i) -> T {
+    const T* Pb = P + bit * nf * nc;
+    return RESTRICT ? Pb[i * nc + o] : Pb[o * nc + i];
+  };
+  // child bits of a fine output element (h-prolongation)
+  auto fine_bits = [&](int64_t eo, int* ch) {
+    const unsigned u = (unsigned)eo, r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
+    ch[0] = ex & 1;
+    ch[1] = ey & 1;
+    ch[2] = ez & 1;
+  };
+  T acc[kMaxN];
 #pragma unroll
-  for (int j = 0; j < kTrOut; ++j) acc[j] = 0;
-  const int opl = W == 1 ? (no3 + 63) / 64 : 1;  // outputs per lane
+  for (int j = 0; j < kMaxN; ++j) acc[j] = 0;
   for (int c = 0; c < nchild; ++c) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    tr_sync();
     for (int idx = lane; idx < W * ni3; idx += 64) {
       const int le = idx / ni3, p = idx - le * ni3;
       const int64_t eo = eb + le;
@@ -456,57 +472,64 @@ __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* o
       }
       B[idx] = in[ei * ni3 + p];
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int j = 0; j < opl; ++j) {
-      const int le = W == 1 ? 0 : lane / no3;
-      const int o = W == 1 ? lane + 64 * j : lane - le * no3;
-      const int64_t eo = eb + le;
-      if (le >= W || o >= no3 || eo >= nel_out) continue;
-      // child (matrix) per direction
-      int ch[3] = {0, 0, 0};
+    tr_sync();
+    int ch[3] = {0, 0, 0};
+    // pass 1, x-lines: lane -> (element le, line i1 + ni i2)
+    if (lane < W * ni2) {
+      const int le = lane / ni2, line = lane - le * ni2;
       if (a.kind == 1) {
-        if (RESTRICT) {
-          ch[0] = c & 1;
-          ch[1] = (c >> 1) & 1;
-          ch[2] = c >> 2;
-        } else {
-          const unsigned u = (unsigned)eo, r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
-          ch[0] = ex & 1;
-          ch[1] = ey & 1;
-          ch[2] = ez & 1;
-        }
+        if (RESTRICT) ch[0] = c & 1;
+        else if (eb + le < nel_out) fine_bits(eb + le, ch);
       }
-      const int o0 = o % no, o1 = (o / no) % no, o2 = o / (no * no);
-      const T* M0 = P + ch[0] * nf * nc;
-      const T* M1 = P + ch[1] * nf * nc;
-      const T* M2 = P + ch[2] * nf * nc;
-      // M(o, i) = P[o][i] (prolongation, P is nf x nc) or P[i][o] (restriction)
-      T m0[kMaxN];
-      for (int i0 = 0; i0 < ni; ++i0) m0[i0] = RESTRICT ? M0[i0 * nc + o0] : M0[o0 * nc + i0];
-      const T* Bl = B + le * ni3;
-      T s = 0;
-      for (int i2 = 0; i2 < ni; ++i2) {
-        T s1 = 0;
-        for (int i1 = 0; i1 < ni; ++i1) {
-          const T* line = Bl + ni * (i1 + ni * i2);
-          T s0 = 0;
-          for (int i0 = 0; i0 < ni; ++i0) s0 += m0[i0] * line[i0];
-          s1 += (RESTRICT ? M1[i1 * nc + o1] : M1[o1 * nc + i1]) * s0;
-        }
-        s += (RESTRICT ? M2[i2 * nc + o2] : M2[o2 * nc + i2]) * s1;
+      T x[kMaxN];
+      for (int i0 = 0; i0 < ni; ++i0) x[i0] = B[le * ni3 + ni * line + i0];
+      for (int o0 = 0; o0 < no; ++o0) {
+        T s = 0;
+        for (int i0 = 0; i0 < ni; ++i0) s += M(ch[0], o0, i0) * x[i0];
+        T1[le * no * ni2 + o0 + no * line] = s;
       }
-      acc[j] += s;
+    }
+    tr_sync();
+    // pass 2, y-lines: lane -> (element le, o0, i2); T2 overwrites the input
+    if (lane < W * no * ni) {
+      const int le = lane / (no * ni), r = lane - le * (no * ni), o0 = r % no, i2 = r / no;
+      if (a.kind == 1) {
+        if (RESTRICT) ch[1] = (c >> 1) & 1;
+        else if (eb + le < nel_out) fine_bits(eb + le, ch);
+      }
+      T x[kMaxN];
+      for (int i1 = 0; i1 < ni; ++i1) x[i1] = T1[le * no * ni2 + o0 + no * (i1 + ni * i2)];
+      for (int o1 = 0; o1 < no; ++o1) {
+        T s = 0;
+        for (int i1 = 0; i1 < ni; ++i1) s += M(ch[1], o1, i1) * x[i1];
+        B[le * no2 * ni + o0 + no * (o1 + no * i2)] = s;
+      }
+    }
+    tr_sync();
+    // pass 3, z-lines: lane -> (element le, o0 + no o1), accumulated over children
+    if (lane < W * no2) {
+      const int le = lane / no2, r = lane - le * no2;
+      if (a.kind == 1) {
+        if (RESTRICT) ch[2] = c >> 2;
+        else if (eb + le < nel_out) fine_bits(eb + le, ch);
+      }
+      T x[kMaxN];
+      for (int i2 = 0; i2 < ni; ++i2) x[i2] = B[le * no2 * ni + r + no2 * i2];
+      for (int o2 = 0; o2 < no; ++o2) {
+        T s = 0;
+        for (int i2 = 0; i2 < ni; ++i2) s += M(ch[2], o2, i2) * x[i2];
+        acc[o2] += s;
+      }
     }
   }
-  for (int j = 0; j < opl; ++j) {
-    const int le = W == 1 ? 0 : lane / no3;
-    const int o = W == 1 ? lane + 64 * j : lane - le * no3;
+  if (lane < W * no2) {
+    const int le = lane / no2, r = lane - le * no2;
     const int64_t eo = eb + le;
-    if (le >= W || o >= no3 || eo >= nel_out) continue;
-    const int64_t g = eo * no3 + o;
-    out[g] = (!RESTRICT && add) ? out[g] + acc[j] : acc[j];
+    if (eo < nel_out)
+      for (int o2 = 0; o2 < no; ++o2) {
+        const int64_t g = eo * no3 + r + (int64_t)no2 * o2;
+        out[g] = (!RESTRICT && add) ? out[g] + acc[o2] : acc[o2];
+      }
   }
 }
 
@@ -515,9 +538,10 @@ static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double
                          bool restrict_) {
   TrArgs<T> a;
   {
+    // W elements: every pass's lines (ni^2, no ni, no^2 per element) fit in 64 lanes
     const int ni = restrict_ ? nf : nc, no = restrict_ ? nc : nf;
-    const int ni3 = ni * ni * ni, no3 = no * no * no;
-    int W = std::min(64 / no3, kTrLds / ni3);
+    const int lines = std::max(ni * ni, std::max(no * ni, no * no));
+    const int W = 64 / lines;
     a.W = W < 1 ? 1 : W;
   }
   a.nf = nf;
