@@ -59,7 +59,17 @@ def apply_bytes(nel, k, prec_bytes, curved):
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "op_kernel_curved_k4_64_f64_pmc.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1910_01900_amd", "csrc", "op_kernels.hip")
+# the sources the FP64 apply kernel is compiled from (hashed together)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_01900_amd", "csrc", f)
+                  for f in ("op_body.h", "op_kernels.hip", "hmg_internal.h")]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
@@ -73,9 +83,7 @@ def measured_traffic(workload):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    with open(KERNEL_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])

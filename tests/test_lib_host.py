@@ -196,3 +196,34 @@ def test_batch_layout_and_arguments_host():
         assert lib.hmg_batch_create(a, 2, 1, C.byref(b)) == code
     for h in hs + [f32, fe]:
         lib.hmg_level_destroy(h)
+
+
+def test_network_and_coarse_mode_arguments_host():
+    lib = hmg.lib()
+    n = C.c_void_p()
+    assert lib.hmg_net_create(12, 4, 1, C.byref(n)) == -1  # grid must be a multiple of 8
+    assert lib.hmg_net_create(16, 0, 1, C.byref(n)) == -1
+    assert lib.hmg_net_create(16, 4, 1, C.byref(n)) == 0
+    npar, ws = C.c_int64(), C.c_size_t()
+    assert lib.hmg_net_query(n, C.byref(npar), C.byref(ws)) == 0
+    assert npar.value == 181217 and ws.value > 0
+    # unbound network: workspace errors, no launch
+    assert lib.hmg_net_bind(n, None, 0, None) == -6
+    assert lib.hmg_net_forward(n, None, None, 1, None) == -6
+    assert lib.hmg_net_train_step(n, None, None, 1, 1e-3, None, None) == -6
+    # hierarchy coarse modes: unknown mode, learned without a bound network
+    H = C.c_void_p()
+    d = hmg.Mesh((4, 4, 4), 2).desc()
+    assert lib.hmg_hierarchy_create(C.byref(d), b"cph", 1, 2, 3, hmg.F64, 1, C.byref(H)) == 0
+    assert lib.hmg_hierarchy_set_coarse(H, 7, None, 0.5) == -1
+    assert lib.hmg_hierarchy_set_coarse(H, hmg.COARSE_LEARNED, None, 0.5) == -1
+    assert lib.hmg_hierarchy_set_coarse(H, hmg.COARSE_LEARNED, n, 0.5) == -1  # not bound
+    assert lib.hmg_hierarchy_set_coarse(H, hmg.COARSE_SMOOTH, None, 0.0) == 0
+    assert lib.hmg_hierarchy_capture(H, None, 5) == -1
+    assert lib.hmg_hierarchy_capture(H, None, 0) == 0
+    nc, mx, my, mz, sc = C.c_int64(), C.c_int(), C.c_int(), C.c_int(), C.c_double()
+    assert lib.hmg_hierarchy_coarse_info(H, C.byref(nc), C.byref(mx), C.byref(my), C.byref(mz), C.byref(sc)) == 0
+    assert (mx.value, my.value, mz.value) == (3, 3, 3) and nc.value == 27  # Q1 on 2^3
+    assert lib.hmg_hierarchy_coarse_solve_batch(H, None, None, 1, None) == -6  # not bound
+    lib.hmg_hierarchy_destroy(H)
+    lib.hmg_net_destroy(n)
