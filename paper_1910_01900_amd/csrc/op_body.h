@@ -58,6 +58,30 @@ struct Cfg {
   static constexpr int WPE = N >= 7 ? 2 : 3;  // per-wavefront copy of S, Sp, M, l'(0), l'(1)
 };
 
+// Whether the epilogue of MODE reads the input vector again (Chebyshev
+// update, u.(A u)) and the wavefront keeps its own input values in LDS
+// instead of reading them from memory a second time: only where the extra
+// LDS does not lower residency (workgroups per CU from 160 KB of LDS,
+// against the register limit: WPE for the FP64 curvilinear kernels, about
+// five otherwise).
+template <int N, typename T, bool CURVED, bool FE, int MODE>
+constexpr bool keeps_input() {
+  if (FE || (MODE != OP_CHEB && MODE != OP_DOT)) return false;
+  using C = Cfg<N, CURVED, FE>;
+  constexpr int base = C::WAVES * (C::EW * C::PER + C::LT) * (int)sizeof(T);
+  constexpr int extra = C::WAVES * C::EW * C::N3 * (int)sizeof(T);
+  constexpr int vgpr_blocks = (CURVED && sizeof(T) == 8) ? C::WPE : 5;
+  constexpr int b0 = 163840 / base, b1 = 163840 / (base + extra);
+  return (b1 < vgpr_blocks ? b1 : vgpr_blocks) == (b0 < vgpr_blocks ? b0 : vgpr_blocks);
+}
+// LDS values of one wavefront: EW elements of PER, the lane tables, and the
+// kept input values.
+template <int N, typename T, bool CURVED, bool FE, int MODE>
+constexpr int op_wave_lds() {
+  using C = Cfg<N, CURVED, FE>;
+  return C::EW * C::PER + C::LT + (keeps_input<N, T, CURVED, FE, MODE>() ? C::EW * C::N3 : 0);
+}
+
 // ------------------------------------------------------------------ helpers
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
@@ -570,7 +594,9 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   if constexpr (!FE) {
     for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3;
-      W0[li * PER + (idx - li * N3)] = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
+      const T v = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
+      W0[li * PER + (idx - li * N3)] = v;
+      if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = v;
     }
   } else {
     // continuous FE levels take one vector; element and node indices fit
@@ -801,11 +827,14 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     } else if constexpr (MODE == OP_RESID) {
       a.out[g] = a.b[g] - val;
     } else if constexpr (MODE == OP_CHEB) {
-      const T x = a.u[g];
+      T x;
+      if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) x = LT[C::LT + idx];  // kept in LDS
+      else x = a.u[g];
       a.out[g] = x + a.sigma * (x - a.xold[g]) + a.theta * a.dinv[gv] * (a.b[g] - val);
     } else {
       a.out[g] = val;
-      acc += (double)a.u[g] * (double)val;
+      if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) acc += (double)LT[C::LT + idx] * (double)val;
+      else acc += (double)a.u[g] * (double)val;
     }
   }
   if constexpr (!FE && MODE == OP_DOT)

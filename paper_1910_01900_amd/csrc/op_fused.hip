@@ -8,9 +8,10 @@
 namespace hmg {
 
 template <int N>
-constexpr int fused_wave_lds() {
-  using C = Cfg<N, false, false>;
-  return C::EW * C::PER + C::LT;
+constexpr int fused_wave_lds() {  // the largest of the modes and precisions (in values)
+  return op_wave_lds<N, float, false, false, OP_CHEB>() > op_wave_lds<N, double, false, false, OP_CHEB>()
+             ? op_wave_lds<N, float, false, false, OP_CHEB>()
+             : op_wave_lds<N, double, false, false, OP_CHEB>();
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kFusedWave =

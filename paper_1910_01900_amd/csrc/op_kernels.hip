@@ -12,9 +12,10 @@ template <int N, typename T, bool CURVED, bool FE, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<N, CURVED, FE>::WPE)))
 op_kernel(const OpArgs<T> a) {
   using C = Cfg<N, CURVED, FE>;
-  __shared__ T smem[C::WAVES * (C::EW * C::PER + C::LT)];
+  constexpr int WL = op_wave_lds<N, T, CURVED, FE, MODE>();
+  __shared__ T smem[C::WAVES * WL];
   const int wave = threadIdx.x >> 6;
-  T* const W0 = smem + wave * (C::EW * C::PER + C::LT);  // this wavefront's LDS
+  T* const W0 = smem + wave * WL;  // this wavefront's LDS
   const int64_t it0 = block_chunk(a, xcd_block()) * C::EB + (int64_t)wave * C::EW;  // first item of the wave
   load_lane_tables<T, C::LT>(a.tabs, W0 + C::EW * C::PER);
   const double acc = op_items<N, T, CURVED, FE, MODE>(a, it0, W0);
@@ -39,9 +40,10 @@ template <int N, typename T, bool CURVED, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<N, CURVED, false>::WPE)))
 op_multi_kernel(const MultiArgs<T> m) {
   using C = Cfg<N, CURVED, false>;
-  __shared__ T smem[C::WAVES * (C::EW * C::PER + C::LT)];
+  constexpr int WL = op_wave_lds<N, T, CURVED, false, MODE>();
+  __shared__ T smem[C::WAVES * WL];
   const int wave = threadIdx.x >> 6;
-  T* const W0 = smem + wave * (C::EW * C::PER + C::LT);
+  T* const W0 = smem + wave * WL;
   const cptr<MeshEntry<T>> tab = (cptr<MeshEntry<T>>)(uintptr_t)m.table;
   const cptr<int64_t> xcd = (cptr<int64_t>)(uintptr_t)m.xcd;
   const int x = blockIdx.x & 7;
