@@ -399,17 +399,17 @@ struct TrArgs {
   int W;  // output elements per wavefront
 };
 
-// Wavefront-local transfer kernel, sum-factorized: a wavefront takes W
-// output elements (W n-point lines per lane pass fit in 64 lanes), stages
-// each input element in LDS and applies the 1-D matrix M (M = P_child for
+// Wavefront-local transfer kernel, sum-factorized: a wavefront stages W
+// input elements in LDS and applies the 1-D matrix M (M = P_child for
 // prolongation, P_child^T for restriction) direction by direction, one
-// line per lane:
+// n-point line per lane and pass (lanes loop when a pass has more lines):
 //   T1[o0, i1, i2] = sum_i0 M0[o0, i0] in[i0, i1, i2]
 //   T2[o0, o1, i2] = sum_i1 M1[o1, i1] T1[o0, i1, i2]
 //   out[o0, o1, o2] = sum_i2 M2[o2, i2] T2[o0, o1, i2]   (x fastest)
-// The h-restriction adds the 8 children in a fixed order.  No workgroup
-// barrier: four independent wavefronts per workgroup.
-constexpr int kTrBuf = 512;  // values per LDS buffer and wavefront (64 lanes x 8)
+// W fills the LDS buffers (kTrBytes per buffer); the h-restriction adds the
+// 8 children in a fixed order in registers (one output line per lane).  No
+// workgroup barrier: four independent wavefronts per workgroup.
+constexpr int kTrBytes = 4096;  // bytes per LDS buffer and wavefront
 
 __device__ __forceinline__ void tr_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -419,7 +419,8 @@ __device__ __forceinline__ void tr_sync() {
 
 template <typename T, bool RESTRICT>
 __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* out, int add) {
-  __shared__ T buf[4][2][kTrBuf];
+  constexpr int BUF = kTrBytes / (int)sizeof(T);
+  __shared__ T buf[4][2][BUF];
   __shared__ T Pl[4][2 * kMaxN * kMaxN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nf = a.nf, nc = a.nc;
@@ -428,7 +429,7 @@ __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* o
   const int W = a.W;
   const int64_t nel_out = RESTRICT ? a.nel_c : a.nel_f;
   const int64_t eb = ((int64_t)blockIdx.x * 4 + wave) * W;  // first output element of the wavefront
-  T* const B = buf[wave][0];   // input element(s), later T2
+  T* const B = buf[wave][0];   // input elements, later T2
   T* const T1 = buf[wave][1];
   T* const P = Pl[wave];
   for (int i = lane; i < 2 * nf * nc; i += 64) {
@@ -437,20 +438,23 @@ __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* o
   }
   const int Fx = a.Nf[0], Fy = a.Nf[1];
   const int Cx = Fx / 2, Cy = Fy / 2;
-  const int nchild = (RESTRICT && a.kind == 1) ? 8 : 1;
+  const bool hres = RESTRICT && a.kind == 1;
+  const int nchild = hres ? 8 : 1;
   // M_d(o, i) of child bit b: P[i][o] (restriction) or P[o][i] (prolongation)
   auto M = [&](int bit, int o, int i) -> T {
     const T* Pb = P + bit * nf * nc;
     return RESTRICT ? Pb[i * nc + o] : Pb[o * nc + i];
   };
-  // child bits of a fine output element (h-prolongation)
-  auto fine_bits = [&](int64_t eo, int* ch) {
+  // child bit of direction d for output element le (h-transfers)
+  auto bit = [&](int d, int c, int le) -> int {
+    if (a.kind != 1) return 0;
+    if (RESTRICT) return d == 0 ? (c & 1) : (d == 1 ? ((c >> 1) & 1) : (c >> 2));
+    const int64_t eo = eb + le;
+    if (eo >= nel_out) return 0;
     const unsigned u = (unsigned)eo, r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
-    ch[0] = ex & 1;
-    ch[1] = ey & 1;
-    ch[2] = ez & 1;
+    return d == 0 ? (ex & 1) : (d == 1 ? (ey & 1) : (ez & 1));
   };
-  T acc[kMaxN];
+  T acc[kMaxN];  // h-restriction: this lane's output line, summed over the children
 #pragma unroll
   for (int j = 0; j < kMaxN; ++j) acc[j] = 0;
   for (int c = 0; c < nchild; ++c) {
@@ -473,63 +477,56 @@ __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* o
       B[idx] = in[ei * ni3 + p];
     }
     tr_sync();
-    int ch[3] = {0, 0, 0};
-    // pass 1, x-lines: lane -> (element le, line i1 + ni i2)
-    if (lane < W * ni2) {
-      const int le = lane / ni2, line = lane - le * ni2;
-      if (a.kind == 1) {
-        if (RESTRICT) ch[0] = c & 1;
-        else if (eb + le < nel_out) fine_bits(eb + le, ch);
-      }
+    // pass 1, x-lines: (element le, line i1 + ni i2)
+    for (int ln = lane; ln < W * ni2; ln += 64) {
+      const int le = ln / ni2, line = ln - le * ni2;
+      const int b0 = bit(0, c, le);
       T x[kMaxN];
       for (int i0 = 0; i0 < ni; ++i0) x[i0] = B[le * ni3 + ni * line + i0];
       for (int o0 = 0; o0 < no; ++o0) {
         T s = 0;
-        for (int i0 = 0; i0 < ni; ++i0) s += M(ch[0], o0, i0) * x[i0];
+        for (int i0 = 0; i0 < ni; ++i0) s += M(b0, o0, i0) * x[i0];
         T1[le * no * ni2 + o0 + no * line] = s;
       }
     }
     tr_sync();
-    // pass 2, y-lines: lane -> (element le, o0, i2); T2 overwrites the input
-    if (lane < W * no * ni) {
-      const int le = lane / (no * ni), r = lane - le * (no * ni), o0 = r % no, i2 = r / no;
-      if (a.kind == 1) {
-        if (RESTRICT) ch[1] = (c >> 1) & 1;
-        else if (eb + le < nel_out) fine_bits(eb + le, ch);
-      }
+    // pass 2, y-lines: (element le, o0, i2); T2 overwrites the input
+    for (int ln = lane; ln < W * no * ni; ln += 64) {
+      const int le = ln / (no * ni), r = ln - le * (no * ni), o0 = r % no, i2 = r / no;
+      const int b1 = bit(1, c, le);
       T x[kMaxN];
       for (int i1 = 0; i1 < ni; ++i1) x[i1] = T1[le * no * ni2 + o0 + no * (i1 + ni * i2)];
       for (int o1 = 0; o1 < no; ++o1) {
         T s = 0;
-        for (int i1 = 0; i1 < ni; ++i1) s += M(ch[1], o1, i1) * x[i1];
+        for (int i1 = 0; i1 < ni; ++i1) s += M(b1, o1, i1) * x[i1];
         B[le * no2 * ni + o0 + no * (o1 + no * i2)] = s;
       }
     }
     tr_sync();
-    // pass 3, z-lines: lane -> (element le, o0 + no o1), accumulated over children
-    if (lane < W * no2) {
-      const int le = lane / no2, r = lane - le * no2;
-      if (a.kind == 1) {
-        if (RESTRICT) ch[2] = c >> 2;
-        else if (eb + le < nel_out) fine_bits(eb + le, ch);
-      }
+    // pass 3, z-lines: (element le, o0 + no o1)
+    for (int ln = lane; ln < W * no2; ln += 64) {
+      const int le = ln / no2, r = ln - le * no2;
+      const int b2 = bit(2, c, le);
       T x[kMaxN];
       for (int i2 = 0; i2 < ni; ++i2) x[i2] = B[le * no2 * ni + r + no2 * i2];
+      const int64_t eo = eb + le;
       for (int o2 = 0; o2 < no; ++o2) {
         T s = 0;
-        for (int i2 = 0; i2 < ni; ++i2) s += M(ch[2], o2, i2) * x[i2];
-        acc[o2] += s;
+        for (int i2 = 0; i2 < ni; ++i2) s += M(b2, o2, i2) * x[i2];
+        if (hres) {
+          acc[o2] += s;  // one line per lane (W no^2 <= 64)
+        } else if (eo < nel_out) {
+          const int64_t g = eo * no3 + r + (int64_t)no2 * o2;
+          out[g] = (!RESTRICT && add) ? out[g] + s : s;
+        }
       }
     }
   }
-  if (lane < W * no2) {
+  if (hres && lane < W * no2) {
     const int le = lane / no2, r = lane - le * no2;
     const int64_t eo = eb + le;
     if (eo < nel_out)
-      for (int o2 = 0; o2 < no; ++o2) {
-        const int64_t g = eo * no3 + r + (int64_t)no2 * o2;
-        out[g] = (!RESTRICT && add) ? out[g] + acc[o2] : acc[o2];
-      }
+      for (int o2 = 0; o2 < no; ++o2) out[eo * no3 + r + (int64_t)no2 * o2] = acc[o2];
   }
 }
 
@@ -538,10 +535,13 @@ static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double
                          bool restrict_) {
   TrArgs<T> a;
   {
-    // W elements: every pass's lines (ni^2, no ni, no^2 per element) fit in 64 lanes
+    // W elements: the input, T1 and T2 of W elements fit the LDS buffers; the
+    // h-restriction keeps one output line per lane (W no^2 <= 64)
     const int ni = restrict_ ? nf : nc, no = restrict_ ? nc : nf;
-    const int lines = std::max(ni * ni, std::max(no * ni, no * no));
-    const int W = 64 / lines;
+    const int buf = kTrBytes / (int)sizeof(T);
+    const int per = std::max(ni * ni * ni, std::max(no * ni * ni, no * no * ni));
+    int W = buf / per;
+    if (restrict_ && kind == 1) W = std::min(W, 64 / (no * no));
     a.W = W < 1 ? 1 : W;
   }
   a.nf = nf;
