@@ -6,7 +6,9 @@ boundary, seeded U[-1,1] right-hand side.  One step = one full solve from
 x_0 = 0 to ||r||/||r_0|| <= 1e-10: FP64 preconditioned CG (Alg. 1) with one
 V-cycle per iteration (Alg. 2) over the hybrid hierarchy cph (DG4 -> FE4 ->
 FE2 -> FE1 -> h-coarsening to 4^3) in FP32, Chebyshev(5) smoothing (Alg. 3)
-and an exact FP64 coarse solve.  `value` is DoFs solved per second
+and an exact FP64 coarse solve; PCG iterations are replayed from recorded
+HIP graphs (--no-graph: eager launches, the same results bit for bit).
+`value` is DoFs solved per second
 (N * steps / time).  The FP64 and FP32 operator applies are timed on their
 own with HIP events on the launch stream (operator_apply, roofline).
 
@@ -326,7 +328,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
     ap.add_argument("--nrhs", type=int, default=8, help="vectors per batched apply (0: skip)")
-    ap.add_argument("--graph", action="store_true", help="replay PCG iterations from recorded HIP graphs")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="launch every kernel eagerly instead of replaying recorded PCG iterations and V-cycles")
     ap.add_argument("--no-multi", action="store_true", help="skip the 64-mesh batch (multi_64)")
     ap.add_argument("--multi-only", action="store_true", help="only time the 64-mesh batch (multi_64)")
     ap.add_argument("--learned-only", action="store_true",
