@@ -203,3 +203,28 @@ def test_flexible_cg_equals_pcg_with_exact_coarse():
     x2, s2 = H.solve(b, rtol=1e-10)
     assert abs(s1["iters"] - s2["iters"]) <= 1
     assert float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1)) <= 1e-8
+
+
+def test_learned_inputs_mask_free_nodes_with_neumann_face():
+    """Network inputs of a coarse level with a Neumann face: the mask channel
+    is the oracle's free-node set, the residual channel r / RMS(r) there."""
+    bc = (0, 1, 0, 0, 1, 0)
+    hm, _ = meshes((8, 8, 8), 2, True, amp=0.05, bc=bc)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=4, smoother_degree=3, mg_prec=hmg.F64)
+    info = H.coarse_info()
+    assert info["nodes"] == (5, 5, 5)
+    _, oc = meshes((4, 4, 4), 1, True, amp=0.05, bc=bc)
+    free = ofe.free_mask(oc, 1)
+    R = np.stack([uniform(90 + i, 125) for i in range(3)])
+    inp, _ = H.learned_data(8, torch.as_tensor(R, device="cuda"))
+    inp = inp.cpu().numpy().astype(np.float64)
+    for s in range(3):
+        grid = np.zeros((8, 8, 8))
+        rgrid = np.zeros((8, 8, 8))
+        f3 = free.reshape(5, 5, 5, order="F")   # [x, y, z]
+        r3 = R[s].reshape(5, 5, 5, order="F")
+        grid[:5, :5, :5] = f3.transpose(2, 1, 0)  # [z, y, x]
+        sig = np.sqrt((R[s] ** 2 * free).sum() / free.sum())
+        rgrid[:5, :5, :5] = (r3 * f3).transpose(2, 1, 0) / sig
+        np.testing.assert_array_equal(inp[s, ..., 1], grid)
+        np.testing.assert_allclose(inp[s, ..., 0], rgrid, rtol=1e-6, atol=1e-6)

@@ -191,3 +191,17 @@ def test_multi_workload_sampled():
         for r in (0, 3):
             single = levels[i].apply(B.view(U, i, r).contiguous())
             assert torch.equal(B.view(V, i, r), single), (i, r)
+
+
+def test_batch_max_vectors_tiny_meshes():
+    """nrhs = 64 (the limit) on one-element and ragged meshes of several degrees."""
+    spec = [((1, 1, 1), 2, False), ((2, 1, 3), 4, False), ((1, 2, 1), 3, True), ((3, 1, 1), 7, False)]
+    lv = _levels(spec, hmg.F32)
+    B = hmg.Batch([L for L, _, _ in lv], 64)
+    U = _fill(B, 1300)
+    for sch in (SCHEDULES[0], SCHEDULES[3]):
+        B.set_schedule(**sch)
+        V = torch.full((B.total,), SENTINEL, dtype=B.dtype, device="cuda")
+        B.apply(U, V)
+        _check_equal_single(B, U, V)
+        _padding_untouched(B, V)
