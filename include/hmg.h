@@ -59,7 +59,9 @@ typedef enum { HMG_DG = 0, HMG_FE = 1 } hmg_space;
 /* Thread-local text of the last error (empty string if none). */
 const char* hmg_last_error(void);
 
-/* Library version: major*10000 + minor*100 + patch. */
+/* Library version: major*10000 + minor*100 + patch.  0.1.0 (100): levels,
+ * transfers, hierarchy, PCG; 0.2.0 (200): several vectors per launch,
+ * recorded graphs, multi-mesh batches, the learned coarse correction. */
 int hmg_version(void);
 
 /*
