@@ -297,16 +297,24 @@ int hmg_net_gradient(hmg_net* N, const float* in, const float* target, int batch
 int hmg_net_train_step(hmg_net* N, const float* in, const float* target, int batch, double lr,
                        double* loss, hipStream_t stream);
 
-enum { HMG_COARSE_EXACT = 0, HMG_COARSE_SMOOTH = 1, HMG_COARSE_LEARNED = 2 };
+enum { HMG_COARSE_EXACT = 0, HMG_COARSE_SMOOTH = 1, HMG_COARSE_LEARNED = 2, HMG_COARSE_CG = 3 };
 /*
- * Coarsest-level solve of the V-cycle: EXACT (dense FP64 inverse),
- * SMOOTH (Chebyshev smoothing only, the V-cycle without a coarse solve) or
- * LEARNED: x = network(b), judged on the GPU by |b - A x| <= accept |b|
- * (finite), else the exact solve (fallbacks counted, hmg_hierarchy_coarse_stats).
+ * Coarsest-level solve of the V-cycle: EXACT (dense FP64 inverse; coarse
+ * levels up to 8192 unknowns, the default there), CG (Jacobi-preconditioned
+ * CG in the level precision to hmg_hierarchy_set_coarse_cg's tolerance; the
+ * default above 8192 unknowns), SMOOTH (Chebyshev smoothing only, the
+ * V-cycle without a coarse solve) or LEARNED: x = network(b), judged on the
+ * GPU by |b - A x| <= accept |b| (finite), else the exact solve or, without
+ * a dense inverse, the CG solve (fallbacks counted, hmg_hierarchy_coarse_stats).
  * LEARNED needs a continuous Q1 coarsest level whose node grid fits the
- * network's grid and switches hmg_pcg_solve to flexible CG.
+ * network's grid.  LEARNED and CG switch hmg_pcg_solve to flexible CG (the
+ * preconditioner changes between iterations).
+ * HMG_ERR_UNSUPPORTED: EXACT without a dense inverse.
  */
 int hmg_hierarchy_set_coarse(hmg_hierarchy* H, int mode, hmg_net* net, double accept);
+/* Iterative coarse solve: stop at |r.z| <= rtol^2 |r_0.z_0| or after maxit
+ * iterations (defaults 1e-3, 50); converged iterations cost empty launches. */
+int hmg_hierarchy_set_coarse_cg(hmg_hierarchy* H, double rtol, int maxit);
 /* Flexible CG (beta = -(z_{k+1} . A p_k) / (p_k . A p_k)); equal to PCG in
  * exact arithmetic for a fixed symmetric preconditioner. */
 int hmg_hierarchy_set_flexible(hmg_hierarchy* H, int enable);
@@ -318,7 +326,8 @@ int hmg_hierarchy_coarse_info(const hmg_hierarchy* H, int64_t* n, int* Mx, int* 
  * without recorded graphs while capturing. */
 int hmg_hierarchy_capture(hmg_hierarchy* H, double* buf, int capacity);
 int hmg_hierarchy_captured(const hmg_hierarchy* H, int* count);
-/* E[s] = A_c^{-1} R[s] for count coarse vectors (FP64, n values each). */
+/* E[s] = A_c^{-1} R[s] for count coarse vectors (FP64, n values each): the
+ * dense inverse, or FP64 Jacobi-PCG to 1e-12 without one (blocks). */
 int hmg_hierarchy_coarse_solve_batch(const hmg_hierarchy* H, const double* R, double* E, int count,
                                      hipStream_t stream);
 /* Network inputs (and targets if target != NULL) of count <= 1024 coarse

@@ -688,6 +688,9 @@ struct hmg_hierarchy {
   double accept = 0.0;
   double c0 = 1.0;   // output scale of the network: 1 / mean free diagonal of the coarse operator
   double lmax_c = 0.0;
+  bool dense = true;          // dense inverse of the coarsest operator (<= 8192 unknowns)
+  double coarse_rtol = 1e-3;  // iterative coarse solve: Jacobi-PCG tolerance and iteration cap
+  int coarse_maxit = 50;
   bool flexible = false;
   int64_t net_version = -1;  // network parameters the recorded graphs saw
   // coarse right-hand sides of eager V-cycles copied to a caller buffer (FP64)
@@ -810,10 +813,9 @@ extern "C" int hmg_hierarchy_create(const hmg_mesh_desc* desc, const char* strat
     }
   }
   H->nc = H->lv.back()->n_dofs;
-  if (H->nc > 8192) {
-    delete H;
-    return fail(HMG_ERR_UNSUPPORTED, "coarse level has more than 8192 unknowns (choose a strategy that coarsens further)");
-  }
+  // dense inverse up to 8192 unknowns; above, the coarse solve is iterative
+  H->dense = H->nc <= 8192;
+  H->coarse_mode = H->dense ? HMG_COARSE_EXACT : HMG_COARSE_CG;
   // workspace layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -832,10 +834,10 @@ extern "C" int hmg_hierarchy_create(const hmg_mesh_desc* desc, const char* strat
     H->off_f64 = take(H->fine64->ws_bytes);
     H->off_c64 = take(H->coarse64->ws_bytes);
   }
-  H->off_ainv = take((size_t)H->nc * H->nc * 8);
+  H->off_ainv = take(H->dense ? (size_t)H->nc * H->nc * 8 : 8);
   H->off_cg = take((size_t)4 * H->fine64->n_dofs * 8);
   H->off_part = take((size_t)kPartials * 8);
-  H->off_scal = take(16 * 8);
+  H->off_scal = take(32 * 8);
   H->ws_bytes = off;
   *out = H;
   return HMG_OK;
@@ -941,7 +943,7 @@ extern "C" int hmg_hierarchy_bind(hmg_hierarchy* H, void* ws, size_t bytes, hipS
   for (size_t l = 0; l + 1 < H->lv.size(); ++l)
     TRY(estimate_lmax(H->lv[l], 20, H->seed + l, &H->lmax[l], s));
   TRY(estimate_lmax(H->lv.back(), 20, H->seed + H->lv.size(), &H->lmax_c, s));
-  TRY(coarse_setup(H, s));
+  if (H->dense) TRY(coarse_setup(H, s));
   {  // network output scale: 1 / mean diagonal over the free coarse unknowns
     const hmg_level* C = H->coarse64;
     const NodeGrid ng = coarse_nodes(H);
@@ -963,8 +965,8 @@ extern "C" int hmg_hierarchy_bind(hmg_hierarchy* H, void* ws, size_t bytes, hipS
     H->c0 = nd > 0 && sd > 0 ? nd / sd : 1.0;
   }
   {
-    int zero[2] = {0, 0};
-    HMG_HIP(hipMemcpyAsync(H->scal() + 10, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    std::vector<double> zero(32, 0.0);
+    HMG_HIP(hipMemcpyAsync(H->scal(), zero.data(), 32 * 8, hipMemcpyHostToDevice, s));
     HMG_HIP(hipStreamSynchronize(s));
   }
   H->bound = true;
@@ -1008,6 +1010,52 @@ static NodeGrid coarse_nodes(const hmg_hierarchy* H) {
   return ng;
 }
 
+// Jacobi-preconditioned CG (Alg. 1 with D^{-1}) for L x = b, x_0 = 0, at most
+// maxit iterations, stopping on the GPU once r.z <= rtol^2 r_0.z_0: every
+// later kernel returns at once (the gate *skip), so the sequence can be
+// recorded.  Eager launches also read the gate every 8 iterations and stop
+// early.  *skip must be set before the call (nonzero: do nothing).
+// Scalars: sc[16..17] r.z (alternating), sc[18] p.q, sc[19] r_0.z_0.
+static int coarse_cg(hmg_hierarchy* H, const hmg_level* L, const void* b, void* x, double rtol, int maxit,
+                     hipStream_t s) {
+  const int pr = L->prec;
+  const int64_t n = L->n_dofs;
+  void *r = L->tmp(0), *z = L->tmp(1), *p = L->tmp(2), *q = L->tmp(3);
+  double* sc = H->scal() + 16;
+  int* skip = (int*)(H->scal() + 24);
+  int* iters = skip + 1;
+  double* part = H->part();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HMG_HIP(hipStreamIsCapturing(s, &cs));
+  const bool eager = cs == hipStreamCaptureStatusNone;
+  if (eager) {  // a solve the gate already skips costs no launches
+    int done = 0;
+    HMG_HIP(hipMemcpyAsync(&done, skip, sizeof(int), hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    if (done) return HMG_OK;
+  }
+  TRY(ccg_init(pr, b, L->dinv(), x, r, z, p, n, skip, s));
+  TRY(vec_dot_gated(pr, r, z, n, part, sc + 0, skip, s));
+  TRY(vec_dot_gated(pr, r, z, n, part, sc + 3, skip, s));
+  for (int it = 0; it < maxit; ++it) {
+    double* old = sc + (it & 1);
+    double* nw = sc + ((it + 1) & 1);
+    TRY(launch_operator_gated(L, OP_APPLY, p, q, nullptr, skip, s));
+    TRY(vec_dot_gated(pr, p, q, n, part, sc + 2, skip, s));
+    TRY(ccg_xr(pr, x, r, z, p, q, L->dinv(), n, old, sc + 2, skip, s));
+    TRY(vec_dot_gated(pr, r, z, n, part, nw, skip, s));
+    TRY(ccg_p(pr, p, z, n, nw, old, skip, s));
+    TRY(ccg_check(nw, sc + 3, rtol * rtol, skip, iters, s));
+    if (eager && (it & 7) == 7) {
+      int done = 0;
+      HMG_HIP(hipMemcpyAsync(&done, skip, sizeof(int), hipMemcpyDeviceToHost, s));
+      HMG_HIP(hipStreamSynchronize(s));
+      if (done) break;
+    }
+  }
+  return HMG_OK;
+}
+
 // Coarsest level: x(l) from b(l) by the selected coarse solve.
 static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
   hmg_level* L = H->lv[l];
@@ -1015,9 +1063,13 @@ static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
     TRY(vec_convert(L->prec, H->b(l), HMG_F64, H->cap_buf + (size_t)H->cap_count * H->nc, H->nc, s));
     H->cap_count++;
   }
+  int* skip = (int*)(H->scal() + 24);
   switch (H->coarse_mode) {
     case HMG_COARSE_SMOOTH:
       return chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax_c, 0.06, 1.2, 1, s);
+    case HMG_COARSE_CG:
+      TRY(set_flag(skip, 0, s));
+      return coarse_cg(H, L, H->b(l), H->x(l), H->coarse_rtol, H->coarse_maxit, s);
     case HMG_COARSE_LEARNED: {
       hmg_net* N = H->net;
       const NodeGrid ng = coarse_nodes(H);
@@ -1029,8 +1081,12 @@ static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
       TRY(launch_operator(L, OP_RESID, H->x(l), H->r(l), H->b(l), nullptr, 0, 0, nullptr, s));
       TRY(vec_dot(L->prec, H->r(l), H->r(l), H->nc, H->part(), gate, s));
       TRY(vec_dot(L->prec, H->b(l), H->b(l), H->nc, H->part(), gate + 1, s));
-      return coarse_gemv_gated(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, gate, H->accept,
-                               (int*)(H->scal() + 10), s);
+      if (H->dense)
+        return coarse_gemv_gated(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, gate, H->accept,
+                                 (int*)(H->scal() + 10), s);
+      // no dense inverse: the iterative coarse solve runs only for a rejected correction
+      TRY(gate_to_skip(gate, H->accept, skip, (int*)(H->scal() + 10), s));
+      return coarse_cg(H, L, H->b(l), H->x(l), H->coarse_rtol, H->coarse_maxit, s);
     }
     default:
       return coarse_gemv(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, s);
@@ -1215,8 +1271,11 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
 
 extern "C" int hmg_hierarchy_set_coarse(hmg_hierarchy* H, int mode, hmg_net* net, double accept) {
   if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
-  if (mode != HMG_COARSE_EXACT && mode != HMG_COARSE_SMOOTH && mode != HMG_COARSE_LEARNED)
+  if (mode != HMG_COARSE_EXACT && mode != HMG_COARSE_SMOOTH && mode != HMG_COARSE_LEARNED &&
+      mode != HMG_COARSE_CG)
     return fail(HMG_ERR_INVALID, "unknown coarse mode");
+  if (mode == HMG_COARSE_EXACT && !H->dense)
+    return fail(HMG_ERR_UNSUPPORTED, "no dense coarse inverse above 8192 unknowns");
   if (mode == HMG_COARSE_LEARNED) {
     if (!net || !net->bound) return fail(HMG_ERR_INVALID, "learned coarse solve needs a bound network");
     if (H->lv.back()->space != HMG_FE || H->lv.back()->k != 1)
@@ -1229,7 +1288,8 @@ extern "C" int hmg_hierarchy_set_coarse(hmg_hierarchy* H, int mode, hmg_net* net
   H->coarse_mode = mode;
   H->net = mode == HMG_COARSE_LEARNED ? net : nullptr;
   H->accept = accept;
-  H->flexible = mode == HMG_COARSE_LEARNED ? true : H->flexible;
+  // an inexact or learned coarse solve changes the preconditioner between iterations
+  H->flexible = (mode == HMG_COARSE_LEARNED || mode == HMG_COARSE_CG) ? true : H->flexible;
   H->drop_graphs();
   return HMG_OK;
 }
@@ -1278,7 +1338,15 @@ extern "C" int hmg_hierarchy_coarse_solve_batch(const hmg_hierarchy* H, const do
   TRY(check_ptr(R, "R"));
   TRY(check_ptr(E, "E"));
   if ((const void*)R == (void*)E) return fail(HMG_ERR_INVALID, "R and E must not overlap");
-  return coarse_gemm(H->ainv(), R, E, (int)H->nc, count, s);
+  if (H->dense) return coarse_gemm(H->ainv(), R, E, (int)H->nc, count, s);
+  // no dense inverse: FP64 Jacobi-PCG on the FP64 coarse level, sample by sample
+  hmg_hierarchy* Hm = const_cast<hmg_hierarchy*>(H);
+  int* skip = (int*)(H->scal() + 24);
+  for (int i = 0; i < count; ++i) {
+    TRY(set_flag(skip, 0, s));
+    TRY(coarse_cg(Hm, H->coarse64, R + (size_t)i * H->nc, E + (size_t)i * H->nc, 1e-12, 20000, s));
+  }
+  return HMG_OK;
 }
 
 extern "C" int hmg_hierarchy_learned_data(const hmg_hierarchy* H, int grid, const double* R, const double* E,
@@ -1304,5 +1372,15 @@ extern "C" int hmg_hierarchy_coarse_stats(const hmg_hierarchy* H, int* fallbacks
   if (!H || !H->bound || !fallbacks) return fail(HMG_ERR_INVALID, "hierarchy not bound or NULL argument");
   HMG_HIP(hipMemcpyAsync(fallbacks, H->scal() + 10, sizeof(int), hipMemcpyDeviceToHost, s));
   HMG_HIP(hipStreamSynchronize(s));
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_set_coarse_cg(hmg_hierarchy* H, double rtol, int maxit) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (!(rtol > 0) || !(rtol < 1) || maxit < 1 || maxit > 100000)
+    return fail(HMG_ERR_INVALID, "need 0 < rtol < 1 and 1 <= maxit <= 100000");
+  H->coarse_rtol = rtol;
+  H->coarse_maxit = maxit;
+  H->drop_graphs();
   return HMG_OK;
 }

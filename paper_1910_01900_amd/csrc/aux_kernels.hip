@@ -288,7 +288,9 @@ static dim3 node_grid(const FeGeo& G) {
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* dg, const T* u, T* out, const T* b,
-                                                              const T* dinv, const T* xold, T sigma, T theta) {
+                                                              const T* dinv, const T* xold, T sigma, T theta,
+                                                              const int* skip) {
+  if (skip && *skip) return;  // gated apply (iterative coarse solve)
   const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
   if (gx >= G.Mx || gy >= G.My) return;
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
@@ -341,7 +343,7 @@ __global__ void k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add
 
 template <typename T>
 static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                    const void* xold, double sigma, double theta, hipStream_t s) {
+                    const void* xold, double sigma, double theta, hipStream_t s, const int* skip) {
   FeGeo G = fe_geo(L->mesh, L->k);
   if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
   const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
@@ -350,23 +352,141 @@ static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, cons
   switch (mode) {
     case OP_RESID:
       hipLaunchKernelGGL((k_fe_sum<T, OP_RESID>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
       break;
     case OP_CHEB:
       hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
       break;
     default:
       hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta);
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
   }
   return check_launch("fe_sum");
 }
 int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                const void* xold, double sigma, double theta, hipStream_t s) {
-  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s);
-  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s);
+                const void* xold, double sigma, double theta, hipStream_t s, const int* skip) {
+  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s, skip);
+  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s, skip);
 }
+
+// ------------------------------------------------------------------ gated CG (coarse solve)
+// Jacobi-preconditioned CG (Alg. 1 with D^{-1}) on one level; FP64 scalars
+// in device memory; every kernel returns at once while *skip != 0, so a
+// converged or unneeded solve costs launches only.
+template <typename T>
+__global__ void k_ccg_init(const T* b, const T* dinv, T* x, T* r, T* z, T* p, int64_t n, const int* skip) {
+  if (*skip) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T bi = b[i], zi = dinv[i] * bi;
+    x[i] = 0;
+    r[i] = bi;
+    z[i] = zi;
+    p[i] = zi;
+  }
+}
+template <typename T>
+__global__ void k_ccg_xr(T* x, T* r, T* z, const T* p, const T* q, const T* dinv, int64_t n, const double* rz,
+                         const double* pq, const int* skip) {
+  if (*skip) return;
+  const T a = (T)(*rz / *pq);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    z[i] = dinv[i] * ri;
+  }
+}
+template <typename T>
+__global__ void k_ccg_p(T* p, const T* z, int64_t n, const double* rzn, const double* rz, const int* skip) {
+  if (*skip) return;
+  const T beta = (T)(*rzn / *rz);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+__global__ void k_ccg_check(const double* rzn, const double* rz0, double tol2, int* skip, int* iters) {
+  if (blockIdx.x != 0 || threadIdx.x != 0 || *skip) return;
+  *iters += 1;
+  if (!(*rzn > tol2 * *rz0)) *skip = 1;  // converged, or NaN
+}
+template <typename T>
+__global__ void k_dot_gated(const T* x, const T* y, int64_t n, double* partials, const int* skip) {
+  if (*skip) return;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)x[i] * (double)y[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+__global__ void k_reduce_gated(const double* partials, int np, double* out, const int* skip) {
+  if (*skip) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) *out = s;
+}
+__global__ void k_gate_to_skip(const double* gate, double accept2, int* skip, int* fallbacks) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double rr = gate[0], bb = gate[1];
+  const bool ok = isfinite(rr) && rr <= accept2 * bb;
+  *skip = ok ? 1 : 0;
+  if (!ok) *fallbacks += 1;
+}
+__global__ void k_set_flag(int* flag, int v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = v;
+}
+
+int ccg_init(int prec, const void* b, const void* dinv, void* x, void* r, void* z, void* p, int64_t n,
+             const int* skip, hipStream_t s) {
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_ccg_init<double>, grid_for(n), kBlock, 0, s, (const double*)b, (const double*)dinv,
+                                   (double*)x, (double*)r, (double*)z, (double*)p, n, skip),
+                hipLaunchKernelGGL(k_ccg_init<float>, grid_for(n), kBlock, 0, s, (const float*)b, (const float*)dinv,
+                                   (float*)x, (float*)r, (float*)z, (float*)p, n, skip));
+  return check_launch("ccg_init");
+}
+int ccg_xr(int prec, void* x, void* r, void* z, const void* p, const void* q, const void* dinv, int64_t n,
+           const double* rz, const double* pq, const int* skip, hipStream_t s) {
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_ccg_xr<double>, grid_for(n), kBlock, 0, s, (double*)x, (double*)r, (double*)z,
+                                   (const double*)p, (const double*)q, (const double*)dinv, n, rz, pq, skip),
+                hipLaunchKernelGGL(k_ccg_xr<float>, grid_for(n), kBlock, 0, s, (float*)x, (float*)r, (float*)z,
+                                   (const float*)p, (const float*)q, (const float*)dinv, n, rz, pq, skip));
+  return check_launch("ccg_xr");
+}
+int ccg_p(int prec, void* p, const void* z, int64_t n, const double* rzn, const double* rz, const int* skip,
+          hipStream_t s) {
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_ccg_p<double>, grid_for(n), kBlock, 0, s, (double*)p, (const double*)z, n, rzn, rz,
+                                   skip),
+                hipLaunchKernelGGL(k_ccg_p<float>, grid_for(n), kBlock, 0, s, (float*)p, (const float*)z, n, rzn, rz,
+                                   skip));
+  return check_launch("ccg_p");
+}
+int ccg_check(const double* rzn, const double* rz0, double tol2, int* skip, int* iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_ccg_check, 1, 64, 0, s, rzn, rz0, tol2, skip, iters);
+  return check_launch("ccg_check");
+}
+int vec_dot_gated(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
+                  const int* skip, hipStream_t s) {
+  const unsigned g = dot_grid(n);
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_dot_gated<double>, g, kBlock, 0, s, (const double*)x, (const double*)y, n, partials,
+                                   skip),
+                hipLaunchKernelGGL(k_dot_gated<float>, g, kBlock, 0, s, (const float*)x, (const float*)y, n, partials,
+                                   skip));
+  hipLaunchKernelGGL(k_reduce_gated, 1, 1024, 0, s, (const double*)partials, (int)g, out, skip);
+  return check_launch("dot_gated");
+}
+int gate_to_skip(const double* gate, double accept, int* skip, int* fallbacks, hipStream_t s) {
+  hipLaunchKernelGGL(k_gate_to_skip, 1, 64, 0, s, gate, accept * accept, skip, fallbacks);
+  return check_launch("gate_to_skip");
+}
+int set_flag(int* flag, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_flag, 1, 64, 0, s, flag, v);
+  return check_launch("set_flag");
+}
+
 int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int weight_mult, int add,
                 hipStream_t s) {
   FeGeo G = fe_geo(m, k);

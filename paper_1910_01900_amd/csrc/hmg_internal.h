@@ -187,6 +187,7 @@ struct OpArgs {
   int nrhs;               // vectors applied at once (work item = element x vector)
   int64_t ld;             // distance between consecutive vectors, in values
   T h[3];
+  const int* skip;        // continuous FE levels: the launch does nothing while *skip != 0 (NULL: never)
 };
 
 // The level's constant arguments (vectors unset, one vector, linear order).
@@ -214,6 +215,7 @@ inline OpArgs<T> make_args(const hmg_level* L) {
   a.nrhs = 1;
   a.ld = L->n_dofs;
   for (int d = 0; d < 3; ++d) a.h[d] = (T)L->mesh.h(d);
+  a.skip = nullptr;
   return a;
 }
 
@@ -237,8 +239,8 @@ struct MeshEntry {
 };
 // The host writes the table that the kernels read: the layout must agree in
 // the host and the device compilation.
-static_assert(sizeof(MeshEntry<double>) == 216 && sizeof(MeshEntry<float>) == 200, "MeshEntry layout");
-static_assert(offsetof(MeshEntry<double>, off) == 184 && offsetof(MeshEntry<float>, off) == 168, "MeshEntry layout");
+static_assert(sizeof(MeshEntry<double>) == 224 && sizeof(MeshEntry<float>) == 208, "MeshEntry layout");
+static_assert(offsetof(MeshEntry<double>, off) == 192 && offsetof(MeshEntry<float>, off) == 176, "MeshEntry layout");
 static_assert(offsetof(OpArgs<double>, ld) == 152 && offsetof(OpArgs<float>, h) == 152, "OpArgs layout");
 
 // One multi-mesh launch: meshes table[0..count) (device memory, vector
@@ -278,6 +280,27 @@ int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, 
                             const void* b, const void* xold, double sigma, double theta, int* nparts,
                             hipStream_t s);
 
+// launch_operator with a device gate: on continuous FE levels every kernel
+// of the apply returns at once while *skip != 0 (DG levels ignore it).
+int launch_operator_gated(const hmg_level* L, int mode, const void* u, void* out, const void* b,
+                          const int* skip, hipStream_t s);
+// Jacobi-preconditioned CG steps with FP64 scalars in device memory; every
+// kernel returns at once while *skip != 0.
+int ccg_init(int prec, const void* b, const void* dinv, void* x, void* r, void* z, void* p, int64_t n,
+             const int* skip, hipStream_t s);
+int ccg_xr(int prec, void* x, void* r, void* z, const void* p, const void* q, const void* dinv, int64_t n,
+           const double* rz, const double* pq, const int* skip, hipStream_t s);
+int ccg_p(int prec, void* p, const void* z, int64_t n, const double* rzn, const double* rz, const int* skip,
+          hipStream_t s);
+// *skip = 1 once *rzn <= tol2 * *rz0 (or not finite); *iters counts the iterations run
+int ccg_check(const double* rzn, const double* rz0, double tol2, int* skip, int* iters, hipStream_t s);
+// dot product that does nothing while *skip != 0
+int vec_dot_gated(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
+                  const int* skip, hipStream_t s);
+// *skip = (gate[0] <= accept^2 gate[1] and finite); a rejected gate adds one to *fallbacks
+int gate_to_skip(const double* gate, double accept, int* skip, int* fallbacks, hipStream_t s);
+int set_flag(int* flag, int v, hipStream_t s);
+
 // vectors (type by prec); n elements
 int vec_fill(int prec, void* x, double a, int64_t n, hipStream_t s);
 int vec_copy(int prec, const void* x, void* y, int64_t n, hipStream_t s);
@@ -315,7 +338,7 @@ int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weigh
              hipStream_t s);
 // FE operator node sum with a mode (see launch_operator)
 int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                const void* xold, double sigma, double theta, hipStream_t s);
+                const void* xold, double sigma, double theta, hipStream_t s, const int* skip = nullptr);
 // coarse dense FP64 inverse apply: x = Ainv b (b, x of prec), n unknowns
 int coarse_gemv(int prec, const double* Ainv, const void* b, void* x, int n, hipStream_t s);
 // SplitMix64 uniform [-1,1) vector

@@ -12,6 +12,9 @@ template <int N, typename T, bool CURVED, bool FE, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<N, CURVED, FE>::WPE)))
 op_kernel(const OpArgs<T> a) {
   using C = Cfg<N, CURVED, FE>;
+  if constexpr (FE) {
+    if (a.skip && *a.skip) return;  // gated apply (iterative coarse solve)
+  }
   constexpr int WL = op_wave_lds<N, T, CURVED, FE, MODE>();
   __shared__ T smem[C::WAVES * WL];
   const int wave = threadIdx.x >> 6;
@@ -73,9 +76,10 @@ static constexpr int kTileY = 4;
 template <int N, typename T, bool CURVED, bool FE>
 static int run_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                   const void* xold, double sigma, double theta, int* nparts, int nrhs, int64_t ld,
-                  hipStream_t s) {
+                  const int* skip, hipStream_t s) {
   using C = Cfg<N, CURVED, FE>;
   OpArgs<T> a = make_args<T>(L);
+  a.skip = FE ? skip : nullptr;
   a.nrhs = nrhs;
   a.ld = ld;
   a.u = (const T*)u;
@@ -113,23 +117,22 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   }
   int rc = check_launch("op_kernel");
   if (rc) return rc;
-  if (FE) return fe_node_sum(L, mode, u, out, b, xold, sigma, theta, s);
+  if (FE) return fe_node_sum(L, mode, u, out, b, xold, sigma, theta, s, skip);
   return HMG_OK;
 }
 
 template <int N, typename T>
 static int dispatch_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                        const void* xold, double sigma, double theta, int* nparts, int nrhs, int64_t ld,
-                       hipStream_t s) {
+                       const int* skip, hipStream_t s) {
   const bool curved = L->mesh.curved, fe = L->space == HMG_FE;
   if (curved) {
-    if (fe) return run_op<N, T, true, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
-    return run_op<N, T, true, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+    if (fe) return run_op<N, T, true, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+    return run_op<N, T, true, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
   }
-  if (fe) return run_op<N, T, false, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
-  return run_op<N, T, false, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+  if (fe) return run_op<N, T, false, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+  return run_op<N, T, false, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
 }
-
 
 template <int N, typename T, bool CURVED, bool P>
 static int run_multi_p(int mode, const MultiLaunch& L, hipStream_t s) {
@@ -177,10 +180,10 @@ static int occ_multi(int mode) {
 #ifdef HMG_ONLY_N
 int HMG_CAT(op_launch_n, HMG_ONLY_N)(const hmg_level* L, int mode, const void* u, void* out,
                                       const void* b, const void* xold, double sigma, double theta,
-                                      int* nparts, int nrhs, int64_t ld, hipStream_t s) {
+                                      int* nparts, int nrhs, int64_t ld, const int* skip, hipStream_t s) {
   if (L->prec == HMG_F64)
-    return dispatch_op<HMG_ONLY_N, double>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
-  return dispatch_op<HMG_ONLY_N, float>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+    return dispatch_op<HMG_ONLY_N, double>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+  return dispatch_op<HMG_ONLY_N, float>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
 }
 int HMG_CAT(multi_launch_n, HMG_ONLY_N)(int prec, bool curved, int mode, const MultiLaunch& m, hipStream_t s) {
   if (prec == HMG_F64)
@@ -198,7 +201,7 @@ int HMG_CAT(multi_occupancy_n, HMG_ONLY_N)(int prec, bool curved, int mode) {
 #ifdef HMG_DISPATCH_ONLY
 #define HMG_DECL(N)                                                                          \
   int op_launch_n##N(const hmg_level*, int, const void*, void*, const void*, const void*,    \
-                     double, double, int*, int, int64_t, hipStream_t);                        \
+                     double, double, int*, int, int64_t, const int*, hipStream_t);            \
   int multi_launch_n##N(int, bool, int, const MultiLaunch&, hipStream_t);                     \
   int multi_occupancy_n##N(int, bool, int);
 HMG_DECL(2)
@@ -214,19 +217,29 @@ int launch_operator(const hmg_level* L, int mode, const void* u, void* out, cons
   return launch_operator_batched(L, mode, 1, L->n_dofs, u, out, b, xold, sigma, theta, nparts, s);
 }
 
-int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
-                            const void* b, const void* xold, double sigma, double theta, int* nparts,
-                            hipStream_t s) {
+static int launch_any(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out, const void* b,
+                      const void* xold, double sigma, double theta, int* nparts, const int* skip, hipStream_t s) {
   if (L->n_el == 0 || nrhs == 0) return HMG_OK;
   if (nrhs > 1 && (L->space != HMG_DG || mode == OP_DOT))
     return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: DG levels, apply/residual/Chebyshev only");
   switch (L->n) {
 #define HMG_CASE(N) \
-  case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, s);
+  case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
     HMG_CASE(2) HMG_CASE(3) HMG_CASE(4) HMG_CASE(5) HMG_CASE(6) HMG_CASE(7) HMG_CASE(8)
 #undef HMG_CASE
   }
   return fail(HMG_ERR_UNSUPPORTED, "degree must be 1..7");
+}
+
+int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
+                            const void* b, const void* xold, double sigma, double theta, int* nparts,
+                            hipStream_t s) {
+  return launch_any(L, mode, nrhs, ld, u, out, b, xold, sigma, theta, nparts, nullptr, s);
+}
+
+int launch_operator_gated(const hmg_level* L, int mode, const void* u, void* out, const void* b,
+                          const int* skip, hipStream_t s) {
+  return launch_any(L, mode, 1, L->n_dofs, u, out, b, nullptr, 0, 0, nullptr, skip, s);
 }
 
 int multi_launch(int n, int prec, bool curved, int mode, const MultiLaunch& m, hipStream_t s) {

@@ -105,6 +105,7 @@ def lib():
             "hmg_net_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, _P, _P]),
             "hmg_hierarchy_set_coarse": (C.c_int, [_P, C.c_int, _P, C.c_double]),
             "hmg_hierarchy_set_flexible": (C.c_int, [_P, C.c_int]),
+            "hmg_hierarchy_set_coarse_cg": (C.c_int, [_P, C.c_double, C.c_int]),
             "hmg_hierarchy_coarse_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int),
                                                     C.POINTER(C.c_int), C.POINTER(C.c_int),
                                                     C.POINTER(C.c_double)]),
@@ -401,7 +402,7 @@ class Batch:
             self._h = C.c_void_p()
 
 
-COARSE_EXACT, COARSE_SMOOTH, COARSE_LEARNED = 0, 1, 2
+COARSE_EXACT, COARSE_SMOOTH, COARSE_LEARNED, COARSE_CG = 0, 1, 2, 3
 
 
 class Net:
@@ -491,6 +492,10 @@ class Hierarchy:
         """Coarsest-level solve: COARSE_EXACT, COARSE_SMOOTH or COARSE_LEARNED (with net)."""
         self._net = net
         check(lib().hmg_hierarchy_set_coarse(self._h, mode, net._h if net is not None else None, accept))
+
+    def set_coarse_cg(self, rtol=1e-3, maxit=50):
+        """Tolerance and iteration cap of the iterative (Jacobi-PCG) coarse solve."""
+        check(lib().hmg_hierarchy_set_coarse_cg(self._h, rtol, maxit))
 
     def set_flexible(self, enable):
         check(lib().hmg_hierarchy_set_flexible(self._h, 1 if enable else 0))

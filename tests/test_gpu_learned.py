@@ -228,3 +228,65 @@ def test_learned_inputs_mask_free_nodes_with_neumann_face():
         rgrid[:5, :5, :5] = (r3 * f3).transpose(2, 1, 0) / sig
         np.testing.assert_array_equal(inp[s, ..., 1], grid)
         np.testing.assert_allclose(inp[s, ..., 0], rgrid, rtol=1e-6, atol=1e-6)
+
+
+def test_cg_coarse_solve_matches_exact_iterations():
+    """The iterative coarse solve (Jacobi-PCG, tight tolerance) gives the exact
+    coarse solve's iteration count; loose, it still converges (flexible CG)."""
+    H, _ = _hierarchy()
+    b = torch.as_tensor(uniform(5, H.n_dofs), device="cuda")
+    _, st_exact = H.solve(b, rtol=1e-10)
+    H.set_coarse(hmg.COARSE_CG)
+    H.set_coarse_cg(1e-10, 400)
+    _, st_tight = H.solve(b, rtol=1e-10, maxit=100)
+    assert abs(st_tight["iters"] - st_exact["iters"]) <= 1
+    H.set_coarse_cg(1e-2, 30)
+    _, st_loose = H.solve(b, rtol=1e-10, maxit=100)
+    print("iterations: exact %d, CG 1e-10 %d, CG 1e-2 %d" % (st_exact["iters"], st_tight["iters"], st_loose["iters"]))
+    assert st_loose["status"] == "HMG_OK"
+
+
+def _large_coarse():
+    """Coarsest level Q1 on 24^3 (15,625 nodes): above the dense limit."""
+    hm, om = meshes((24, 24, 24), 2, True, amp=0.05)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=24, smoother_degree=4, mg_prec=hmg.F32)
+    return H, hm
+
+
+def test_large_coarse_level_iterative_targets_and_learned_fallback():
+    H, hm = _large_coarse()
+    info = H.coarse_info()
+    assert info["nodes"] == (25, 25, 25) and info["n"] == 15625
+    with pytest.raises(hmg.HmgError):
+        H.set_coarse(hmg.COARSE_EXACT)
+    # training targets by FP64 Jacobi-PCG, checked against the oracle's Q1 matrix
+    _, oc = meshes((24, 24, 24), 1, True, amp=0.05)
+    A = ofe.assemble(oc, 1)
+    free = ofe.free_mask(oc, 1)
+    R = np.stack([uniform(110 + i, 15625) * free for i in range(2)])
+    E = H.coarse_solve_batch(torch.as_tensor(R, device="cuda")).cpu().numpy()
+    for i in range(2):
+        assert np.linalg.norm(R[i] - A @ E[i]) <= 1e-9 * np.linalg.norm(R[i])
+    b = torch.as_tensor(uniform(6, H.n_dofs), device="cuda")
+    H.set_coarse(hmg.COARSE_CG)
+    _, st_cg = H.solve(b, rtol=1e-10, maxit=100)
+    H.set_coarse(hmg.COARSE_SMOOTH)
+    _, st_sm = H.solve(b, rtol=1e-10, maxit=200)
+    net = hmg.Net(grid=32, max_batch=16, seed=9)
+    H.set_coarse(hmg.COARSE_CG)
+    loss = _train(H, net, samples=256, steps=150, batch=16)
+    H.set_coarse(hmg.COARSE_LEARNED, net, accept=0.5)
+    f0 = H.coarse_stats()
+    x, st = H.solve(b, rtol=1e-10, maxit=200)
+    fb = H.coarse_stats() - f0
+    print("loss %.3e; iterations CG %d, smoothing only %d, learned %d (%d fallbacks)"
+          % (loss, st_cg["iters"], st_sm["iters"], st["iters"], fb))
+    assert st["status"] == "HMG_OK" and st["rn"] <= 1e-10 * st["r0"]
+    L64 = hmg.Level(hm)
+    assert float(torch.linalg.norm(L64.residual(b, x)) / torch.linalg.norm(b)) <= 2e-10
+    # poisoned weights: the iterative coarse solve takes over every time
+    net.set_params(torch.full((net.n_params,), float("nan"), dtype=torch.float32, device="cuda"))
+    f1 = H.coarse_stats()
+    _, st_bad = H.solve(b, rtol=1e-10, maxit=200)
+    assert H.coarse_stats() - f1 == st_bad["iters"]
+    assert abs(st_bad["iters"] - st_cg["iters"]) <= 1

@@ -96,10 +96,14 @@ def test_hierarchy_levels_host(strategy, expect):
     h = C.c_void_p()
     d = m.desc()
     code = lib.hmg_hierarchy_create(C.byref(d), strategy.encode(), 1, 4, 5, hmg.F64, 1, C.byref(h))
-    if strategy == "p":
-        assert code == -2  # DG1 on 16^3 = 32768 coarse unknowns: above the dense limit
-        return
     assert code == 0, lib.hmg_last_error()
+    if strategy == "p":
+        # DG1 on 16^3 = 32768 coarse unknowns: above the dense limit, so the coarse
+        # solve is iterative and the exact mode is refused
+        assert lib.hmg_hierarchy_set_coarse(h, hmg.COARSE_EXACT, None, 0.0) == -2
+        assert lib.hmg_hierarchy_set_coarse(h, hmg.COARSE_CG, None, 0.0) == 0
+        assert lib.hmg_hierarchy_set_coarse_cg(h, 0.0, 10) == -1
+        assert lib.hmg_hierarchy_set_coarse_cg(h, 1e-4, 100) == 0
     n = C.c_int()
     assert lib.hmg_hierarchy_levels(h, C.byref(n)) == 0
     got = []
