@@ -205,20 +205,23 @@ def multi_mesh_bench(prec, nrhs=4, reps=10, cheb_degree=5):
     return out
 
 
-def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16):
+def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16, h_min=12):
     """Learned coarse-grid correction on the curvilinear 48^3 mesh, k = 5
-    (23.9M DoFs), hierarchy cph down to Q1 on 12^3 (2,197 coarse nodes), FP32
-    V-cycle: PCG with the exact coarse solve, with Chebyshev smoothing only
-    on the coarsest level, and flexible CG with the learned correction
-    (judge: coarse residual <= 0.5, else exact).  Training pairs: the coarse
-    right-hand sides of the V-cycles of seeded solves and their exact
-    solves."""
+    (23.9M DoFs), hierarchy cph down to Q1 on h_min^3, FP32 V-cycle.
+    h_min = 12 (2,197 coarse nodes): PCG with the exact (dense) coarse
+    solve; h_min = 24 (15,625 nodes, no dense inverse): flexible CG with the
+    iterative (Jacobi-PCG, 1e-3, at most 50 iterations) coarse solve.
+    Against both: Chebyshev smoothing only on the coarsest level, and
+    flexible CG with the learned correction (judge: coarse residual <= 0.5,
+    else the exact or iterative solve).  Training pairs: the coarse
+    right-hand sides of the V-cycles of seeded solves and their exact (FP64
+    dense or CG to 1e-12) solves."""
     import torch
     from paper_1910_01900_amd import hmg
     from paper_1910_01900_amd.inputs import uniform
     mesh = hmg.Mesh((48, 48, 48), 5, deformed=True, amp=0.05)
     t0 = time.time()
-    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=12, smoother_degree=5, mg_prec=hmg.F32)
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=h_min, smoother_degree=5, mg_prec=hmg.F32)
     info = H.coarse_info()
     log("learned: hierarchy in %.1f s, coarse nodes %s" % (time.time() - t0, info["nodes"]))
     N = H.n_dofs
@@ -243,12 +246,13 @@ def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16):
 
     out = {"workload": "curved_k5_48", "dofs": N, "coarse_nodes": list(info["nodes"]), "coarse_unknowns": info["n"]}
     res = {}
-    for name, mode in (("exact", hmg.COARSE_EXACT), ("smooth", hmg.COARSE_SMOOTH)):
+    base = hmg.COARSE_EXACT if info["n"] <= 8192 else hmg.COARSE_CG
+    for name, mode in (("exact" if base == hmg.COARSE_EXACT else "cg", base), ("smooth", hmg.COARSE_SMOOTH)):
         H.set_coarse(mode)
         ms, st = solve_ms()
         res[name] = {"solve_ms": ms, "iterations": st["iters"], "vcycle_ms": vcycle_ms()}
         log("learned: %s coarse solve: %.1f ms, %d iterations" % (name, ms, st["iters"]))
-    H.set_coarse(hmg.COARSE_EXACT)
+    H.set_coarse(base)
     # training pairs from the method's own V-cycles and exact coarse solves
     t0 = time.time()
     R = torch.zeros((samples, info["n"]), dtype=torch.float64, device="cuda")
@@ -356,7 +360,9 @@ def main():
     torch.cuda.set_device(0)
 
     if a.learned_only:
-        print(json.dumps(learned_bench()), flush=True)
+        res = {"coarse_12": learned_bench(),
+               "coarse_24": learned_bench(samples=1024, steps=2500, batch=32, grid=32, h_min=24)}
+        print(json.dumps(res), flush=True)
         return
 
     if a.multi_only:
