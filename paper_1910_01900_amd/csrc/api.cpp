@@ -1337,7 +1337,10 @@ extern "C" int hmg_hierarchy_coarse_solve_batch(const hmg_hierarchy* H, const do
   if (count == 0) return HMG_OK;
   TRY(check_ptr(R, "R"));
   TRY(check_ptr(E, "E"));
-  if ((const void*)R == (void*)E) return fail(HMG_ERR_INVALID, "R and E must not overlap");
+  {
+    const size_t len = (size_t)count * H->nc;
+    if (R < E + len && E < R + len) return fail(HMG_ERR_INVALID, "R and E must not overlap");
+  }
   if (H->dense) return coarse_gemm(H->ainv(), R, E, (int)H->nc, count, s);
   // no dense inverse: FP64 Jacobi-PCG on the FP64 coarse level, sample by sample
   hmg_hierarchy* Hm = const_cast<hmg_hierarchy*>(H);

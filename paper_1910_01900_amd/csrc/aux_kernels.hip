@@ -389,7 +389,9 @@ template <typename T>
 __global__ void k_ccg_xr(T* x, T* r, T* z, const T* p, const T* q, const T* dinv, int64_t n, const double* rz,
                          const double* pq, const int* skip) {
   if (*skip) return;
-  const T a = (T)(*rz / *pq);
+  // p.q = 0 only for p = 0 (b = 0, or a breakdown): no step, x stays
+  const double pqv = *pq;
+  const T a = pqv > 0 ? (T)(*rz / pqv) : T(0);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += a * p[i];
     const T ri = r[i] - a * q[i];
@@ -400,7 +402,8 @@ __global__ void k_ccg_xr(T* x, T* r, T* z, const T* p, const T* q, const T* dinv
 template <typename T>
 __global__ void k_ccg_p(T* p, const T* z, int64_t n, const double* rzn, const double* rz, const int* skip) {
   if (*skip) return;
-  const T beta = (T)(*rzn / *rz);
+  const double rzv = *rz;
+  const T beta = rzv != 0 ? (T)(*rzn / rzv) : T(0);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
 }

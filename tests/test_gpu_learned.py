@@ -263,10 +263,12 @@ def test_large_coarse_level_iterative_targets_and_learned_fallback():
     _, oc = meshes((24, 24, 24), 1, True, amp=0.05)
     A = ofe.assemble(oc, 1)
     free = ofe.free_mask(oc, 1)
-    R = np.stack([uniform(110 + i, 15625) * free for i in range(2)])
+    # (a zero right-hand side must give exactly zero, not 0/0 step sizes)
+    R = np.stack([uniform(110 + i, 15625) * free for i in range(2)] + [np.zeros(15625)])
     E = H.coarse_solve_batch(torch.as_tensor(R, device="cuda")).cpu().numpy()
     for i in range(2):
         assert np.linalg.norm(R[i] - A @ E[i]) <= 1e-9 * np.linalg.norm(R[i])
+    assert np.all(E[2] == 0)
     b = torch.as_tensor(uniform(6, H.n_dofs), device="cuda")
     H.set_coarse(hmg.COARSE_CG)
     _, st_cg = H.solve(b, rtol=1e-10, maxit=100)
@@ -284,6 +286,10 @@ def test_large_coarse_level_iterative_targets_and_learned_fallback():
     assert st["status"] == "HMG_OK" and st["rn"] <= 1e-10 * st["r0"]
     L64 = hmg.Level(hm)
     assert float(torch.linalg.norm(L64.residual(b, x)) / torch.linalg.norm(b)) <= 2e-10
+    # zero right-hand side: the judge rejects any nonzero correction and the
+    # iterative fallback keeps x = 0
+    z = H.vcycle(torch.zeros_like(b))
+    assert bool(torch.all(z == 0))
     # poisoned weights: the iterative coarse solve takes over every time
     net.set_params(torch.full((net.n_params,), float("nan"), dtype=torch.float32, device="cuda"))
     f1 = H.coarse_stats()
