@@ -320,9 +320,10 @@ __device__ __forceinline__ void nb_finish(const T* F, const T* LT, int t, const 
 // d-lines of the Gauss-point data R (u, du/dx, du/dy, du/dz), the flux, and
 // the face test coefficients: vt multiplies the test value, gt the test's
 // normal derivative (Sec. 2, SIPG flux with the mirror principle).
-template <int N, typename T, int d>
+template <int N, typename T, int d, bool PRE>
 __device__ __forceinline__ void own_flux(const OpArgs<T>& a, const T* R, int t, const ElemInfo& I,
-                                         const T (&un)[6], const T (&dnn)[6], T (&vt)[6], T (&gt)[6]) {
+                                         const T (&un)[6], const T (&dnn)[6], T (&vt)[6], T (&gt)[6],
+                                         T (&gc)[2][3]) {
   constexpr int N3 = N * N * N, NT = N * N;
   constexpr TabOff O(N);
   // global loads first: own-side metric, surface weights, penalties
@@ -360,6 +361,31 @@ __device__ __forceinline__ void own_flux(const OpArgs<T>& a, const T* R, int t, 
     const T w = neu ? T(0) : dA[s];
     vt[f] = (tau_face(te, tn[s], hf) * jump - avg) * w;
     gt[f] = T(-0.5) * jump * w;
+    if constexpr (PRE) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) gc[s][r] = co[s][r] * gt[f];
+    }
+  }
+}
+
+// Add the face tests of direction d to the d-lines of the integration
+// arrays from the products gc of the own-side metric and gt (no loads).
+template <int N, typename T, int d>
+__device__ __forceinline__ void inject_pre(const OpArgs<T>& a, const T (&vt)[6], const T (&gc)[2][3], T (&vq)[N],
+                                           T (&fx)[N], T (&fy)[N], T (&fz)[N]) {
+  constexpr TabOff O(N);
+  const cptr<T> c = fresh(a.tabs);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int f = 2 * d + s;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const T l = c[(s ? O.lg1() : O.lg0()) + m];
+      vq[m] += l * vt[f];
+      fx[m] += l * gc[s][0];
+      fy[m] += l * gc[s][1];
+      fz[m] += l * gc[s][2];
+    }
   }
 }
 
@@ -721,17 +747,22 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     }
     wave_sync();
     // ---- face fluxes (DG): own traces by extrapolation
+    // x- and y-face tests: the products of the own-side metric with gt are
+    // formed in the flux phase (the metric is in registers there), so the
+    // test phases need no second load of it
+    constexpr bool pre_gc = true;
     T vt[6], gt[6];
+    [[maybe_unused]] T gc0[2][3], gc1[2][3];
     if constexpr (!FE) {
 #pragma unroll
       for (int f = 0; f < 6; ++f) vt[f] = gt[f] = 0;
       // one direction per block (the fences keep the blocks from being
       // merged, which would put all three directions' data in flight)
-      if (act) own_flux<N, T, 0>(a, R, t, I, un, dnn, vt, gt);
+      if (act) own_flux<N, T, 0, pre_gc>(a, R, t, I, un, dnn, vt, gt, gc0);
       wave_sync();
-      if (act) own_flux<N, T, 1>(a, R, t, I, un, dnn, vt, gt);
+      if (act) own_flux<N, T, 1, pre_gc>(a, R, t, I, un, dnn, vt, gt, gc1);
       wave_sync();
-      if (act) own_flux<N, T, 2>(a, R, t, I, un, dnn, vt, gt);
+      if (act) own_flux<N, T, 2, false>(a, R, t, I, un, dnn, vt, gt, gc1);
       wave_sync();
     }
     // ---- quadrature-point operator on z-lines, z-face tests
@@ -764,7 +795,10 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         read_line<N, T, 0>(B, t, fx);
         read_line<N, T, 0>(Cc, t, fy);
         read_line<N, T, 0>(Dg, t, fz);
-        inject<N, T, 0>(a, I, t, vt, gt, vq, fx, fy, fz);
+        if constexpr (pre_gc)
+          inject_pre<N, T, 0>(a, vt, gc0, vq, fx, fy, fz);
+        else
+          inject<N, T, 0>(a, I, t, vt, gt, vq, fx, fy, fz);
         write_line<N, T, 0>(A, t, vq);
         write_line<N, T, 0>(B, t, fx);
         write_line<N, T, 0>(Cc, t, fy);
@@ -780,7 +814,10 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       if constexpr (!FE) {
         T vq[N];
         read_line<N, T, 1>(A, t, vq);
-        inject<N, T, 1>(a, I, t, vt, gt, vq, fx, fy, fz);
+        if constexpr (pre_gc)
+          inject_pre<N, T, 1>(a, vt, gc1, vq, fx, fy, fz);
+        else
+          inject<N, T, 1>(a, I, t, vt, gt, vq, fx, fy, fz);
         const cptr<T> c = fresh(a.tabs);
         eo_apply<N, T, 1>(c + O.eo(EO_ST), vq, cy);
       }
