@@ -751,8 +751,12 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // formed in the flux phase (the metric is in registers there), so the
     // test phases need no second load of it
     constexpr bool pre_gc = true;
+    // z faces: their tests join the metric phase, whose loads are one round
+    // trip anyway; the products save six loads there, and for n = 4, 6 they
+    // cost a wavefront per SIMD (FP32, n = 4) or spill (FP64, n = 6)
+    constexpr bool pre_gc_z = N == 5 || N >= 7;
     T vt[6], gt[6];
-    [[maybe_unused]] T gc0[2][3], gc1[2][3];
+    [[maybe_unused]] T gc0[2][3], gc1[2][3], gc2[2][3];
     if constexpr (!FE) {
 #pragma unroll
       for (int f = 0; f < 6; ++f) vt[f] = gt[f] = 0;
@@ -762,7 +766,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       wave_sync();
       if (act) own_flux<N, T, 1, pre_gc>(a, R, t, I, un, dnn, vt, gt, gc1);
       wave_sync();
-      if (act) own_flux<N, T, 2, false>(a, R, t, I, un, dnn, vt, gt, gc1);
+      if (act) own_flux<N, T, 2, pre_gc_z>(a, R, t, I, un, dnn, vt, gt, gc2);
       wave_sync();
     }
     // ---- quadrature-point operator on z-lines, z-face tests
@@ -781,7 +785,12 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         fz[m] = g02 * gx + g12 * gy + g22 * g3;
         vq[m] = 0;
       }
-      if constexpr (!FE) inject<N, T, 2>(a, I, t, vt, gt, vq, fx, fy, fz);
+      if constexpr (!FE) {
+        if constexpr (pre_gc_z)
+          inject_pre<N, T, 2>(a, vt, gc2, vq, fx, fy, fz);
+        else
+          inject<N, T, 2>(a, I, t, vt, gt, vq, fx, fy, fz);
+      }
       if constexpr (!FE) write_line<N, T, 2>(A, t, vq);
       write_line<N, T, 2>(B, t, fx);
       write_line<N, T, 2>(Cc, t, fy);
