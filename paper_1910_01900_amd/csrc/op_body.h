@@ -585,7 +585,14 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   const int nload = (int)(left <= 0 ? 0 : (left < EW ? left : EW)) * N3;
   const int ta = t % N, tbb = t / N;
 
-  // ---- neighbour traces (curved DG), before the own data occupies LDS
+  // ---- neighbour traces (curved DG), before the own data occupies LDS.
+  // For n >= 7 and FP64 n = 5 the own values are loaded into registers with
+  // the neighbour data (one round trip for both) and go to LDS once the
+  // neighbour phase is done; elsewhere the registers would cost a wavefront
+  // per SIMD or spill.
+  constexpr int OWN_PER_LANE = (EW * N3 + 63) / 64;
+  constexpr bool early_own = CURVED && !FE && (N >= 7 || (N == 5 && sizeof(T) == 8));
+  [[maybe_unused]] T own[OWN_PER_LANE];
   T un[6], dnn[6];
   if constexpr (CURVED && !FE) {
     // neighbour-side face metric: for n = 5, 7, 8 loaded with the
@@ -594,6 +601,14 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // cost a wavefront per SIMD, so it is loaded after them
     constexpr bool early_cn = N == 5 || N >= 7;
     T cn[6][3];
+    if constexpr (early_own) {
+#pragma unroll
+      for (int j = 0; j < OWN_PER_LANE; ++j) {
+        const int idx = lane + 64 * j;
+        const int li = idx / N3;
+        own[j] = idx < nload ? a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)] : T(0);
+      }
+    }
     {  // neighbour lines of all six faces: end value P, normal derivative Q
       T nl[6][N];
       load_nb_lines<N, T, 0>(a, ub, I, t, nl[0], nl[1]);
@@ -658,7 +673,17 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   }
 
   // ---- own element data into LDS (coalesced per wavefront)
-  if constexpr (!FE) {
+  if constexpr (early_own) {
+#pragma unroll
+    for (int j = 0; j < OWN_PER_LANE; ++j) {
+      const int idx = lane + 64 * j;
+      if (idx < nload) {
+        const int li = idx / N3;
+        W0[li * PER + (idx - li * N3)] = own[j];
+        if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = own[j];
+      }
+    }
+  } else if constexpr (!FE) {
     for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3;
       const T v = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
