@@ -148,15 +148,45 @@ __device__ __forceinline__ int lidx(int t, int m) {
   return t + NT * m;
 }
 
+// Position of node (i, j, l) of an element in its LDS arrays.  For n = 8
+// the x index is XOR-swizzled with (j + l) mod 8: the 64 lanes of an x-line
+// access (one i, all j, l) then spread over the banks instead of meeting 8
+// at a time on the same bank (x-lines are 8 values apart), and y and z line
+// accesses stay at most two-way conflicted.  Other degrees keep the plain
+// x-fastest order, whose line accesses are already at most two-way.
+template <int N>
+__device__ __forceinline__ int vpos(int i, int j, int l) {
+  if constexpr (N == 8)
+    return (i ^ ((j + l) & 7)) + N * j + N * N * l;
+  else
+    return i + N * j + N * N * l;
+}
+// LDS position of node p (x-fastest index) of an element.
+template <int N>
+__device__ __forceinline__ int vpos_of(int p) {
+  if constexpr (N == 8)
+    return vpos<N>(p & 7, (p >> 3) & 7, p >> 6);
+  else
+    return p;
+}
+// LDS position of point m on the line of lane t along direction d.
+template <int N, int d>
+__device__ __forceinline__ int sidx(int t, int m) {
+  if constexpr (N != 8) return lidx<N, d>(t, m);
+  if constexpr (d == 0) return vpos<N>(m, t % N, t / N);
+  if constexpr (d == 1) return vpos<N>(t % N, m, t / N);
+  return vpos<N>(t % N, t / N, m);
+}
+
 template <int N, typename T, int d>
 __device__ __forceinline__ void read_line(const T* A, int t, T (&x)[N]) {
 #pragma unroll
-  for (int m = 0; m < N; ++m) x[m] = A[lidx<N, d>(t, m)];
+  for (int m = 0; m < N; ++m) x[m] = A[sidx<N, d>(t, m)];
 }
 template <int N, typename T, int d>
 __device__ __forceinline__ void write_line(T* A, int t, const T (&x)[N]) {
 #pragma unroll
-  for (int m = 0; m < N; ++m) A[lidx<N, d>(t, m)] = x[m];
+  for (int m = 0; m < N; ++m) A[sidx<N, d>(t, m)] = x[m];
 }
 
 // y = A x with A given by its even-odd packing c (see TabOff); SIG = +1 for
@@ -679,7 +709,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       const int idx = lane + 64 * j;
       if (idx < nload) {
         const int li = idx / N3;
-        W0[li * PER + (idx - li * N3)] = own[j];
+        W0[li * PER + vpos_of<N>(idx - li * N3)] = own[j];
         if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = own[j];
       }
     }
@@ -687,7 +717,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3;
       const T v = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
-      W0[li * PER + (idx - li * N3)] = v;
+      W0[li * PER + vpos_of<N>(idx - li * N3)] = v;
       if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = v;
     }
   } else {
@@ -705,7 +735,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       const int m = a.bcmask;
       const bool fixed = (gx == 0 && !(m & 1)) || (gx == Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
                          (gy == My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == Mz - 1 && !(m & 32));
-      W0[li * PER + p] = fixed ? T(0) : a.u[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
+      W0[li * PER + vpos_of<N>(p)] = fixed ? T(0) : a.u[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
     }
   }
   wave_sync();
@@ -840,7 +870,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       const T* G = a.metric + e * 6 * N3 + t;
 #pragma unroll
       for (int m = 0; m < N; ++m) {
-        const int o = t + NT * m;
+        const int o = sidx<N, 2>(t, m);
         const T gx = B[o], gy = Cc[o], g3 = Dg[o];
         const T* Gm = G + NT * m;
         // stored order 00, 11, 22, 01, 02, 12
@@ -940,7 +970,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   double acc = 0.0;
   for (int idx = lane; idx < nload; idx += 64) {
     const int li = idx / N3;
-    const T val = W0[li * PER + (idx - li * N3)];
+    const T val = W0[li * PER + vpos_of<N>(idx - li * N3)];
     const int64_t item = it0 + li;
     const int64_t el = a.nrhs == 1 ? item : item / a.nrhs;
     const int64_t gv = el * N3 + (idx - li * N3);  // offset inside one vector
