@@ -58,6 +58,14 @@ struct Cfg {
   static constexpr int WPE = N >= 7 ? 2 : 3;  // per-wavefront copy of S, Sp, M, l'(0), l'(1)
 };
 
+// Minimum waves per SIMD the register allocation of the (N, T) kernel must
+// allow: Cfg::WPE, and four for the FP32 curvilinear DG kernels at n >= 7,
+// whose LDS use allows four workgroups per CU.
+template <int N, typename T, bool CURVED, bool FE>
+constexpr int op_wpe() {
+  return (CURVED && !FE && N >= 7 && sizeof(T) == 4) ? 4 : Cfg<N, CURVED, FE>::WPE;
+}
+
 // Whether the epilogue of MODE reads the input vector again (Chebyshev
 // update, u.(A u)) and the wavefront keeps its own input values in LDS
 // instead of reading them from memory a second time: only where the extra

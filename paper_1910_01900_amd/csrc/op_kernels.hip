@@ -9,7 +9,7 @@ namespace hmg {
 #ifndef HMG_DISPATCH_ONLY
 // ------------------------------------------------------------------ single mesh
 template <int N, typename T, bool CURVED, bool FE, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<N, CURVED, FE>::WPE)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(op_wpe<N, T, CURVED, FE>())))
 op_kernel(const OpArgs<T> a) {
   using C = Cfg<N, CURVED, FE>;
   if constexpr (FE) {
