@@ -698,11 +698,11 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   }
 
 
-  // own-side face data: for n = 5 each direction's is loaded a phase ahead
-  // of its use, those of the x faces with the own values (1.4% faster; for
-  // n = 3, 4, 6 the registers cost a wavefront per SIMD, for n = 7, 8 it
-  // is slower); otherwise in the phase that uses it
-  constexpr bool pf_faces = N == 5;
+  // own-side face data: for n = 5 and 8 each direction's is loaded a phase
+  // ahead of its use, those of the x faces with the own values (1-2%
+  // faster; for n = 3, 4, 6 the registers cost a wavefront per SIMD);
+  // otherwise in the phase that uses it
+  constexpr bool pf_faces = N == 5 || N == 8;
   [[maybe_unused]] OwnFace<T> F0, F1, F2;
   [[maybe_unused]] T te = 0;
   if constexpr (CURVED && !FE && pf_faces) {
