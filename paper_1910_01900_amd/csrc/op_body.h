@@ -624,12 +624,12 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   const int ta = t % N, tbb = t / N;
 
   // ---- neighbour traces (curved DG), before the own data occupies LDS.
-  // For n >= 7 and FP64 n = 5 the own values are loaded into registers with
-  // the neighbour data (one round trip for both) and go to LDS once the
-  // neighbour phase is done; elsewhere the registers would cost a wavefront
-  // per SIMD or spill.
+  // For n >= 7 and FP64 n = 5, 6 the own values are loaded into registers
+  // with the neighbour data (one round trip for both) and go to LDS once the
+  // neighbour phase is done (FP64 n = 6: 8% faster despite three spilled
+  // registers); elsewhere the registers would cost a wavefront per SIMD.
   constexpr int OWN_PER_LANE = (EW * N3 + 63) / 64;
-  constexpr bool early_own = CURVED && !FE && (N >= 7 || (N == 5 && sizeof(T) == 8));
+  constexpr bool early_own = CURVED && !FE && (N >= 7 || ((N == 5 || N == 6) && sizeof(T) == 8));
   [[maybe_unused]] T own[OWN_PER_LANE];
   T un[6], dnn[6];
   if constexpr (CURVED && !FE) {

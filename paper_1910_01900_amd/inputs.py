@@ -30,6 +30,7 @@ WORKLOADS = {
     "cube_k3_8": dict(nel=(8, 8, 8), degree=3, deformed=False, amp=0.0, tau_scale_seed=None),
     "curved_k4_64": dict(nel=(64, 64, 64), degree=4, deformed=True, amp=0.05, tau_scale_seed=None),
     "curved_k7_48": dict(nel=(48, 48, 48), degree=7, deformed=True, amp=0.05, tau_scale_seed=5),
+    "curved_k5_48": dict(nel=(48, 48, 48), degree=5, deformed=True, amp=0.05, tau_scale_seed=None),
 }
 
 
