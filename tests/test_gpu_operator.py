@@ -78,6 +78,22 @@ def test_fe_apply_matches_oracle(k, deformed):
     assert np.all(np.abs(v - ref) <= 1e-12 * (abs(A) @ np.abs(u)))
 
 
+@pytest.mark.parametrize("k", [3, 7])
+@pytest.mark.parametrize("deformed", [False, True])
+def test_fe_apply_degrees_3_and_7(k, deformed):
+    """FE levels of degree 3 and 7 (degree 7: the XOR-swizzled LDS layout on
+    the gather path) on 18 elements: 4.5 workgroups at one element per
+    wavefront (k = 7), a ragged tail."""
+    hm, om = meshes((3, 2, 3), k, deformed, bc=(0, 1, 0, 0, 1, 0))
+    L = hmg.Level(hm, space=hmg.FE)
+    u = uniform(3, L.n_dofs)
+    v = to_np(L.apply(L.vector(u)))
+    A = ofe.assemble(om, k)
+    ref = A @ u
+    assert rel_inf(v, ref) < 1e-12
+    assert np.all(np.abs(v - ref) <= 1e-12 * (abs(A) @ np.abs(u)))
+
+
 @pytest.mark.parametrize("space", [hmg.DG, hmg.FE])
 @pytest.mark.parametrize("deformed", [False, True])
 def test_diagonal_matches_oracle(space, deformed):
