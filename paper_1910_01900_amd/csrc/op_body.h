@@ -699,9 +699,9 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
 
 
   // own-side face data: for n = 5 and 8 each direction's is loaded a phase
-  // ahead of its use, those of the x faces with the own values (1-2%
-  // faster; for n = 3, 4, 6 the registers cost a wavefront per SIMD);
-  // otherwise in the phase that uses it
+  // ahead of its use, those of the x faces in the phase that moves the own
+  // values to LDS (1-2% faster; for n = 3, 4, 6 the registers cost a
+  // wavefront per SIMD); otherwise in the phase that uses it
   constexpr bool pf_faces = N == 5 || N == 8;
   [[maybe_unused]] OwnFace<T> F0, F1, F2;
   [[maybe_unused]] T te = 0;
@@ -841,14 +841,13 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // ---- face fluxes (DG): own traces by extrapolation
     // x- and y-face tests: the products of the own-side metric with gt are
     // formed in the flux phase (the metric is in registers there), so the
-    // test phases need no second load of it
-    constexpr bool pre_gc = true;
-    // z faces: their tests join the metric phase, whose loads are one round
+    // test phases need no second load of it.  z faces: their tests join the metric phase, whose loads are one round
     // trip anyway; the products save six loads there, and for n = 4, 6 they
     // cost a wavefront per SIMD (FP32, n = 4) or spill (FP64, n = 6)
     constexpr bool pre_gc_z = N == 5 || N >= 7;
     T vt[6], gt[6];
-    [[maybe_unused]] T gc0[2][3], gc1[2][3], gc2[2][3];
+    T gc0[2][3], gc1[2][3];
+    [[maybe_unused]] T gc2[2][3];
     if constexpr (!FE) {
 #pragma unroll
       for (int f = 0; f < 6; ++f) vt[f] = gt[f] = 0;
@@ -860,13 +859,13 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         F0 = load_own_face<N, T, 0>(a, I, t);
         te = a.tau[I.e];
       }
-      if (act) own_flux<N, T, 0, pre_gc>(a, F0, te, R, t, I, un, dnn, vt, gt, gc0);
+      if (act) own_flux<N, T, 0, true>(a, F0, te, R, t, I, un, dnn, vt, gt, gc0);
       wave_sync();
       if constexpr (pf_faces)
         F2 = load_own_face<N, T, 2>(a, I, t);
       else
         F1 = load_own_face<N, T, 1>(a, I, t);
-      if (act) own_flux<N, T, 1, pre_gc>(a, F1, te, R, t, I, un, dnn, vt, gt, gc1);
+      if (act) own_flux<N, T, 1, true>(a, F1, te, R, t, I, un, dnn, vt, gt, gc1);
       wave_sync();
       if constexpr (!pf_faces) F2 = load_own_face<N, T, 2>(a, I, t);
       if (act) own_flux<N, T, 2, pre_gc_z>(a, F2, te, R, t, I, un, dnn, vt, gt, gc2);
@@ -907,10 +906,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         read_line<N, T, 0>(B, t, fx);
         read_line<N, T, 0>(Cc, t, fy);
         read_line<N, T, 0>(Dg, t, fz);
-        if constexpr (pre_gc)
-          inject_pre<N, T, 0>(a, vt, gc0, vq, fx, fy, fz);
-        else
-          inject<N, T, 0>(a, I, t, vt, gt, vq, fx, fy, fz);
+        inject_pre<N, T, 0>(a, vt, gc0, vq, fx, fy, fz);
         write_line<N, T, 0>(A, t, vq);
         write_line<N, T, 0>(B, t, fx);
         write_line<N, T, 0>(Cc, t, fy);
@@ -926,10 +922,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       if constexpr (!FE) {
         T vq[N];
         read_line<N, T, 1>(A, t, vq);
-        if constexpr (pre_gc)
-          inject_pre<N, T, 1>(a, vt, gc1, vq, fx, fy, fz);
-        else
-          inject<N, T, 1>(a, I, t, vt, gt, vq, fx, fy, fz);
+        inject_pre<N, T, 1>(a, vt, gc1, vq, fx, fy, fz);
         const cptr<T> c = fresh(a.tabs);
         eo_apply<N, T, 1>(c + O.eo(EO_ST), vq, cy);
       }
