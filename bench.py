@@ -13,9 +13,12 @@ HIP graphs (--no-graph: eager launches, the same results bit for bit).
 own with HIP events on the launch stream (operator_apply, roofline).
 
 The plain FP64 solve (the same hierarchy with an FP64 V-cycle) is timed
-after the timed region and reported beside it.  `roofline.traffic` is read
-from the committed counter summary of the FP64 apply kernel when that
-summary was taken on the current kernel source, else null.
+after the timed region and reported beside it.  `roofline.traffic` (HBM
+bytes per launch) and `roofline.fp64_flops` (executed FP64 arithmetic per
+launch, timed with the same live launch duration) are read from the
+committed counter summary of the FP64 apply kernel when that summary was
+taken on the current kernel source; else traffic is null and fp64_flops
+absent.
 
 After the timed region, the 64-mesh batch multi_64 (64 Cartesian unit cubes
 with N_i^3 elements, N_i ~ U{4..24}, degree k_i ~ U{2..7}, 4 vectors each)
@@ -39,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DoF/s of SIPG operator apply (FP64/FP32); solve time per DoF at 1e-10 rel. residual"
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
 
 
 def log(*a):
@@ -74,10 +78,10 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the FP64 apply kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when there is none for this
-    workload or it was taken on a different kernel source."""
+def _pmc_field(workload, name):
+    """A per-launch figure of the FP64 apply kernel from the committed counter
+    summary, or None when there is none for this workload or it was taken on
+    a different kernel source."""
     if workload != "curved_k4_64" or not os.path.exists(PMC_SUMMARY):
         return None
     fields = {}
@@ -88,9 +92,20 @@ def measured_traffic(workload):
     if fields.get("kernel_source_sha256") != kernel_source_sha():
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[name])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch (FETCH_SIZE / WRITE_SIZE passes)."""
+    return _pmc_field(workload, "traffic_bytes_per_launch")
+
+
+def measured_fp64_flops(workload):
+    """Executed FP64 VALU flops per launch (SQ_INSTS_VALU_{FMA,MUL,ADD}_F64
+    passes, times the active lanes per wavefront)."""
+    return _pmc_field(workload, "fp64_flops_per_launch")
 
 
 def time_applies(L, u, v, reps):
@@ -506,6 +521,11 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(a.workload),
                      "algorithmic_bytes_per_launch": bytes64},
     }
+    flops = measured_fp64_flops(a.workload)
+    if flops is not None:  # executed FP64 arithmetic of the same kernel, same live timing
+        tf = flops / (ms64 * 1e-3) / 1e12
+        out["roofline"]["fp64_flops"] = {"achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": tf / PEAK_FP64_TFLOPS, "per_launch": flops}
     if plain is not None:
         out["solve_plain_fp64"] = plain
     if batched is not None:
