@@ -841,9 +841,10 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // ---- face fluxes (DG): own traces by extrapolation
     // x- and y-face tests: the products of the own-side metric with gt are
     // formed in the flux phase (the metric is in registers there), so the
-    // test phases need no second load of it.  z faces: their tests join the metric phase, whose loads are one round
-    // trip anyway; the products save six loads there, and for n = 4, 6 they
-    // cost a wavefront per SIMD (FP32, n = 4) or spill (FP64, n = 6)
+    // test phases need no second load of it.  z faces: their tests join the
+    // metric phase, whose loads are one round trip anyway; the products save
+    // six loads there, and for n = 4, 6 they cost a wavefront per SIMD
+    // (FP32, n = 4) or spill (FP64, n = 6)
     constexpr bool pre_gc_z = N == 5 || N >= 7;
     T vt[6], gt[6];
     T gc0[2][3], gc1[2][3];
@@ -881,7 +882,8 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         const T gx = B[o], gy = Cc[o], g3 = Dg[o];
         const T* Gm = G + NT * m;
         // stored order 00, 11, 22, 01, 02, 12
-                const T g00 = Gm[0], g11 = Gm[N3], g22 = Gm[2 * N3], g01 = Gm[3 * N3], g02 = Gm[4 * N3], g12 = Gm[5 * N3];
+        const T g00 = Gm[0], g11 = Gm[N3], g22 = Gm[2 * N3];
+        const T g01 = Gm[3 * N3], g02 = Gm[4 * N3], g12 = Gm[5 * N3];
         fx[m] = g00 * gx + g01 * gy + g02 * g3;
         fy[m] = g01 * gx + g11 * gy + g12 * g3;
         fz[m] = g02 * gx + g12 * gy + g22 * g3;
