@@ -43,3 +43,24 @@ def test_agrees_with_the_oracle_pins():
         t = tab[o["cite"].split(" (")[0]]
         for key in ("n10", "strategy", "pseq", "ip", "N", "k", "curved"):
             assert t[key] == o[key], (o["cite"], key)
+
+
+def test_one_element_curvilinear_sipg_is_indefinite():
+    """Why the curvilinear DG-to-one-element cases are not compared: on the
+    deformed cube as one element (the coarsest h-level), the oracle's SIPG
+    matrix with the paper's penalty is indefinite at k = 1 (and definite at
+    k = 2), so no coarse solve of that level can be the paper's."""
+    import numpy as np
+    from oracle import mesh as om
+    from oracle import sipg
+    m = om.BoxMesh((1, 1, 1), lo=(-1.0,) * 3, hi=(1.0,) * 3, deform=0.15, waves=2)
+    for k, definite in ((1, False), (2, True)):
+        A = sipg.assemble(m, k)
+        A = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+        lo = np.linalg.eigvalsh(0.5 * (A + A.T))[0]
+        assert (lo > 0) == definite, (k, lo)
+    # two elements per direction: definite
+    m2 = om.BoxMesh((2, 2, 2), lo=(-1.0,) * 3, hi=(1.0,) * 3, deform=0.15, waves=2)
+    A = sipg.assemble(m2, 1)
+    A = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    assert np.linalg.eigvalsh(0.5 * (A + A.T))[0] > 0
