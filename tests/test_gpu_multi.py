@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 # (nel, k, deformed): ragged sizes, every degree, both geometry kinds
 MIXED = [((3, 2, 2), 1, False), ((4, 3, 5), 2, False), ((2, 2, 2), 3, True), ((3, 3, 2), 4, False),
          ((2, 3, 2), 5, True), ((2, 2, 2), 7, False), ((5, 4, 3), 2, False), ((1, 1, 1), 6, False),
-         ((3, 1, 2), 6, True), ((2, 2, 3), 3, False)]
+         ((3, 1, 2), 6, True), ((2, 2, 3), 3, False), ((2, 3, 3), 4, True), ((2, 1, 3), 7, True)]
 CARTESIAN = [m for m in MIXED if not m[2]]
 SENTINEL = 7.0
 
