@@ -200,14 +200,22 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(WgradArgs a) {
 }
 
 // grad_w[co][kk] = sum over chunks (fixed order); grad_b[co] = sum_P dz[P][co].
-__global__ void k_wgrad_reduce(const float* part, int nchunk, int cout, int cout_pad, int kpad, int K,
-                               float* gw) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cout * K) return;
-  const int co = i / K, kk = i - co * K;
+// gw[co][kk] = sum over chunks of part[chunk][co][kk]: 64 weights per
+// workgroup, its four wavefronts taking every fourth chunk, combined in a
+// fixed order (deterministic).
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* part, int nchunk, int cout, int cout_pad,
+                                                      int kpad, int K, float* gw) {
+  __shared__ float red[256];
+  const int w = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + w;
   float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * cout_pad + co) * kpad + kk];
-  gw[i] = s;
+  if (i < cout * K) {
+    const int co = i / K, kk = i - co * K;
+    for (int c = g; c < nchunk; c += 4) s += part[((int64_t)c * cout_pad + co) * kpad + kk];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && i < cout * K) gw[i] = (red[w] + red[w + 64]) + (red[w + 128] + red[w + 192]);
 }
 // Bias gradient in two fixed-order stages: part[blk][co] = sum of dz over
 // the 256 points of block blk (tile staged in LDS, coalesced), then
@@ -226,12 +234,19 @@ __global__ void __launch_bounds__(256) k_bias_part(const float* dz, int P, int c
     part[(int64_t)blockIdx.x * cout + threadIdx.x] = s;
   }
 }
-__global__ void k_bias_reduce(const float* part, int nb, int cout, float* gb) {
-  const int co = threadIdx.x;
-  if (co >= cout) return;
+// One workgroup per channel: strided partial sums, then a fixed-order tree.
+__global__ void __launch_bounds__(256) k_bias_reduce(const float* part, int nb, int cout, float* gb) {
+  __shared__ float red[256];
+  const int co = blockIdx.x;
   float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * cout + co];
-  gb[co] = s;
+  for (int b = threadIdx.x; b < nb; b += 256) s += part[(int64_t)b * cout + co];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gb[co] = red[0];
 }
 
 // BF16 weight matrices from the FP32 parameters w[co][t][ci]:
@@ -405,11 +420,12 @@ int net_wgrad(const WgradArgs& a, float* gw, float* gb, hipStream_t s) {
   hipLaunchKernelGGL(k_conv_wgrad, dim3((unsigned)((ntiles + per_wg - 1) / per_wg), (unsigned)a.nchunk), 256, 0, s,
                      a);
   const int K = 27 * a.cin;
-  hipLaunchKernelGGL(k_wgrad_reduce, blocks((int64_t)a.cout * K), 256, 0, s, a.part, a.nchunk, a.cout, a.cout_pad,
+  hipLaunchKernelGGL(k_wgrad_reduce, (unsigned)(((int64_t)a.cout * K + 63) / 64), 256, 0, s, a.part, a.nchunk,
+                     a.cout, a.cout_pad,
                      a.kpad, K, gw);
   const unsigned nb = (unsigned)((a.P + 255) / 256);
   hipLaunchKernelGGL(k_bias_part, nb, 256, 0, s, a.dz, a.P, a.cout, a.bpart);
-  hipLaunchKernelGGL(k_bias_reduce, 1, 64, 0, s, a.bpart, (int)nb, a.cout, gb);
+  hipLaunchKernelGGL(k_bias_reduce, (unsigned)a.cout, 256, 0, s, a.bpart, (int)nb, a.cout, gb);
   return check_launch("k_conv_wgrad");
 }
 int net_weight_prep(const float* w, int cin, int cout, uint16_t* wf, int cout_pad, int kpad_f, uint16_t* wt,
