@@ -61,7 +61,9 @@ const char* hmg_last_error(void);
 
 /* Library version: major*10000 + minor*100 + patch.  0.1.0 (100): levels,
  * transfers, hierarchy, PCG; 0.2.0 (200): several vectors per launch,
- * recorded graphs, multi-mesh batches, the learned coarse correction. */
+ * recorded graphs, multi-mesh batches, the learned coarse correction;
+ * 0.3.0 (300): the iterative coarse solve (HMG_COARSE_CG,
+ * hmg_hierarchy_set_coarse_cg) for coarse levels without a dense inverse. */
 int hmg_version(void);
 
 /*

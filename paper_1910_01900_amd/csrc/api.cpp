@@ -215,7 +215,7 @@ void cheb_coeffs(int ns, double lmax, double lof, double hif, std::vector<double
 using namespace hmg;
 
 extern "C" const char* hmg_last_error(void) { return g_err.c_str(); }
-extern "C" int hmg_version(void) { return 200; }
+extern "C" int hmg_version(void) { return 300; }
 
 // ================================================================== levels
 static int level_init(const Mesh& m, int space, int prec, hmg_level** out) {

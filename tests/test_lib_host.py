@@ -18,7 +18,7 @@ def test_exports_every_declared_symbol():
     assert len(declared) >= 25
     missing = [s for s in declared if s not in exported]
     assert not missing, missing
-    assert hmg.lib().hmg_version() == 200
+    assert hmg.lib().hmg_version() == 300
 
 
 def _create(mesh, space=hmg.DG, prec=hmg.F64):
