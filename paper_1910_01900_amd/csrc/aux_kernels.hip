@@ -540,13 +540,15 @@ __device__ __forceinline__ void tr_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, bool RESTRICT>
+// NF, NC > 0: the node counts at compile time (unrolled 1-D products, the
+// line arrays in registers); 0: taken from the arguments.
+template <typename T, bool RESTRICT, int NF, int NC>
 __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* out, int add) {
   constexpr int BUF = kTrBytes / (int)sizeof(T);
   __shared__ T buf[4][2][BUF];
   __shared__ T Pl[4][2 * kMaxN * kMaxN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nf = a.nf, nc = a.nc;
+  const int nf = NF ? NF : a.nf, nc = NC ? NC : a.nc;
   const int ni = RESTRICT ? nf : nc, no = RESTRICT ? nc : nf;
   const int ni2 = ni * ni, ni3 = ni2 * ni, no2 = no * no, no3 = no2 * no;
   const int W = a.W;
@@ -680,6 +682,25 @@ static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double
   return a;
 }
 
+// Launch with compile-time node counts for the (fine, coarse) pairs the
+// hierarchies use (p: n -> n-1, n -> floor(k/2)+1, n -> 2; h and c: n -> n),
+// the generic kernel otherwise.
+template <typename T, bool R>
+static void launch_transfer(int nf, int nc, unsigned g, const TrArgs<T>& a, const T* in, T* out, int add,
+                            hipStream_t s) {
+#define HMG_TR(F, C)                                                                  \
+  if (nf == F && nc == C) {                                                           \
+    hipLaunchKernelGGL((k_transfer<T, R, F, C>), g, 256, 0, s, a, in, out, add); \
+    return;                                                                           \
+  }
+  HMG_TR(2, 2) HMG_TR(3, 3) HMG_TR(4, 4) HMG_TR(5, 5) HMG_TR(6, 6) HMG_TR(7, 7) HMG_TR(8, 8)
+  HMG_TR(3, 2) HMG_TR(4, 3) HMG_TR(5, 4) HMG_TR(6, 5) HMG_TR(7, 6) HMG_TR(8, 7)
+  HMG_TR(4, 2) HMG_TR(5, 3) HMG_TR(6, 3) HMG_TR(7, 4) HMG_TR(8, 4)
+  HMG_TR(5, 2) HMG_TR(6, 2) HMG_TR(7, 2) HMG_TR(8, 2)
+#undef HMG_TR
+  hipLaunchKernelGGL((k_transfer<T, R, 0, 0>), g, 256, 0, s, a, in, out, add);
+}
+
 int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
                      const double* P1, const void* coarse, void* fine, int add, hipStream_t s) {
   const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
@@ -688,11 +709,11 @@ int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const 
   if (prec == HMG_F64) {
     auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1, false);
     const unsigned g = (unsigned)((nel_f + 4 * a.W - 1) / (4 * a.W));
-    hipLaunchKernelGGL((k_transfer<double, false>), g, 256, 0, s, a, (const double*)coarse, (double*)fine, add);
+    launch_transfer<double, false>(nf, nc, g, a, (const double*)coarse, (double*)fine, add, s);
   } else {
     auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1, false);
     const unsigned g = (unsigned)((nel_f + 4 * a.W - 1) / (4 * a.W));
-    hipLaunchKernelGGL((k_transfer<float, false>), g, 256, 0, s, a, (const float*)coarse, (float*)fine, add);
+    launch_transfer<float, false>(nf, nc, g, a, (const float*)coarse, (float*)fine, add, s);
   }
   return check_launch("tr_prolong");
 }
@@ -705,11 +726,11 @@ int tr_dg_restrict(int prec, int kind, int nf, int nc, const int Nf[3], const do
   if (prec == HMG_F64) {
     auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1, true);
     const unsigned g = (unsigned)((nel_c + 4 * a.W - 1) / (4 * a.W));
-    hipLaunchKernelGGL((k_transfer<double, true>), g, 256, 0, s, a, (const double*)fine, (double*)coarse, 0);
+    launch_transfer<double, true>(nf, nc, g, a, (const double*)fine, (double*)coarse, 0, s);
   } else {
     auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1, true);
     const unsigned g = (unsigned)((nel_c + 4 * a.W - 1) / (4 * a.W));
-    hipLaunchKernelGGL((k_transfer<float, true>), g, 256, 0, s, a, (const float*)fine, (float*)coarse, 0);
+    launch_transfer<float, true>(nf, nc, g, a, (const float*)fine, (float*)coarse, 0, s);
   }
   return check_launch("tr_restrict");
 }
