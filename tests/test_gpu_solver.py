@@ -13,14 +13,14 @@ from paper_1910_01900_amd.inputs import uniform
 pytestmark = pytest.mark.gpu
 
 
-def _transfer_case(kind, space, kf, kc, nel_f, nel_c, deformed):
+def _transfer_case(kind, space, kf, kc, nel_f, nel_c, deformed, prec=hmg.F64):
     hf, of = meshes(nel_f, kf, deformed, bc=(0, 1, 0, 0, 1, 0))
     hc, oc = meshes(nel_c, kc, deformed, bc=(0, 1, 0, 0, 1, 0))
     if kind == "c":
-        F, Cl = hmg.Level(hf), hmg.Level(hc, space=hmg.FE)
+        F, Cl = hmg.Level(hf, prec=prec), hmg.Level(hc, space=hmg.FE, prec=prec)
         P = transfer.c_prolongation(of, kf)
     else:
-        F, Cl = hmg.Level(hf, space=space), hmg.Level(hc, space=space)
+        F, Cl = hmg.Level(hf, space=space, prec=prec), hmg.Level(hc, space=space, prec=prec)
         if kind == "p":
             P = transfer.dg_p(of, kf, kc) if space == hmg.DG else transfer.fe_p(of, kf, kc)
         else:
@@ -47,6 +47,45 @@ def test_transfers_match_oracle(kind, space, kf, kc, nel_f, nel_c):
     assert rel_inf(to_np(f), f0 + P @ c) < 1e-13
     r = uniform(22, F.n_dofs)
     assert rel_inf(to_np(T.restrict(F.vector(r))), P.T @ r) < 1e-13
+
+
+# node-count pairs outside the hierarchies' p-sequences (k -> k-1, floor(k/2),
+# 1): the transfer kernel with run-time node counts
+@pytest.mark.parametrize("kind,space,kf,kc,nel_f", [
+    ("p", hmg.DG, 7, 2, (3, 2, 3)),
+    ("p", hmg.DG, 5, 3, (2, 3, 2)),
+    ("p", hmg.DG, 7, 4, (2, 2, 3)),
+    ("p", hmg.FE, 6, 4, (2, 3, 2)),
+])
+def test_transfers_other_degree_pairs_match_oracle(kind, space, kf, kc, nel_f):
+    F, Cl, T, P = _transfer_case(kind, space, kf, kc, nel_f, nel_f, True)
+    c = uniform(23, Cl.n_dofs)
+    f0 = uniform(24, F.n_dofs)
+    f = F.vector(f0)
+    T.prolongate_add(Cl.vector(c), f)
+    assert rel_inf(to_np(f), f0 + P @ c) < 1e-13
+    r = uniform(25, F.n_dofs)
+    assert rel_inf(to_np(T.restrict(F.vector(r))), P.T @ r) < 1e-13
+
+
+@pytest.mark.parametrize("kind,space,kf,kc,nel_f,nel_c", [
+    ("p", hmg.DG, 7, 3, (2, 2, 3), (2, 2, 3)),
+    ("h", hmg.DG, 5, 5, (4, 2, 2), (2, 1, 1)),
+    ("p", hmg.DG, 6, 3, (2, 2, 3), (2, 2, 3)),
+    ("p", hmg.FE, 4, 2, (3, 2, 3), (3, 2, 3)),
+    ("p", hmg.DG, 7, 2, (3, 2, 3), (3, 2, 3)),
+])
+def test_transfers_fp32_match_oracle(kind, space, kf, kc, nel_f, nel_c):
+    # FP32 data and FP32-rounded 1-D matrices; sums of at most n^3 products
+    F, Cl, T, P = _transfer_case(kind, space, kf, kc, nel_f, nel_c, True, prec=hmg.F32)
+    c = uniform(26, Cl.n_dofs)
+    f0 = uniform(27, F.n_dofs)
+    f = F.vector(f0)
+    T.prolongate_add(Cl.vector(c), f)
+    ref = f0.astype(np.float32).astype(np.float64) + P @ c.astype(np.float32).astype(np.float64)
+    assert rel_inf(to_np(f), ref) < 2e-6
+    r = uniform(28, F.n_dofs).astype(np.float32).astype(np.float64)
+    assert rel_inf(to_np(T.restrict(F.vector(r))), P.T @ r) < 2e-6
 
 
 def _oracle_hierarchy(om, k, strategy, pseq, h_min, H):
