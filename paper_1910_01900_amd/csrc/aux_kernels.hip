@@ -252,10 +252,11 @@ __device__ __forceinline__ bool node_fixed(const FeGeo& G, int gx, int gy, int g
 // Sum of a DG-layout vector over the elements sharing node (gx, gy, gz), in
 // a fixed order (z, then y, then x candidates, lower first); *mult is the
 // number of elements.
-template <typename T>
+// K > 0: the degree at compile time (constant divisions); 0: G.k.
+template <typename T, int K = 0>
 __device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int gx, int gy, int gz, int* mult) {
-  const int n = G.k + 1, n3 = n * n * n;
-  const Axis X = node_axis(gx, G.k, G.Nx), Y = node_axis(gy, G.k, G.Ny), Z = node_axis(gz, G.k, G.Nz);
+  const int k = K ? K : G.k, n = k + 1, n3 = n * n * n;
+  const Axis X = node_axis(gx, k, G.Nx), Y = node_axis(gy, k, G.Ny), Z = node_axis(gz, k, G.Nz);
   T s = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -286,7 +287,7 @@ static dim3 node_grid(const FeGeo& G) {
               (unsigned)G.Mz);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int K>
 __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* dg, const T* u, T* out, const T* b,
                                                               const T* dinv, const T* xold, T sigma, T theta,
                                                               const int* skip) {
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
   if (gx >= G.Mx || gy >= G.My) return;
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
   int mult;
-  T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
+  T v = node_gather_sum<T, K>(G, dg, gx, gy, gz, &mult);
   if (node_fixed(G, gx, gy, gz)) v = u[i];
   if (MODE == OP_APPLY) {
     out[i] = v;
@@ -341,6 +342,25 @@ __global__ void k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add
   }
 }
 
+template <typename T, int K>
+static void launch_fe_sum(int mode, dim3 g, dim3 blk, const FeGeo& G, const T* dg, const void* u, void* out,
+                          const void* b, const T* di, const void* xold, double sigma, double theta, hipStream_t s,
+                          const int* skip) {
+  switch (mode) {
+    case OP_RESID:
+      hipLaunchKernelGGL((k_fe_sum<T, OP_RESID, K>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+      break;
+    case OP_CHEB:
+      hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB, K>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY, K>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+  }
+}
+
 template <typename T>
 static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, hipStream_t s, const int* skip) {
@@ -349,18 +369,15 @@ static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, cons
   const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
   const T* dg = (const T*)L->scratch();
   const T* di = (const T*)L->dinv();
-  switch (mode) {
-    case OP_RESID:
-      hipLaunchKernelGGL((k_fe_sum<T, OP_RESID>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
-      break;
-    case OP_CHEB:
-      hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
-      break;
-    default:
-      hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+  switch (G.k) {
+    case 1: launch_fe_sum<T, 1>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    case 2: launch_fe_sum<T, 2>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    case 3: launch_fe_sum<T, 3>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    case 4: launch_fe_sum<T, 4>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    case 5: launch_fe_sum<T, 5>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    case 6: launch_fe_sum<T, 6>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    case 7: launch_fe_sum<T, 7>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
+    default: launch_fe_sum<T, 0>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip);
   }
   return check_launch("fe_sum");
 }
