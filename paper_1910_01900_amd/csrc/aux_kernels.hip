@@ -243,38 +243,47 @@ static FeGeo fe_geo(const Mesh& m, int k) {
   g.nnodes = (int64_t)g.Mx * g.My * g.Mz;
   return g;
 }
+// (bitwise, without branches: it does not order the loads around it)
 __device__ __forceinline__ bool node_fixed(const FeGeo& G, int gx, int gy, int gz) {
   const int m = G.bcmask;
-  return (gx == 0 && !(m & 1)) || (gx == G.Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
-         (gy == G.My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == G.Mz - 1 && !(m & 32));
+  return ((gx == 0) & !(m & 1)) | ((gx == G.Mx - 1) & !(m & 2)) | ((gy == 0) & !(m & 4)) |
+         ((gy == G.My - 1) & !(m & 8)) | ((gz == 0) & !(m & 16)) | ((gz == G.Mz - 1) & !(m & 32));
 }
 
 // Sum of a DG-layout vector over the elements sharing node (gx, gy, gz), in
 // a fixed order (z, then y, then x candidates, lower first); *mult is the
-// number of elements.
+// number of elements. The candidates' loads are all issued before the sum
+// (each under its own condition), so they are in flight together; the sum
+// then takes them in that order.
 // K > 0: the degree at compile time (constant divisions); 0: G.k.
 template <typename T, int K = 0>
 __device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int gx, int gy, int gz, int* mult) {
   const int k = K ? K : G.k, n = k + 1, n3 = n * n * n;
   const Axis X = node_axis(gx, k, G.Nx), Y = node_axis(gy, k, G.Ny), Z = node_axis(gz, k, G.Nz);
-  T s = 0;
+  T v[8];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    if (c == 1 && !Z.two) break;
     const int ez = c ? Z.e1 : Z.e0, lz = c ? Z.l1 : Z.l0;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      if (b == 1 && !Y.two) break;
       const int ey = b ? Y.e1 : Y.e0, ly = b ? Y.l1 : Y.l0;
       const int64_t row = (int64_t)G.Nx * (ey + G.Ny * ez);
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        if (a == 1 && !X.two) break;
         const int ex = a ? X.e1 : X.e0, lx = a ? X.l1 : X.l0;
-        s += dg[(row + ex) * n3 + lx + n * (ly + n * lz)];
+        const bool ok = (c == 0 || Z.two) && (b == 0 || Y.two) && (a == 0 || X.two);
+        v[4 * c + 2 * b + a] = ok ? dg[(row + ex) * n3 + lx + n * (ly + n * lz)] : T(0);
       }
     }
   }
+  T s = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        if ((c == 0 || Z.two) && (b == 0 || Y.two) && (a == 0 || X.two)) s += v[4 * c + 2 * b + a];
   *mult = (1 + X.two) * (1 + Y.two) * (1 + Z.two);
   return s;
 }
@@ -295,16 +304,23 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
   const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
   if (gx >= G.Mx || gy >= G.My) return;
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
+  // node-vector loads first, in flight with the gather
+  T x = 0, xo = 0, di = 0, bi = 0;
+  if (MODE == OP_CHEB) {
+    x = u[i];
+    xo = xold[i];
+    di = dinv[i];
+  }
+  if (MODE != OP_APPLY) bi = b[i];
   int mult;
   T v = node_gather_sum<T, K>(G, dg, gx, gy, gz, &mult);
-  if (node_fixed(G, gx, gy, gz)) v = u[i];
+  if (node_fixed(G, gx, gy, gz)) v = MODE == OP_CHEB ? x : u[i];
   if (MODE == OP_APPLY) {
     out[i] = v;
   } else if (MODE == OP_RESID) {
-    out[i] = b[i] - v;
+    out[i] = bi - v;
   } else {
-    const T x = u[i];
-    out[i] = x + sigma * (x - xold[i]) + theta * dinv[i] * (b[i] - v);
+    out[i] = x + sigma * (x - xo) + theta * di * (bi - v);
   }
 }
 // fe (+)= free * w * E^T dg
