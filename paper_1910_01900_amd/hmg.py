@@ -201,9 +201,34 @@ def stream():
 
 
 def ptr(t):
-    torch = _torch()
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("expected a contiguous CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def vec(t, dtype, n, name="vector"):
+    """ptr(t) after checking that t holds at least n values of dtype: the
+    kernels read and write n values of the handle's precision and trust the
+    pointer, so a shorter or differently typed tensor is refused here,
+    before any launch."""
+    if t.dtype != dtype:
+        raise ValueError("%s: expected %s, got %s" % (name, dtype, t.dtype))
+    if t.numel() < n:
+        raise ValueError("%s: %d values, need at least %d" % (name, t.numel(), n))
+    return ptr(t)
+
+
+def rows(t, dtype, width, name="vectors"):
+    """ptr(t) for a 2-D tensor of rows of at least `width` values of dtype,
+    contiguous within each row (row stride = t.stride(0))."""
+    if t.dim() != 2:
+        raise ValueError("%s: expected a 2-D tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s: expected %s, got %s" % (name, dtype, t.dtype))
+    if t.shape[1] < width or t.stride(1) != 1 or t.stride(0) < width:
+        raise ValueError("%s: rows of %d contiguous values needed" % (name, width))
+    if not t.is_cuda:
+        raise ValueError("%s: expected a CUDA tensor" % name)
     return C.c_void_p(t.data_ptr())
 
 
@@ -241,12 +266,14 @@ class Level:
 
     def apply(self, u, v=None):
         v = self.vector() if v is None else v
-        check(lib().hmg_operator_apply(self._h, ptr(u), ptr(v), stream()))
+        n, dt = self.n_dofs, self.dtype
+        check(lib().hmg_operator_apply(self._h, vec(u, dt, n, "u"), vec(v, dt, n, "v"), stream()))
         return v
 
     def residual(self, b, u, r=None):
         r = self.vector() if r is None else r
-        check(lib().hmg_residual(self._h, ptr(b), ptr(u), ptr(r), stream()))
+        n, dt = self.n_dofs, self.dtype
+        check(lib().hmg_residual(self._h, vec(b, dt, n, "b"), vec(u, dt, n, "u"), vec(r, dt, n, "r"), stream()))
         return r
 
     def vectors(self, nrhs):
@@ -259,21 +286,25 @@ class Level:
     def apply_batched(self, u, v=None):
         """v[r, :n] = A u[r, :n] for every row of the 2-D tensors u, v."""
         v = self.vectors(u.shape[0]) if v is None else v
-        if u.stride(0) != v.stride(0) or u.stride(1) != 1 or v.stride(1) != 1:
-            raise ValueError("u and v need the same row stride and contiguous rows")
-        check(lib().hmg_operator_apply_batched(self._h, u.shape[0], ptr(u), ptr(v), u.stride(0), stream()))
+        if u.stride(0) != v.stride(0) or u.shape[0] != v.shape[0]:
+            raise ValueError("u and v need the same rows and row stride")
+        n, dt = self.n_dofs, self.dtype
+        check(lib().hmg_operator_apply_batched(self._h, u.shape[0], rows(u, dt, n, "u"), rows(v, dt, n, "v"),
+                                               u.stride(0), stream()))
         return v
 
     def residual_batched(self, b, u, r=None):
         r = self.vectors(u.shape[0]) if r is None else r
-        if not (b.stride(0) == u.stride(0) == r.stride(0)):
-            raise ValueError("b, u and r need the same row stride")
-        check(lib().hmg_residual_batched(self._h, u.shape[0], ptr(b), ptr(u), ptr(r), u.stride(0), stream()))
+        if not (b.stride(0) == u.stride(0) == r.stride(0)) or not (b.shape[0] == u.shape[0] == r.shape[0]):
+            raise ValueError("b, u and r need the same rows and row stride")
+        n, dt = self.n_dofs, self.dtype
+        check(lib().hmg_residual_batched(self._h, u.shape[0], rows(b, dt, n, "b"), rows(u, dt, n, "u"),
+                                         rows(r, dt, n, "r"), u.stride(0), stream()))
         return r
 
     def diagonal(self):
         d = self.vector()
-        check(lib().hmg_diagonal(self._h, ptr(d), stream()))
+        check(lib().hmg_diagonal(self._h, vec(d, self.dtype, self.n_dofs, "d"), stream()))
         return d
 
     def lambda_max(self, iters=20, seed=1):
@@ -282,7 +313,8 @@ class Level:
         return out.value
 
     def chebyshev(self, b, x, degree, lmax, lo=0.06, hi=1.2, x_is_zero=False):
-        check(lib().hmg_chebyshev_smooth(self._h, ptr(b), ptr(x), degree, lmax, lo, hi,
+        n, dt = self.n_dofs, self.dtype
+        check(lib().hmg_chebyshev_smooth(self._h, vec(b, dt, n, "b"), vec(x, dt, n, "x"), degree, lmax, lo, hi,
                                          1 if x_is_zero else 0, stream()))
         return x
 
@@ -308,12 +340,16 @@ class Transfer:
         check(lib().hmg_transfer_bind(self._h, ptr(self.ws), ws.value))
 
     def prolongate_add(self, c, f):
-        check(lib().hmg_prolongate_add(self._h, ptr(c), ptr(f), stream()))
+        F, Cl = self.fine, self.coarse
+        check(lib().hmg_prolongate_add(self._h, vec(c, Cl.dtype, Cl.n_dofs, "coarse"),
+                                       vec(f, F.dtype, F.n_dofs, "fine"), stream()))
         return f
 
     def restrict(self, f, c=None):
         c = self.coarse.vector() if c is None else c
-        check(lib().hmg_restrict(self._h, ptr(f), ptr(c), stream()))
+        F, Cl = self.fine, self.coarse
+        check(lib().hmg_restrict(self._h, vec(f, F.dtype, F.n_dofs, "fine"),
+                                 vec(c, Cl.dtype, Cl.n_dofs, "coarse"), stream()))
         return c
 
     def __del__(self):
@@ -361,7 +397,8 @@ class Batch:
 
     def autotune(self, u, v, reps=5):
         ms = C.c_double()
-        check(lib().hmg_batch_autotune(self._h, ptr(u), ptr(v), reps, stream(), C.byref(ms)))
+        check(lib().hmg_batch_autotune(self._h, vec(u, self.dtype, self.total, "u"), vec(v, self.dtype, self.total, "v"),
+                                       reps, stream(), C.byref(ms)))
         return ms.value
 
     def schedule(self):
@@ -379,12 +416,14 @@ class Batch:
 
     def apply(self, u, v=None):
         v = self.vector() if v is None else v
-        check(lib().hmg_batch_apply(self._h, ptr(u), ptr(v), stream()))
+        n, dt = self.total, self.dtype
+        check(lib().hmg_batch_apply(self._h, vec(u, dt, n, "u"), vec(v, dt, n, "v"), stream()))
         return v
 
     def residual(self, b, u, r=None):
         r = self.vector() if r is None else r
-        check(lib().hmg_batch_residual(self._h, ptr(b), ptr(u), ptr(r), stream()))
+        n, dt = self.total, self.dtype
+        check(lib().hmg_batch_residual(self._h, vec(b, dt, n, "b"), vec(u, dt, n, "u"), vec(r, dt, n, "r"), stream()))
         return r
 
     def set_chebyshev(self, lmax, degree, lo=0.06, hi=1.2):
@@ -393,7 +432,9 @@ class Batch:
 
     def chebyshev(self, b, x, tmp=None):
         tmp = self.vector() if tmp is None else tmp
-        check(lib().hmg_batch_chebyshev_smooth(self._h, ptr(b), ptr(x), ptr(tmp), stream()))
+        n, dt = self.total, self.dtype
+        check(lib().hmg_batch_chebyshev_smooth(self._h, vec(b, dt, n, "b"), vec(x, dt, n, "x"), vec(tmp, dt, n, "tmp"),
+                                               stream()))
         return x
 
     def __del__(self):
@@ -420,29 +461,44 @@ class Net:
         torch = _torch()
         self._loss = torch.zeros(32, dtype=torch.float64, device="cuda")
 
+    def _check_batch(self, inp, target=None):
+        """Batch size of inp [B, G, G, G, 2] (and target [B, G, G, G]), FP32."""
+        torch, G = _torch(), self.grid
+        if inp.dtype != torch.float32 or tuple(inp.shape[1:]) != (G, G, G, 2):
+            raise ValueError("input: expected float32 [batch, %d, %d, %d, 2]" % (G, G, G))
+        B = inp.shape[0]
+        if not 1 <= B <= self.max_batch:
+            raise ValueError("batch %d outside 1..%d" % (B, self.max_batch))
+        if target is not None and (target.dtype != torch.float32 or tuple(target.shape) != (B, G, G, G)):
+            raise ValueError("target: expected float32 [%d, %d, %d, %d]" % (B, G, G, G))
+        return B
+
     def params(self):
         t = _torch().empty(self.n_params, dtype=_torch().float32, device="cuda")
         check(lib().hmg_net_get_params(self._h, ptr(t), stream()))
         return t
 
     def set_params(self, t):
-        check(lib().hmg_net_set_params(self._h, ptr(t.contiguous()), stream()))
+        check(lib().hmg_net_set_params(self._h, vec(t.contiguous(), _torch().float32, self.n_params, "params"),
+                                       stream()))
 
     def forward(self, inp):
-        B = inp.shape[0]
+        B = self._check_batch(inp)
         out = _torch().empty((B,) + tuple(inp.shape[1:-1]), dtype=_torch().float32, device="cuda")
         check(lib().hmg_net_forward(self._h, ptr(inp), ptr(out), B, stream()))
         return out
 
     def gradient(self, inp, target):
+        B = self._check_batch(inp, target)
         g = _torch().empty(self.n_params, dtype=_torch().float32, device="cuda")
-        check(lib().hmg_net_gradient(self._h, ptr(inp), ptr(target), inp.shape[0], ptr(g), ptr(self._loss),
+        check(lib().hmg_net_gradient(self._h, ptr(inp), ptr(target), B, ptr(g), ptr(self._loss),
                                      stream()))
         return float(self._loss[0]), g
 
     def train_step(self, inp, target, lr):
         """One Adam step; returns the loss as a device scalar (no sync)."""
-        check(lib().hmg_net_train_step(self._h, ptr(inp), ptr(target), inp.shape[0], lr, ptr(self._loss),
+        B = self._check_batch(inp, target)
+        check(lib().hmg_net_train_step(self._h, ptr(inp), ptr(target), B, lr, ptr(self._loss),
                                        stream()))
         return self._loss[0]
 
@@ -509,6 +565,10 @@ class Hierarchy:
     def capture(self, buf):
         """Copy the coarse right-hand side of following V-cycles into rows of buf [cap, n] (FP64)."""
         self._cap = buf
+        if buf is not None:
+            rows(buf, _torch().float64, self.coarse_info()["n"], "capture buffer")
+            if buf.stride(0) != self.coarse_info()["n"]:
+                raise ValueError("capture buffer: rows of exactly n values")
         check(lib().hmg_hierarchy_capture(self._h, ptr(buf) if buf is not None else None,
                                           0 if buf is None else buf.shape[0]))
 
@@ -518,6 +578,7 @@ class Hierarchy:
         return c.value
 
     def coarse_solve_batch(self, R):
+        self._coarse_rows(R, "R")
         E = _torch().empty_like(R)
         check(lib().hmg_hierarchy_coarse_solve_batch(self._h, ptr(R), ptr(E), R.shape[0], stream()))
         return E
@@ -525,6 +586,11 @@ class Hierarchy:
     def learned_data(self, grid, R, E=None):
         """Network inputs [count, grid, grid, grid, 2] (and targets) of coarse vectors R (and E)."""
         torch = _torch()
+        self._coarse_rows(R, "R")
+        if E is not None:
+            self._coarse_rows(E, "E")
+            if E.shape[0] != R.shape[0]:
+                raise ValueError("R and E need the same number of rows")
         cnt = R.shape[0]
         inp = torch.empty((cnt, grid, grid, grid, 2), dtype=torch.float32, device="cuda")
         tgt = torch.empty((cnt, grid, grid, grid), dtype=torch.float32, device="cuda") if E is not None else None
@@ -535,6 +601,12 @@ class Hierarchy:
                                                    stream()))
         return inp, tgt
 
+    def _coarse_rows(self, t, name):
+        """t: [count, n] FP64 coarse vectors, rows of exactly n values."""
+        n = self.coarse_info()["n"]
+        if t.dim() != 2 or t.dtype != _torch().float64 or t.shape[1] != n or not t.is_contiguous():
+            raise ValueError("%s: expected a contiguous float64 [count, %d] tensor" % (name, n))
+
     def coarse_stats(self):
         f = C.c_int()
         check(lib().hmg_hierarchy_coarse_stats(self._h, C.byref(f), stream()))
@@ -543,14 +615,17 @@ class Hierarchy:
     def vcycle(self, b, x=None):
         torch = _torch()
         x = torch.zeros_like(b) if x is None else x
-        check(lib().hmg_vcycle(self._h, ptr(b), ptr(x), stream()))
+        n, dt = self.n_dofs, torch.float64
+        check(lib().hmg_vcycle(self._h, vec(b, dt, n, "b"), vec(x, dt, n, "x"), stream()))
         return x
 
     def solve(self, b, x=None, rtol=1e-10, atol=0.0, maxit=200, allow_not_converged=False):
         torch = _torch()
         x = torch.zeros_like(b) if x is None else x
         st = SolveStats()
-        code = lib().hmg_pcg_solve(self._h, ptr(b), ptr(x), rtol, atol, maxit, C.byref(st), stream())
+        n, dt = self.n_dofs, torch.float64
+        code = lib().hmg_pcg_solve(self._h, vec(b, dt, n, "b"), vec(x, dt, n, "x"), rtol, atol, maxit, C.byref(st),
+                                   stream())
         check(code, allow=(0, 1) if allow_not_converged else (0,))
         return x, {"iters": st.iters, "r0": st.r0, "rn": st.rn, "rho": st.rho, "n10": st.n10,
                    "status": STATUS.get(code, code)}
