@@ -675,7 +675,7 @@ struct hmg_hierarchy {
   // workspace layout
   size_t ws_bytes = 0;
   std::vector<size_t> off_lv, off_tr, off_b, off_x, off_r;
-  size_t off_f64 = 0, off_c64 = 0, off_ainv = 0, off_cg = 0, off_part = 0, off_scal = 0;
+  size_t off_f64 = 0, off_c64 = 0, off_ainv = 0, off_cg = 0, off_part = 0, off_scal = 0, off_c64v = 0;
   char* ws = nullptr;
   bool bound = false;
   // launch graphs (hmg_hierarchy_set_graph): one PCG iteration and one
@@ -712,6 +712,10 @@ struct hmg_hierarchy {
   double* part() const { return (double*)(ws + off_part); }
   double* scal() const { return (double*)(ws + off_scal); }
   double* ainv() const { return (double*)(ws + off_ainv); }
+  // FP64 right-hand side and solution of the iterative coarse solve when the
+  // V-cycle runs in FP32 (the coarse solve itself is an FP64 step)
+  double* cb64() const { return (double*)(ws + off_c64v); }
+  double* cx64() const { return (double*)(ws + off_c64v) + nc; }
   ~hmg_hierarchy() {
     drop_graphs();
     if (cap) (void)hipStreamDestroy(cap);
@@ -835,6 +839,7 @@ extern "C" int hmg_hierarchy_create(const hmg_mesh_desc* desc, const char* strat
     H->off_c64 = take(H->coarse64->ws_bytes);
   }
   H->off_ainv = take(H->dense ? (size_t)H->nc * H->nc * 8 : 8);
+  H->off_c64v = take(H->own_coarse64 ? (size_t)2 * H->nc * 8 : 8);
   H->off_cg = take((size_t)4 * H->fine64->n_dofs * 8);
   H->off_part = take((size_t)kPartials * 8);
   H->off_scal = take(32 * 8);
@@ -1056,6 +1061,22 @@ static int coarse_cg(hmg_hierarchy* H, const hmg_level* L, const void* b, void* 
   return HMG_OK;
 }
 
+// The iterative coarse solve, always in FP64: on the FP64 copy of the
+// coarsest level, the level-precision right-hand side converted on the way
+// in and the solution converted back.  *skip (set before the call) gates
+// the conversion in and the solve.  The solve sets *skip once it has
+// converged, so the conversion back is gated by the judge's decision
+// *accepted instead (0 outside the learned correction).
+static int coarse_cg64(hmg_hierarchy* H, size_t l, hipStream_t s) {
+  hmg_level* L = H->lv[l];
+  if (!H->own_coarse64) return coarse_cg(H, L, H->b(l), H->x(l), H->coarse_rtol, H->coarse_maxit, s);
+  int* skip = (int*)(H->scal() + 24);
+  int* accepted = skip + 2;
+  TRY(vec_convert_gated(L->prec, H->b(l), HMG_F64, H->cb64(), H->nc, skip, s));
+  TRY(coarse_cg(H, H->coarse64, H->cb64(), H->cx64(), H->coarse_rtol, H->coarse_maxit, s));
+  return vec_convert_gated(HMG_F64, H->cx64(), L->prec, H->x(l), H->nc, accepted, s);
+}
+
 // Coarsest level: x(l) from b(l) by the selected coarse solve.
 static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
   hmg_level* L = H->lv[l];
@@ -1069,7 +1090,8 @@ static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
       return chebyshev(L, H->b(l), H->x(l), H->ns, H->lmax_c, 0.06, 1.2, 1, s);
     case HMG_COARSE_CG:
       TRY(set_flag(skip, 0, s));
-      return coarse_cg(H, L, H->b(l), H->x(l), H->coarse_rtol, H->coarse_maxit, s);
+      if (H->own_coarse64) TRY(set_flag(skip + 2, 0, s));
+      return coarse_cg64(H, l, s);
     case HMG_COARSE_LEARNED: {
       hmg_net* N = H->net;
       const NodeGrid ng = coarse_nodes(H);
@@ -1085,8 +1107,8 @@ static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
         return coarse_gemv_gated(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, gate, H->accept,
                                  (int*)(H->scal() + 10), s);
       // no dense inverse: the iterative coarse solve runs only for a rejected correction
-      TRY(gate_to_skip(gate, H->accept, skip, (int*)(H->scal() + 10), s));
-      return coarse_cg(H, L, H->b(l), H->x(l), H->coarse_rtol, H->coarse_maxit, s);
+      TRY(gate_to_skip(gate, H->accept, skip, (int*)(H->scal() + 10), s, skip + 2));
+      return coarse_cg64(H, l, s);
     }
     default:
       return coarse_gemv(L->prec, H->ainv(), H->b(l), H->x(l), (int)H->nc, s);

@@ -53,6 +53,13 @@ __global__ void k_convert(const A* x, B* y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (B)x[i];
 }
+// y = x converted, skipped while *skip != 0 (gated coarse solves)
+template <typename A, typename B>
+__global__ void k_convert_gated(const A* x, B* y, int64_t n, const int* skip) {
+  if (*skip) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (B)x[i];
+}
 template <typename T>
 __global__ void k_dot(const T* x, const T* y, int64_t n, double* partials) {
   double acc = 0.0;
@@ -155,6 +162,18 @@ int vec_convert(int from, const void* x, int to, void* y, int64_t n, hipStream_t
   else
     hipLaunchKernelGGL((k_convert<float, double>), grid_for(n), kBlock, 0, s, (const float*)x, (double*)y, n);
   return check_launch("convert");
+}
+int vec_convert_gated(int from, const void* x, int to, void* y, int64_t n, const int* skip, hipStream_t s) {
+  if (n <= 0) return HMG_OK;
+  if (from == HMG_F64 && to == HMG_F64)
+    hipLaunchKernelGGL((k_convert_gated<double, double>), grid_for(n), kBlock, 0, s, (const double*)x, (double*)y, n, skip);
+  else if (from == HMG_F64)
+    hipLaunchKernelGGL((k_convert_gated<double, float>), grid_for(n), kBlock, 0, s, (const double*)x, (float*)y, n, skip);
+  else if (to == HMG_F64)
+    hipLaunchKernelGGL((k_convert_gated<float, double>), grid_for(n), kBlock, 0, s, (const float*)x, (double*)y, n, skip);
+  else
+    hipLaunchKernelGGL((k_convert_gated<float, float>), grid_for(n), kBlock, 0, s, (const float*)x, (float*)y, n, skip);
+  return check_launch("convert_gated");
 }
 static unsigned dot_grid(int64_t n) {
   unsigned g = grid_for(n, 8);
@@ -461,11 +480,12 @@ __global__ void k_reduce_gated(const double* partials, int np, double* out, cons
   double s = block_reduce(acc);
   if (threadIdx.x == 0) *out = s;
 }
-__global__ void k_gate_to_skip(const double* gate, double accept2, int* skip, int* fallbacks) {
+__global__ void k_gate_to_skip(const double* gate, double accept2, int* skip, int* fallbacks, int* accepted) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   const double rr = gate[0], bb = gate[1];
   const bool ok = isfinite(rr) && rr <= accept2 * bb;
   *skip = ok ? 1 : 0;
+  if (accepted) *accepted = ok ? 1 : 0;
   if (!ok) *fallbacks += 1;
 }
 __global__ void k_set_flag(int* flag, int v) {
@@ -514,8 +534,8 @@ int vec_dot_gated(int prec, const void* x, const void* y, int64_t n, double* par
   hipLaunchKernelGGL(k_reduce_gated, 1, 1024, 0, s, (const double*)partials, (int)g, out, skip);
   return check_launch("dot_gated");
 }
-int gate_to_skip(const double* gate, double accept, int* skip, int* fallbacks, hipStream_t s) {
-  hipLaunchKernelGGL(k_gate_to_skip, 1, 64, 0, s, gate, accept * accept, skip, fallbacks);
+int gate_to_skip(const double* gate, double accept, int* skip, int* fallbacks, hipStream_t s, int* accepted) {
+  hipLaunchKernelGGL(k_gate_to_skip, 1, 64, 0, s, gate, accept * accept, skip, fallbacks, accepted);
   return check_launch("gate_to_skip");
 }
 int set_flag(int* flag, int v, hipStream_t s) {

@@ -297,8 +297,10 @@ int ccg_check(const double* rzn, const double* rz0, double tol2, int* skip, int*
 // dot product that does nothing while *skip != 0
 int vec_dot_gated(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
                   const int* skip, hipStream_t s);
-// *skip = (gate[0] <= accept^2 gate[1] and finite); a rejected gate adds one to *fallbacks
-int gate_to_skip(const double* gate, double accept, int* skip, int* fallbacks, hipStream_t s);
+// *skip = (gate[0] <= accept^2 gate[1] and finite); a rejected gate adds one to *fallbacks;
+// *accepted (if not NULL) receives the same decision
+int gate_to_skip(const double* gate, double accept, int* skip, int* fallbacks, hipStream_t s,
+                 int* accepted = nullptr);
 int set_flag(int* flag, int v, hipStream_t s);
 
 // vectors (type by prec); n elements
@@ -310,6 +312,8 @@ int vec_recip(int prec, const void* x, void* y, int64_t n, hipStream_t s);      
 int vec_mul3(int prec, double a, const void* d, const void* b, void* z, int64_t n,
              hipStream_t s);  // z = a d .* b
 int vec_convert(int from, const void* x, int to, void* y, int64_t n, hipStream_t s);
+// the same, doing nothing while *skip != 0
+int vec_convert_gated(int from, const void* x, int to, void* y, int64_t n, const int* skip, hipStream_t s);
 // deterministic two-stage dot: result to dev double* out (and nparts returned)
 int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
             hipStream_t s);
