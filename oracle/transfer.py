@@ -51,9 +51,21 @@ def dg_p(mesh, kf, kc):
 
 
 def coarse_mesh(mesh):
-    """The octree parent mesh (every N_d halved)."""
+    """The octree parent mesh (every N_d halved).  A per-element penalty
+    factor (not part of the paper; used by the variable-penalty workload)
+    is re-discretized like the rest of the operator (Sec. 2: coarser levels
+    evaluate the operator for the coarse parameters): the parent's factor
+    is the mean over its eight children."""
     assert all(N % 2 == 0 for N in mesh.nel)
-    return BoxMesh(tuple(N // 2 for N in mesh.nel), mesh.lo, mesh.hi, mesh.deform, mesh.waves, mesh.bc)
+    cn = tuple(N // 2 for N in mesh.nel)
+    ts = None
+    if mesh.tau_scale is not None:
+        ts = np.zeros(int(np.prod(cn)))
+        fine = np.asarray(mesh.tau_scale, dtype=np.float64)
+        for e in range(mesh.n_el):
+            ex, ey, ez = (int(c) for c in mesh.coords(e))
+            ts[ex // 2 + cn[0] * (ey // 2 + cn[1] * (ez // 2))] += fine[e] / 8.0
+    return BoxMesh(cn, mesh.lo, mesh.hi, mesh.deform, mesh.waves, mesh.bc, ts)
 
 
 def dg_h(mesh_f, k):

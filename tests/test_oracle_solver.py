@@ -154,9 +154,28 @@ def test_paper_iteration_counts(case):
     mesh = BoxMesh((N, N, N), lo=(-1, -1, -1), hi=(1, 1, 1),
                    deform=0.15 if case["curved"] else 0.0, waves=2)
     k = case["k"]
-    H = solver.Hierarchy(mesh, k, case["strategy"], pseq=case["pseq"], h_min=1, ip_factor=case["ip"])
+    H = solver.Hierarchy(mesh, k, case["strategy"], pseq=case["pseq"], h_min=2, ip_factor=case["ip"])
     f = lambda X: 27 * np.pi ** 2 * np.prod(np.sin(3 * np.pi * X), axis=-1)
     b = sipg.rhs(mesh, k, f, ip_factor=case["ip"])
     _, hist = solver.pcg(H.levels[0]["A"], b, precond=H.vcycle, rtol=1e-10)
     _, n10 = solver.metrics(hist)
     assert abs(n10 - case["n10"]) <= 0.05 * case["n10"], (n10, case)
+
+
+def test_coarse_mesh_penalty_scale_is_the_mean_of_the_children():
+    """Re-discretization of a per-element penalty factor on the octree
+    parent: a constant factor stays the same (the coarse operator equals the
+    one assembled with that factor as ip_factor), and in general the parent
+    takes the mean over its eight children."""
+    from oracle import transfer
+    m = BoxMesh((4, 2, 2), deform=0.05, tau_scale=np.full(16, 3.0))
+    c = transfer.coarse_mesh(m)
+    assert c.nel == (2, 1, 1) and np.allclose(c.tau_scale, 3.0)
+    A1 = sipg.assemble(c, 2)
+    A2 = sipg.assemble(BoxMesh((2, 1, 1), deform=0.05), 2, ip_factor=3.0)
+    assert abs(A1 - A2).max() <= 1e-12 * abs(A2).max()
+    ts = np.arange(16, dtype=float)
+    c = transfer.coarse_mesh(BoxMesh((4, 2, 2), tau_scale=ts))
+    # parent 0 holds children ex in {0,1}, ey in {0,1}, ez in {0,1}
+    kids0 = [ex + 4 * (ey + 2 * ez) for ex in (0, 1) for ey in (0, 1) for ez in (0, 1)]
+    assert c.tau_scale[0] == np.mean(ts[kids0]) and c.tau_scale[1] == np.mean(ts[[i + 2 for i in kids0]])
