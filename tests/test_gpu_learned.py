@@ -76,15 +76,25 @@ def test_gradient_matches_oracle():
     assert abs(loss - L_bf) <= 1e-3 * L_bf
     o = 0
     for ci, co, _, _ in unet.LAYERS:
-        n = co * 27 * ci + co
-        s = slice(o, o + n)
-        e_bf = np.linalg.norm(g[s] - g_bf[s]) / np.linalg.norm(g_bf[s])
-        e_64 = np.linalg.norm(g[s] - g_64[s]) / np.linalg.norm(g_64[s])
-        print("layer %d->%d: rel err vs BF16-emulating oracle %.2e, vs FP64 oracle %.2e" % (ci, co, e_bf, e_64))
-        assert e_bf <= 1e-3, (ci, co, e_bf)
-        # BF16 operands (8-bit significand) in every product: a few percent
-        assert e_64 <= 0.15, (ci, co, e_64)
-        o += n
+        nw = co * 27 * ci
+        for name, s in (("w", slice(o, o + nw)), ("b", slice(o + nw, o + nw + co))):
+            e_bf = np.linalg.norm(g[s] - g_bf[s]) / np.linalg.norm(g_bf[s])
+            e_64 = np.linalg.norm(g[s] - g_64[s]) / np.linalg.norm(g_64[s])
+            # element by element: the two sides round the same operands to
+            # BF16, but compute them in FP32 (GPU) or FP64 (oracle); where an
+            # activation lands on the other side of a BF16 rounding boundary
+            # it moves by up to 2^-8 of itself, which reaches the gradient
+            # entries through every later product.  Bound per entry: 2^-8 of
+            # the entry plus 2e-3 of the largest entry of the same group.
+            bound = 2.0 ** -8 * np.abs(g_bf[s]) + 2e-3 * np.abs(g_bf[s]).max()
+            ratio = np.max(np.abs(g[s] - g_bf[s]) / bound)
+            print("layer %d->%d %s: rel err vs BF16-emulating oracle %.2e (max entry ratio %.3f), "
+                  "vs FP64 oracle %.2e" % (ci, co, name, e_bf, ratio, e_64))
+            assert e_bf <= 1e-3, (ci, co, name, e_bf)
+            assert ratio <= 1.0, (ci, co, name, ratio)
+            # BF16 operands (8-bit significand) in every product: a few percent
+            assert e_64 <= 0.15, (ci, co, name, e_64)
+        o += nw + co
 
 
 def test_adam_step_matches_definition():

@@ -115,7 +115,9 @@ def test_vcycle_matches_oracle(strategy, k, nel, deformed):
     b = uniform(30, H.n_dofs)
     import torch
     x = to_np(H.vcycle(torch.as_tensor(b, device="cuda")))
-    assert rel_inf(x, oh.vcycle(b)) < 1e-10
+    err = rel_inf(x, oh.vcycle(b))
+    print("vcycle %s k=%d: rel err %.3e" % (strategy, k, err))
+    assert err < 1e-10
 
 
 def test_vcycle_fp32_close_to_fp64():
@@ -184,7 +186,41 @@ def test_pcg_failure_paths():
     x, st = H.solve(b)
     x2, st2 = H.solve(b, x=x.clone(), rtol=1e-6)
     assert st2["iters"] == 0 or st2["rn"] / st2["r0"] <= 1e-6
-    # misaligned vector is rejected
+    # a misaligned vector of the right length is rejected by the library
+    buf = torch.zeros(H.n_dofs + 32, dtype=torch.float64, device="cuda")
     with pytest.raises(hmg.HmgError) as ei:
-        H.vcycle(b[1:].contiguous()[: H.n_dofs - 1])
+        H.vcycle(buf[1:1 + H.n_dofs])
     assert ei.value.code in (-1,)
+
+
+def test_binding_rejects_wrong_vectors_before_any_launch():
+    """The binding checks precision and length against the handle before
+    calling the library, whose kernels trust the pointers: an FP32 vector
+    for an FP64 solve, a vector shorter than the level, a wrongly shaped
+    batch."""
+    import torch
+    hm, _ = meshes((4, 4, 4), 2, False)
+    H = hmg.Hierarchy(hm, "cph", h_min=1)
+    L = hmg.Level(hm, prec=hmg.F32)
+    b = torch.as_tensor(uniform(34, H.n_dofs), device="cuda")
+    x = torch.full_like(b, 7.0)
+    with pytest.raises(ValueError):
+        H.solve(b.float())
+    with pytest.raises(ValueError):
+        H.solve(b, x=x[:-1])
+    with pytest.raises(ValueError):
+        H.vcycle(b[: H.n_dofs // 2], x)
+    assert bool((x == 7.0).all())  # nothing ran
+    u32 = L.vector(uniform(35, L.n_dofs))
+    with pytest.raises(ValueError):
+        L.apply(u32.double())
+    with pytest.raises(ValueError):
+        L.apply(u32, torch.zeros(L.n_dofs - 1, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        L.residual(u32, u32, torch.zeros(L.n_dofs, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        L.apply_batched(L.vectors(2).double())
+    with pytest.raises(ValueError):
+        L.chebyshev(u32[:10], L.vector(), 2, 1.5)
+    with pytest.raises(ValueError):
+        H.coarse_solve_batch(torch.zeros(2, H.coarse_info()["n"] + 1, dtype=torch.float64, device="cuda"))
