@@ -1,14 +1,14 @@
 """Benchmark: PCG + hybrid multigrid solve on one MI355X.
 
-Workload (default): the curvilinear cube of 64^3 elements, degree k = 4
-(32,768,000 DoFs, x_i += 0.05 prod sin(pi x_j), cubic mapping), Dirichlet
-boundary, seeded U[-1,1] right-hand side.  One step = one full solve from
-x_0 = 0 to ||r||/||r_0|| <= 1e-10: FP64 preconditioned CG (Alg. 1) with one
-V-cycle per iteration (Alg. 2) over the hybrid hierarchy cph (DG4 -> FE4 ->
-FE2 -> FE1 -> h-coarsening to 4^3) in FP32, Chebyshev(5) smoothing (Alg. 3)
-and an exact FP64 coarse solve; PCG iterations are replayed from recorded
-HIP graphs (--no-graph: eager launches, the same results bit for bit).
-`value` is DoFs solved per second
+Workload (default): the curvilinear cube of 48^3 elements, degree k = 7
+(56,623,104 DoFs, x_i += 0.05 prod sin(pi x_j), cubic mapping), per-element
+penalty scale ~ U[1, 10], Dirichlet boundary, seeded U[-1,1] right-hand
+side.  One step = one full solve from x_0 = 0 to ||r||/||r_0|| <= 1e-10:
+FP64 preconditioned CG (Alg. 1) with one V-cycle per iteration (Alg. 2) over
+the hybrid hierarchy cph (DG7 -> FE7 -> FE3 -> FE1 -> h-coarsening to 3^3)
+in FP32, Chebyshev(5) smoothing (Alg. 3) and an exact FP64 coarse solve;
+PCG iterations are replayed from recorded HIP graphs (--no-graph: eager
+launches, the same results bit for bit).  `value` is DoFs solved per second
 (N * steps / time).  The FP64 and FP32 operator applies are timed on their
 own with HIP events on the launch stream (operator_apply, roofline).
 
@@ -16,17 +16,19 @@ The plain FP64 solve (the same hierarchy with an FP64 V-cycle) is timed
 after the timed region and reported beside it.  `roofline.traffic` (HBM
 bytes per launch) and `roofline.fp64_flops` (executed FP64 arithmetic per
 launch, timed with the same live launch duration) are read from the
-committed counter summary of the FP64 apply kernel when that summary was
-taken on the current kernel source; else traffic is null and fp64_flops
-absent.
+committed counter summary of the workload's FP64 apply kernel
+(profiles/op_kernel_<workload>_f64_pmc.md) when that summary was taken on
+the current kernel source; else traffic is null and fp64_flops absent.
 
-After the timed region, the 64-mesh batch multi_64 (64 Cartesian unit cubes
-with N_i^3 elements, N_i ~ U{4..24}, degree k_i ~ U{2..7}, 4 vectors each)
-is applied under several launch schedules and reported as multi_mesh.
+After the timed region, the workloads named by --also (default: the
+curvilinear 64^3 mesh at k = 4, 32.8M DoFs) are reported as sub-blocks
+(best of three solves), and the 64-mesh batch multi_64 (64 Cartesian unit
+cubes with N_i^3 elements, N_i ~ U{4..24}, degree k_i ~ U{2..7}, 4 vectors
+each) is applied under several launch schedules and reported as multi_mesh.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-plain-fp64] [--no-multi]
-                       [--multi-only] [--learned-only] [--tables]
+                       [--also NAMES] [--no-cpu-baseline] [--no-plain-fp64]
+                       [--no-multi] [--multi-only] [--learned-only] [--tables]
 """
 import argparse
 import hashlib
@@ -64,10 +66,13 @@ def apply_bytes(nel, k, prec_bytes, curved):
     return b
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "op_kernel_curved_k4_64_f64_pmc.md")
 # the sources the FP64 apply kernel is compiled from (hashed together)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_01900_amd", "csrc", f)
                   for f in ("op_body.h", "op_kernels.hip", "hmg_internal.h")]
+
+
+def pmc_summary(workload):
+    return os.path.join(ROOT, "profiles", "op_kernel_%s_f64_pmc.md" % workload)
 
 
 def kernel_source_sha():
@@ -80,12 +85,13 @@ def kernel_source_sha():
 
 def _pmc_field(workload, name):
     """A per-launch figure of the FP64 apply kernel from the committed counter
-    summary, or None when there is none for this workload or it was taken on
-    a different kernel source."""
-    if workload != "curved_k4_64" or not os.path.exists(PMC_SUMMARY):
+    summary of this workload (profiles/op_kernel_<workload>_f64_pmc.md), or
+    None when there is none or it was taken on a different kernel source."""
+    path = pmc_summary(workload)
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
@@ -235,7 +241,7 @@ def tables_bench():
         N, k = c["N"], c["k"]
         mesh = hmg.Mesh((N, N, N), k, (-1.0,) * 3, (1.0,) * 3, c["curved"], 0.15 if c["curved"] else 0.0, 2,
                         (0,) * 6, c["ip"], None)
-        H = hmg.Hierarchy(mesh, c["strategy"], pseq=c["pseq"], h_min=1, smoother_degree=5, mg_prec=hmg.F64)
+        H = hmg.Hierarchy(mesh, c["strategy"], pseq=c["pseq"], h_min=2, smoother_degree=5, mg_prec=hmg.F64)
         _, st = H.solve(hmg.Level(mesh).rhs_sine(3 * np.pi), rtol=1e-10, maxit=600)
         dev = (st["n10"] - c["n10"]) / c["n10"]
         ok = abs(dev) <= 0.05 if c["compare"] == "band" else dev <= 0.05
@@ -351,7 +357,10 @@ def cpu_baseline(w, u_host, budget_s=15.0):
     from oracle import sipg
     from oracle.mesh import BoxMesh
     k = w["degree"]
-    om = BoxMesh(tuple(w["nel"]), deform=w["amp"] if w["deformed"] else 0.0)
+    from paper_1910_01900_amd.inputs import tau_scale
+    n_el = int(np.prod(w["nel"]))
+    ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
+    om = BoxMesh(tuple(w["nel"]), deform=w["amp"] if w["deformed"] else 0.0, tau_scale=ts)
     n_el = int(np.prod(w["nel"]))
     # probe on 64 elements, then one run sized to about budget_s seconds
     probe = np.arange(64) * (n_el // 64)
@@ -365,9 +374,20 @@ def cpu_baseline(w, u_host, budget_s=15.0):
     elapsed = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     dofs = len(sel) * (k + 1) ** 3
-    return {"value": dofs / elapsed, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
-            "sample": "FP64 operator apply of %d elements spread over the %s mesh (%d DoFs), %.1f s"
-                      % (len(sel), "x".join(map(str, w["nel"])), dofs, elapsed)}
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": dofs / elapsed, "unit": "DoF/s", "cores": int(min(threads, avail)), "kind": "oracle",
+            "cpu_model": model, "host_cpus_available": int(avail), "blas_threads": int(threads),
+            "sample": "FP64 operator apply (the oracle's dense element-wise quadrature) of %d elements spread "
+                      "over the %s k=%d mesh (%d DoFs), %.1f s" % (len(sel), "x".join(map(str, w["nel"])), k, dofs,
+                                                                   elapsed)}
 
 
 def main():
@@ -375,7 +395,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="curved_k4_64")
+    ap.add_argument("--workload", default="curved_k7_48")
+    ap.add_argument("--also", default="curved_k4_64",
+                    help="comma-separated workloads reported as sub-blocks after the timed one ('' for none)")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
@@ -453,124 +475,34 @@ def main():
                           "batched_ms": msb, "batched_dofs_per_s": (a.nrhs * L.n_dofs / (msb * 1e-3)) if msb else None}))
         return
 
-    t0 = time.time()
-    log("setup: hierarchy cph (FP32 V-cycle) for", a.workload)
-    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32, graph=a.graph)
-    log("setup done in %.1f s; levels:" % (time.time() - t0),
-        [(l["space"], l["degree"], l["nel"][0]) for l in H.levels()])
-    N = H.n_dofs
-    b = torch.as_tensor(uniform(3, N), device="cuda")
-    x = torch.zeros_like(b)
-
-    for i in range(a.warmup):
-        x.zero_()
-        _, st = H.solve(b, x, rtol=1e-10, maxit=100)
-        log("warmup solve %d: %d iterations, n10 %.2f" % (i, st["iters"], st["n10"]))
-    torch.cuda.synchronize()
-    times, stats = [], None
-    t_start = time.perf_counter()
-    for i in range(a.steps):
-        x.zero_()
-        t1 = time.perf_counter()
-        _, stats = H.solve(b, x, rtol=1e-10, maxit=100)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t1)
-        log("step %d: %.1f ms, %d iterations" % (i, times[-1] * 1e3, stats["iters"]))
-    total = time.perf_counter() - t_start
-    ms_per_step = 1e3 * total / a.steps
-
-    del H
-    torch.cuda.empty_cache()
-    plain = None
-    if not a.no_plain_fp64:
-        # plain FP64: the same hierarchy with every level in FP64
-        H64 = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F64, graph=a.graph)
-        x64 = torch.zeros_like(b)
-        _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)  # warm-up
-        torch.cuda.synchronize()
-        t64 = []
-        for _ in range(max(1, min(a.steps, 3))):
-            x64.zero_()
-            t1 = time.perf_counter()
-            _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)
-            torch.cuda.synchronize()
-            t64.append(time.perf_counter() - t1)
-        plain = {"ns_per_dof": 1e9 * min(t64) / N, "ms": 1e3 * min(t64), "iterations": st64["iters"],
-                 "n10": st64["n10"]}
-        log("plain FP64 solve: %.1f ms, %d iterations" % (plain["ms"], plain["iterations"]))
-        del H64, x64
-        torch.cuda.empty_cache()
-
-    # final residual recomputed with the FP64 operator
-    L64 = hmg.Level(mesh, prec=hmg.F64)
-    r = L64.residual(b, x)
-    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
-    log("final relative residual %.3e" % rel)
-
-    # operator applies, timed with HIP events on the launch stream
-    u = L64.vector(uniform(1, L64.n_dofs))
-    v = L64.vector()
-    ms64 = time_applies(L64, u, v, a.apply_reps)
-    u_host = u.cpu().numpy() if not a.no_cpu_baseline else None
-    del u, v, r
-    L32 = hmg.Level(mesh, prec=hmg.F32)
-    u32 = L32.vector(uniform(1, L32.n_dofs))
-    v32 = L32.vector()
-    ms32 = time_applies(L32, u32, v32, a.apply_reps)
-    del u32, v32
-    batched = None
-    if a.nrhs > 1:
-        msb32 = time_applies_batched(L32, a.nrhs, 5)
-        del L32
-        torch.cuda.empty_cache()
-        msb64 = time_applies_batched(L64, a.nrhs, 5)
-        batched = {"nrhs": a.nrhs, "fp64_ms": msb64, "fp32_ms": msb32,
-                   "fp64_dofs_per_s": a.nrhs * N / (msb64 * 1e-3), "fp32_dofs_per_s": a.nrhs * N / (msb32 * 1e-3)}
-        log("batched apply, %d vectors: FP64 %.3f ms (%.2f GDoF/s), FP32 %.3f ms (%.2f GDoF/s)"
-            % (a.nrhs, msb64, batched["fp64_dofs_per_s"] / 1e9, msb32, batched["fp32_dofs_per_s"] / 1e9))
-    bytes64 = apply_bytes(w["nel"], k, 8, w["deformed"])
-    achieved = bytes64 / (ms64 * 1e-3) / 1e9
-    log("apply FP64 %.3f ms (%.2f GDoF/s, %.0f GB/s), FP32 %.3f ms (%.2f GDoF/s)"
-        % (ms64, N / ms64 / 1e6, achieved, ms32, N / ms32 / 1e6))
-
+    res = run_workload(a, a.workload, hmg, timed=True)
     out = {
         "metric": METRIC,
-        "value": N * a.steps / total,
+        "value": res["value"],
+        "value_is": "solve throughput: DoFs solved to 1e-10 relative residual per second (FP64 PCG, FP32 "
+                    "V-cycle), over the timed solves; operator-apply DoF/s in operator_apply",
         "unit": "DoF/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64 (outer CG) / f32 (V-cycle)",
         "data": "synthetic",
-        "config": {"workload": a.workload, "mesh": "x".join(map(str, w["nel"])), "degree": k,
-                   "curved": w["deformed"], "dofs": N, "strategy": "cph", "p_sequence": "floor(p/2)",
-                   "smoother": "Chebyshev(5)", "coarse": "exact FP64, FE1 4^3", "rtol": 1e-10,
-                   "parallelism": "single GPU", "graph": a.graph},
-        "solve": {"ns_per_dof": 1e9 * (total / a.steps) / N, "iterations": stats["iters"],
-                  "n10": stats["n10"], "rho": stats["rho"], "final_rel_residual": rel},
-        "operator_apply": {"fp64_dofs_per_s": N / (ms64 * 1e-3), "fp32_dofs_per_s": N / (ms32 * 1e-3),
-                           "fp64_ms": ms64, "fp32_ms": ms32,
-                           "fp32_achieved_GBs": apply_bytes(w["nel"], k, 4, w["deformed"]) / (ms32 * 1e-3) / 1e9},
-        "roofline": {"kernel": "op_kernel<%d,double,%s,DG,APPLY>" % (k + 1, "curved" if w["deformed"] else "affine"),
-                     "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(a.workload),
-                     "algorithmic_bytes_per_launch": bytes64},
+        "config": res["config"],
     }
-    flops = measured_fp64_flops(a.workload)
-    if flops is not None:  # executed FP64 arithmetic of the same kernel, same live timing
-        tf = flops / (ms64 * 1e-3) / 1e12
-        out["roofline"]["fp64_flops"] = {"achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                                         "frac": tf / PEAK_FP64_TFLOPS, "per_launch": flops}
-    if plain is not None:
-        out["solve_plain_fp64"] = plain
-    if batched is not None:
-        out["operator_apply_batched"] = batched
+    for key in ("solve", "solve_plain_fp64", "operator_apply", "operator_apply_batched", "roofline"):
+        if key in res:
+            out[key] = res[key]
+    if a.also:
+        for name in a.also.split(","):
+            if name and name != a.workload:
+                log("sub-block", name)
+                sub = run_workload(a, name, hmg, timed=False)
+                out.setdefault("other_workloads", {})[name] = sub
     if not a.no_multi:
-        del L64
         torch.cuda.empty_cache()
         multi = {}
         for name, prec in (("fp64", hmg.F64), ("fp32", hmg.F32)):
@@ -586,9 +518,138 @@ def main():
         out["multi_mesh"] = {"workload": "multi_64", **multi}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w, u_host)
+        out["cpu_baseline"] = cpu_baseline(WORKLOADS[a.workload], res["u_host"])
     print(json.dumps(out), flush=True)
 
+
+def coarse_description(levels):
+    """'exact FP64, FE1 3^3' style text from the hierarchy's coarsest level."""
+    c = levels[-1]
+    nel = c["nel"]
+    mesh = ("%d^3" % nel[0]) if nel[0] == nel[1] == nel[2] else "x".join(map(str, nel))
+    solver = "exact FP64 (dense inverse)" if c["n_dofs"] <= 8192 else "FP64 Jacobi-PCG to 1e-3"
+    return "%s, %s%d %s (%d unknowns)" % (solver, c["space"], c["degree"], mesh, c["n_dofs"])
+
+
+def run_workload(a, name, hmg, timed):
+    """Setup, solves and operator applies of one workload.  timed: the
+    contract's timed region (warm-up solves, then exactly `steps` solves
+    bracketed by synchronisations); otherwise the best of three solves."""
+    import torch
+    from paper_1910_01900_amd.inputs import WORKLOADS, tau_scale, uniform
+    w = WORKLOADS[name]
+    k = w["degree"]
+    n_el = int(np.prod(w["nel"]))
+    ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
+    mesh = hmg.Mesh(tuple(w["nel"]), k, deformed=w["deformed"], amp=w["amp"], tau_scale=ts)
+    t0 = time.time()
+    log("setup: hierarchy cph (FP32 V-cycle) for", name)
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32, graph=a.graph)
+    levels = H.levels()
+    log("setup done in %.1f s; levels:" % (time.time() - t0), [(l["space"], l["degree"], l["nel"][0]) for l in levels])
+    N = H.n_dofs
+    b = torch.as_tensor(uniform(3, N), device="cuda")
+    x = torch.zeros_like(b)
+    steps, warmup = (a.steps, a.warmup) if timed else (3, 1)
+    for i in range(warmup):
+        x.zero_()
+        _, st = H.solve(b, x, rtol=1e-10, maxit=100)
+        log("warmup solve %d: %d iterations, n10 %.2f" % (i, st["iters"], st["n10"]))
+    torch.cuda.synchronize()
+    times, stats = [], None
+    t_start = time.perf_counter()
+    for i in range(steps):
+        x.zero_()
+        t1 = time.perf_counter()
+        _, stats = H.solve(b, x, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        log("step %d: %.1f ms, %d iterations" % (i, times[-1] * 1e3, stats["iters"]))
+    total = time.perf_counter() - t_start
+    if not timed:
+        total = min(times) * steps
+    res = {"value": N * steps / total, "ms_per_step": 1e3 * total / steps}
+    del H
+    torch.cuda.empty_cache()
+    res["config"] = {"workload": name, "mesh": "x".join(map(str, w["nel"])), "degree": k,
+                     "curved": w["deformed"], "penalty_scale": "U[1,10] per element" if ts is not None else "1",
+                     "dofs": N, "strategy": "cph", "p_sequence": "floor(p/2)",
+                     "levels": ["%s%d %s" % (l["space"], l["degree"], "x".join(map(str, l["nel"]))) for l in levels],
+                     "smoother": "Chebyshev(5)", "coarse": coarse_description(levels), "rtol": 1e-10,
+                     "parallelism": "single GPU", "graph": a.graph}
+    if not a.no_plain_fp64:
+        # plain FP64: the same hierarchy with every level in FP64
+        H64 = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F64, graph=a.graph)
+        x64 = torch.zeros_like(b)
+        _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)  # warm-up
+        torch.cuda.synchronize()
+        t64 = []
+        for _ in range(max(1, min(steps, 3))):
+            x64.zero_()
+            t1 = time.perf_counter()
+            _, st64 = H64.solve(b, x64, rtol=1e-10, maxit=100)
+            torch.cuda.synchronize()
+            t64.append(time.perf_counter() - t1)
+        res["solve_plain_fp64"] = {"ns_per_dof": 1e9 * min(t64) / N, "ms": 1e3 * min(t64),
+                                   "iterations": st64["iters"], "n10": st64["n10"]}
+        log("plain FP64 solve: %.1f ms, %d iterations" % (1e3 * min(t64), st64["iters"]))
+        del H64, x64
+        torch.cuda.empty_cache()
+
+    # final residual recomputed with the FP64 operator
+    L64 = hmg.Level(mesh, prec=hmg.F64)
+    r = L64.residual(b, x)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    log("final relative residual %.3e" % rel)
+    res["solve"] = {"ms": res["ms_per_step"], "ns_per_dof": 1e6 * res["ms_per_step"] / N,
+                    "iterations": stats["iters"], "n10": stats["n10"], "rho": stats["rho"],
+                    "final_rel_residual": rel}
+    if "solve_plain_fp64" in res:
+        res["solve"]["mixed_vs_plain_fp64_speedup"] = res["solve_plain_fp64"]["ms"] / res["ms_per_step"]
+
+    # operator applies, timed with HIP events on the launch stream
+    u = L64.vector(uniform(1, L64.n_dofs))
+    v = L64.vector()
+    ms64 = time_applies(L64, u, v, a.apply_reps)
+    res["u_host"] = u.cpu().numpy() if (timed and not a.no_cpu_baseline) else None
+    del u, v, r, b, x
+    L32 = hmg.Level(mesh, prec=hmg.F32)
+    u32 = L32.vector(uniform(1, L32.n_dofs))
+    v32 = L32.vector()
+    ms32 = time_applies(L32, u32, v32, a.apply_reps)
+    del u32, v32
+    if a.nrhs > 1:
+        msb32 = time_applies_batched(L32, a.nrhs, 5)
+        del L32
+        torch.cuda.empty_cache()
+        msb64 = time_applies_batched(L64, a.nrhs, 5)
+        res["operator_apply_batched"] = {
+            "nrhs": a.nrhs, "fp64_ms": msb64, "fp32_ms": msb32,
+            "fp64_dofs_per_s": a.nrhs * N / (msb64 * 1e-3), "fp32_dofs_per_s": a.nrhs * N / (msb32 * 1e-3)}
+        log("batched apply, %d vectors: FP64 %.3f ms, FP32 %.3f ms" % (a.nrhs, msb64, msb32))
+    else:
+        del L32
+    del L64
+    torch.cuda.empty_cache()
+    bytes64 = apply_bytes(w["nel"], k, 8, w["deformed"])
+    achieved = bytes64 / (ms64 * 1e-3) / 1e9
+    log("apply FP64 %.3f ms (%.2f GDoF/s, %.0f GB/s), FP32 %.3f ms (%.2f GDoF/s)"
+        % (ms64, N / ms64 / 1e6, achieved, ms32, N / ms32 / 1e6))
+    res["operator_apply"] = {"fp64_dofs_per_s": N / (ms64 * 1e-3), "fp32_dofs_per_s": N / (ms32 * 1e-3),
+                             "fp64_ms": ms64, "fp32_ms": ms32,
+                             "fp32_achieved_GBs": apply_bytes(w["nel"], k, 4, w["deformed"]) / (ms32 * 1e-3) / 1e9}
+    res["roofline"] = {"kernel": "op_kernel<%d,double,%s,DG,APPLY>" % (k + 1, "curved" if w["deformed"] else "affine"),
+                       "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(name),
+                       "algorithmic_bytes_per_launch": bytes64}
+    flops = measured_fp64_flops(name)
+    if flops is not None:  # executed FP64 arithmetic of the same kernel, same live timing
+        tf = flops / (ms64 * 1e-3) / 1e12
+        res["roofline"]["fp64_flops"] = {"achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": tf / PEAK_FP64_TFLOPS, "per_launch": flops}
+    if not timed:
+        res.pop("u_host", None)
+    return res
 
 if __name__ == "__main__":
     main()

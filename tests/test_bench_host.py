@@ -33,23 +33,33 @@ def _summary(path, sha, traffic="4255016947", flops="10542489600"):
 
 
 def test_counter_summary_is_read_only_for_the_current_source(tmp_path, monkeypatch):
-    p = str(tmp_path / "pmc.md")
-    monkeypatch.setattr(bench, "PMC_SUMMARY", p)
+    monkeypatch.setattr(bench, "pmc_summary", lambda w: str(tmp_path / ("op_kernel_%s_f64_pmc.md" % w)))
+    p = bench.pmc_summary("curved_k7_48")
     _summary(p, bench.kernel_source_sha())
-    assert bench.measured_traffic("curved_k4_64") == 4255016947.0
-    assert bench.measured_fp64_flops("curved_k4_64") == 10542489600.0
-    # other workloads have no summary
-    assert bench.measured_traffic("curved_k7_48") is None
+    assert bench.measured_traffic("curved_k7_48") == 4255016947.0
+    assert bench.measured_fp64_flops("curved_k7_48") == 10542489600.0
+    # each workload reads its own summary: none for this one
+    assert bench.measured_traffic("curved_k4_64") is None
     # a summary taken on another kernel source is ignored
     _summary(p, "0" * 64)
-    assert bench.measured_traffic("curved_k4_64") is None
-    assert bench.measured_fp64_flops("curved_k4_64") is None
+    assert bench.measured_traffic("curved_k7_48") is None
+    assert bench.measured_fp64_flops("curved_k7_48") is None
     # missing or malformed fields
     _summary(p, bench.kernel_source_sha(), traffic="n/a", flops=None)
-    assert bench.measured_traffic("curved_k4_64") is None
-    assert bench.measured_fp64_flops("curved_k4_64") is None
-    monkeypatch.setattr(bench, "PMC_SUMMARY", str(tmp_path / "absent.md"))
-    assert bench.measured_traffic("curved_k4_64") is None
+    assert bench.measured_traffic("curved_k7_48") is None
+    assert bench.measured_fp64_flops("curved_k7_48") is None
+
+
+def test_summary_path_is_keyed_by_workload():
+    assert bench.pmc_summary("curved_k7_48").endswith(os.path.join("profiles", "op_kernel_curved_k7_48_f64_pmc.md"))
+
+
+def test_coarse_description_from_the_hierarchy():
+    lv = [{"space": "DG", "degree": 7, "nel": (48, 48, 48), "n_dofs": 56623104},
+          {"space": "FE", "degree": 1, "nel": (3, 3, 3), "n_dofs": 64}]
+    assert bench.coarse_description(lv) == "exact FP64 (dense inverse), FE1 3^3 (64 unknowns)"
+    lv[-1] = {"space": "FE", "degree": 1, "nel": (24, 24, 24), "n_dofs": 15625}
+    assert bench.coarse_description(lv).startswith("FP64 Jacobi-PCG")
 
 
 def test_kernel_source_sha_tracks_the_kernel_sources():
