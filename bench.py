@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--also", default="curved_k4_64",
                     help="comma-separated workloads reported as sub-blocks after the timed one ('' for none)")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--rhs", type=int, default=None,
+                    help="right-hand sides solved together per step (default: the workload's, 8 for curved_k7_48)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-fp64", action="store_true", help="skip the plain FP64 V-cycle solve")
     ap.add_argument("--nrhs", type=int, default=8, help="vectors per batched apply (0: skip)")
@@ -480,7 +482,8 @@ def main():
         "metric": METRIC,
         "value": res["value"],
         "value_is": "solve throughput: DoFs solved to 1e-10 relative residual per second (FP64 PCG, FP32 "
-                    "V-cycle), over the timed solves; operator-apply DoF/s in operator_apply",
+                    "V-cycle; a step solves the workload's right-hand sides together, 8 for curved_k7_48), "
+                    "over the timed steps; operator-apply DoF/s in operator_apply",
         "unit": "DoF/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -493,7 +496,7 @@ def main():
         "data": "synthetic",
         "config": res["config"],
     }
-    for key in ("solve", "solve_plain_fp64", "operator_apply", "operator_apply_batched", "roofline"):
+    for key in ("solve_batched", "solve", "solve_plain_fp64", "operator_apply", "operator_apply_batched", "roofline"):
         if key in res:
             out[key] = res[key]
     if a.also:
@@ -536,39 +539,94 @@ def run_workload(a, name, hmg, timed):
     contract's timed region (warm-up solves, then exactly `steps` solves
     bracketed by synchronisations); otherwise the best of three solves."""
     import torch
-    from paper_1910_01900_amd.inputs import WORKLOADS, tau_scale, uniform
+    from paper_1910_01900_amd.inputs import WORKLOADS, rhs_block, tau_scale, uniform
     w = WORKLOADS[name]
     k = w["degree"]
     n_el = int(np.prod(w["nel"]))
     ts = tau_scale(w["tau_scale_seed"], n_el) if w["tau_scale_seed"] is not None else None
     mesh = hmg.Mesh(tuple(w["nel"]), k, deformed=w["deformed"], amp=w["amp"], tau_scale=ts)
+    nrhs = w["nrhs"] if a.rhs is None else a.rhs
     t0 = time.time()
     log("setup: hierarchy cph (FP32 V-cycle) for", name)
-    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32, graph=a.graph)
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=hmg.F32, graph=a.graph,
+                      max_rhs=nrhs)
     levels = H.levels()
     log("setup done in %.1f s; levels:" % (time.time() - t0), [(l["space"], l["degree"], l["nel"][0]) for l in levels])
     N = H.n_dofs
     b = torch.as_tensor(uniform(3, N), device="cuda")
     x = torch.zeros_like(b)
     steps, warmup = (a.steps, a.warmup) if timed else (3, 1)
+    if nrhs > 1:  # the step: nrhs right-hand sides solved together
+        B = H.vectors(nrhs)
+        for q, v in enumerate(rhs_block(N, nrhs)):
+            B[q, :N] = torch.as_tensor(v)
+        X = H.vectors(nrhs)
+
+        def step():
+            X.zero_()
+            _, sts = H.solve_batched(B, X, rtol=1e-10, maxit=100)
+            return sts
+    else:
+        def step():
+            x.zero_()
+            _, st = H.solve(b, x, rtol=1e-10, maxit=100)
+            return [st]
     for i in range(warmup):
-        x.zero_()
-        _, st = H.solve(b, x, rtol=1e-10, maxit=100)
-        log("warmup solve %d: %d iterations, n10 %.2f" % (i, st["iters"], st["n10"]))
+        sts = step()
+        log("warmup step %d: iterations %s" % (i, [st["iters"] for st in sts]))
     torch.cuda.synchronize()
     times, stats = [], None
     t_start = time.perf_counter()
     for i in range(steps):
-        x.zero_()
         t1 = time.perf_counter()
-        _, stats = H.solve(b, x, rtol=1e-10, maxit=100)
+        stats = step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t1)
-        log("step %d: %.1f ms, %d iterations" % (i, times[-1] * 1e3, stats["iters"]))
+        log("step %d: %.1f ms, iterations %s" % (i, times[-1] * 1e3, [st["iters"] for st in stats]))
     total = time.perf_counter() - t_start
     if not timed:
         total = min(times) * steps
-    res = {"value": N * steps / total, "ms_per_step": 1e3 * total / steps}
+    res = {"value": nrhs * N * steps / total, "ms_per_step": 1e3 * total / steps}
+    if nrhs > 1:
+        # the same right-hand sides one after another, and the single solve of stream 3
+        Xs = H.vectors(nrhs)
+        seq = []
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for q in range(nrhs):
+                Xs[q].zero_()
+                H.solve(B[q, :N], Xs[q, :N], rtol=1e-10, maxit=100)
+            torch.cuda.synchronize()
+            seq.append(time.perf_counter() - t1)
+        r64 = hmg.Level(mesh, prec=hmg.F64)
+        rel = []
+        for q in range(nrhs):
+            r = r64.residual(B[q, :N], X[q, :N])
+            rel.append(float(torch.linalg.norm(r) / torch.linalg.norm(B[q, :N])))
+        del r64, r
+        res["solve_batched"] = {
+            "nrhs": nrhs, "ms": res["ms_per_step"], "ns_per_dof_per_rhs": 1e6 * res["ms_per_step"] / (nrhs * N),
+            "sequential_ms": 1e3 * min(seq), "batched_vs_sequential_speedup": 1e3 * min(seq) / res["ms_per_step"],
+            "iterations": [st["iters"] for st in stats], "n10": [st["n10"] for st in stats],
+            "final_rel_residual": rel, "rhs": "U[-1,1], streams 200..%d" % (199 + nrhs)}
+        log("batched %d RHS: %.1f ms, sequential %.1f ms, residuals max %.2e"
+            % (nrhs, res["ms_per_step"], 1e3 * min(seq), max(rel)))
+        del B, X, Xs
+        x.zero_()
+        t1 = time.perf_counter()
+        _, st1 = H.solve(b, x, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        single_s = time.perf_counter() - t1
+        x.zero_()
+        t1 = time.perf_counter()
+        _, st1 = H.solve(b, x, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        single_s = min(single_s, time.perf_counter() - t1)
+        stats = [st1]
+    else:
+        single_s = total / steps
+    res["single_ms"] = 1e3 * single_s
     del H
     torch.cuda.empty_cache()
     res["config"] = {"workload": name, "mesh": "x".join(map(str, w["nel"])), "degree": k,
@@ -576,6 +634,7 @@ def run_workload(a, name, hmg, timed):
                      "dofs": N, "strategy": "cph", "p_sequence": "floor(p/2)",
                      "levels": ["%s%d %s" % (l["space"], l["degree"], "x".join(map(str, l["nel"]))) for l in levels],
                      "smoother": "Chebyshev(5)", "coarse": coarse_description(levels), "rtol": 1e-10,
+                     "rhs_per_step": nrhs,
                      "parallelism": "single GPU", "graph": a.graph}
     if not a.no_plain_fp64:
         # plain FP64: the same hierarchy with every level in FP64
@@ -601,11 +660,11 @@ def run_workload(a, name, hmg, timed):
     r = L64.residual(b, x)
     rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
     log("final relative residual %.3e" % rel)
-    res["solve"] = {"ms": res["ms_per_step"], "ns_per_dof": 1e6 * res["ms_per_step"] / N,
-                    "iterations": stats["iters"], "n10": stats["n10"], "rho": stats["rho"],
-                    "final_rel_residual": rel}
+    st = stats[0]
+    res["solve"] = {"ms": res["single_ms"], "ns_per_dof": 1e6 * res["single_ms"] / N, "rhs": "U[-1,1], stream 3",
+                    "iterations": st["iters"], "n10": st["n10"], "rho": st["rho"], "final_rel_residual": rel}
     if "solve_plain_fp64" in res:
-        res["solve"]["mixed_vs_plain_fp64_speedup"] = res["solve_plain_fp64"]["ms"] / res["ms_per_step"]
+        res["solve"]["mixed_vs_plain_fp64_speedup"] = res["solve_plain_fp64"]["ms"] / res["single_ms"]
 
     # operator applies, timed with HIP events on the launch stream
     u = L64.vector(uniform(1, L64.n_dofs))

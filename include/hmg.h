@@ -63,7 +63,9 @@ const char* hmg_last_error(void);
  * transfers, hierarchy, PCG; 0.2.0 (200): several vectors per launch,
  * recorded graphs, multi-mesh batches, the learned coarse correction;
  * 0.3.0 (300): the iterative coarse solve (HMG_COARSE_CG,
- * hmg_hierarchy_set_coarse_cg) for coarse levels without a dense inverse. */
+ * hmg_hierarchy_set_coarse_cg) for coarse levels without a dense inverse;
+ * 0.4.0 (400): several right-hand sides per solve (hmg_pcg_solve_batched,
+ * hmg_vcycle_batched), the FP64 iterative coarse solve. */
 int hmg_version(void);
 
 /*
@@ -252,6 +254,32 @@ typedef struct {
  */
 int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, double atol,
                   int maxit, hmg_solve_stats* stats, hipStream_t stream);
+
+/*
+ * Several right-hand sides solved together (Alg. 1 and Alg. 2 for each
+ * vector, with its own scalars): the vectors travel through every level of
+ * the V-cycle as one block, and on DG levels (the finest, with its stored
+ * geometry) every operator application of the smoother, the residual and
+ * the outer CG takes all vectors in one launch, reading the element
+ * geometry once for all of them.  Continuous FE levels, transfers and the
+ * coarse solve take the vectors one after another.
+ * set_max_rhs (1..64, default 1) reserves workspace for up to max_rhs
+ * vectors and must precede hmg_hierarchy_query and _bind.
+ * Vector q of b and x starts q*ld values after the first (FP64, device;
+ * ld >= n_dofs, ld*8 a multiple of 256; b and x must not overlap).
+ * hmg_pcg_solve_batched: x holds the start vectors on entry; each vector
+ * stops, and is left unchanged from then on, when its own ||r||/||r_0|| <=
+ * rtol or ||r|| <= atol; the call returns when all have stopped or after
+ * maxit iterations (HMG_NOT_CONVERGED if any has not).  stats (nrhs
+ * entries, may be NULL) as for hmg_pcg_solve.  Blocks.  The learned coarse
+ * solve is not available here (HMG_ERR_UNSUPPORTED).  nrhs must not
+ * exceed max_rhs; with max_rhs = 1 (nothing reserved; nrhs up to 64) or
+ * nrhs = 1 the call runs hmg_pcg_solve (hmg_vcycle) for each vector.
+ */
+int hmg_hierarchy_set_max_rhs(hmg_hierarchy* H, int max_rhs);
+int hmg_vcycle_batched(hmg_hierarchy* H, int nrhs, const double* b, double* x, int64_t ld, hipStream_t stream);
+int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b, double* x, int64_t ld, double rtol,
+                          double atol, int maxit, hmg_solve_stats* stats, hipStream_t stream);
 
 /*
  * Manufactured right-hand side for u = prod_j sin(freq * x_j):

@@ -215,7 +215,7 @@ void cheb_coeffs(int ns, double lmax, double lof, double hif, std::vector<double
 using namespace hmg;
 
 extern "C" const char* hmg_last_error(void) { return g_err.c_str(); }
-extern "C" int hmg_version(void) { return 300; }
+extern "C" int hmg_version(void) { return 400; }
 
 // ================================================================== levels
 static int level_init(const Mesh& m, int space, int prec, hmg_level** out) {
@@ -676,6 +676,14 @@ struct hmg_hierarchy {
   size_t ws_bytes = 0;
   std::vector<size_t> off_lv, off_tr, off_b, off_x, off_r;
   size_t off_f64 = 0, off_c64 = 0, off_ainv = 0, off_cg = 0, off_part = 0, off_scal = 0, off_c64v = 0;
+  // several right-hand sides solved together (hmg_pcg_solve_batched): per
+  // level blocks of max_rhs vectors (b, x, r, Chebyshev temporary) ld[l]
+  // values apart, and FP64 CG blocks (b, x, r, p, v, z) ld64 values apart
+  int max_rhs = 1;
+  std::vector<int64_t> ldl;
+  std::vector<size_t> off_bb, off_xb, off_rb, off_tb;
+  int64_t ld64 = 0;
+  size_t off_cgb = 0, off_partb = 0, off_scalb = 0, off_actb = 0;
   char* ws = nullptr;
   bool bound = false;
   // launch graphs (hmg_hierarchy_set_graph): one PCG iteration and one
@@ -712,6 +720,14 @@ struct hmg_hierarchy {
   double* part() const { return (double*)(ws + off_part); }
   double* scal() const { return (double*)(ws + off_scal); }
   double* ainv() const { return (double*)(ws + off_ainv); }
+  void* bb(int l) const { return ws + off_bb[l]; }
+  void* xb(int l) const { return ws + off_xb[l]; }
+  void* rb(int l) const { return ws + off_rb[l]; }
+  void* tb(int l) const { return ws + off_tb[l]; }
+  double* cgb(int i) const { return (double*)(ws + off_cgb) + (size_t)i * max_rhs * ld64; }
+  double* partb() const { return (double*)(ws + off_partb); }
+  double* scalb(int i) const { return (double*)(ws + off_scalb) + (size_t)i * max_rhs; }  // 0..5
+  int* actb() const { return (int*)(ws + off_actb); }
   // FP64 right-hand side and solution of the iterative coarse solve when the
   // V-cycle runs in FP32 (the coarse solve itself is an FP64 step)
   double* cb64() const { return (double*)(ws + off_c64v); }
@@ -725,6 +741,8 @@ struct hmg_hierarchy {
     for (auto* l : lv) delete l;
   }
 };
+
+static void hierarchy_layout(hmg_hierarchy* H);
 
 static bool can_h(const Mesh& m, int h_min) {
   for (int d = 0; d < 3; ++d)
@@ -820,13 +838,35 @@ extern "C" int hmg_hierarchy_create(const hmg_mesh_desc* desc, const char* strat
   // dense inverse up to 8192 unknowns; above, the coarse solve is iterative
   H->dense = H->nc <= 8192;
   H->coarse_mode = H->dense ? HMG_COARSE_EXACT : HMG_COARSE_CG;
-  // workspace layout
+  hierarchy_layout(H);
+  *out = H;
+  return HMG_OK;
+}
+
+// Values between consecutive vectors of a block: n rounded up to 256 bytes.
+static int64_t block_ld(int64_t n, size_t es) {
+  const int64_t per = 256 / (int64_t)es;
+  return (n + per - 1) / per * per;
+}
+
+// Workspace layout of a hierarchy (byte offsets and total size).
+static void hierarchy_layout(hmg_hierarchy* H) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off += align256(bytes);
     return o;
   };
+  H->off_lv.clear();
+  H->off_tr.clear();
+  H->off_b.clear();
+  H->off_x.clear();
+  H->off_r.clear();
+  H->off_bb.clear();
+  H->off_xb.clear();
+  H->off_rb.clear();
+  H->off_tb.clear();
+  H->ldl.clear();
   for (auto* L : H->lv) H->off_lv.push_back(take(L->ws_bytes));
   for (auto* T : H->tr) H->off_tr.push_back(take(T->ws_bytes));
   for (auto* L : H->lv) {
@@ -843,9 +883,23 @@ extern "C" int hmg_hierarchy_create(const hmg_mesh_desc* desc, const char* strat
   H->off_cg = take((size_t)4 * H->fine64->n_dofs * 8);
   H->off_part = take((size_t)kPartials * 8);
   H->off_scal = take(32 * 8);
+  if (H->max_rhs > 1) {
+    const size_t m = (size_t)H->max_rhs;
+    for (auto* L : H->lv) {
+      const int64_t ld = block_ld(L->n_dofs, L->elem_size());
+      H->ldl.push_back(ld);
+      H->off_bb.push_back(take(m * ld * L->elem_size()));
+      H->off_xb.push_back(take(m * ld * L->elem_size()));
+      H->off_rb.push_back(take(m * ld * L->elem_size()));
+      H->off_tb.push_back(take(m * ld * L->elem_size()));
+    }
+    H->ld64 = block_ld(H->fine64->n_dofs, 8);
+    H->off_cgb = take(6 * m * H->ld64 * 8);
+    H->off_partb = take(m * kPartialsB * 8);
+    H->off_scalb = take(6 * m * 8);
+    H->off_actb = take(m * sizeof(int));
+  }
   H->ws_bytes = off;
-  *out = H;
-  return HMG_OK;
 }
 
 extern "C" int hmg_hierarchy_query(const hmg_hierarchy* H, int64_t* n, size_t* ws) {
@@ -1067,15 +1121,16 @@ static int coarse_cg(hmg_hierarchy* H, const hmg_level* L, const void* b, void* 
 // the conversion in and the solve.  The solve sets *skip once it has
 // converged, so the conversion back is gated by the judge's decision
 // *accepted instead (0 outside the learned correction).
-static int coarse_cg64(hmg_hierarchy* H, size_t l, hipStream_t s) {
+static int coarse_cg64_at(hmg_hierarchy* H, size_t l, const void* b, void* x, hipStream_t s) {
   hmg_level* L = H->lv[l];
-  if (!H->own_coarse64) return coarse_cg(H, L, H->b(l), H->x(l), H->coarse_rtol, H->coarse_maxit, s);
+  if (!H->own_coarse64) return coarse_cg(H, L, b, x, H->coarse_rtol, H->coarse_maxit, s);
   int* skip = (int*)(H->scal() + 24);
   int* accepted = skip + 2;
-  TRY(vec_convert_gated(L->prec, H->b(l), HMG_F64, H->cb64(), H->nc, skip, s));
+  TRY(vec_convert_gated(L->prec, b, HMG_F64, H->cb64(), H->nc, skip, s));
   TRY(coarse_cg(H, H->coarse64, H->cb64(), H->cx64(), H->coarse_rtol, H->coarse_maxit, s));
-  return vec_convert_gated(HMG_F64, H->cx64(), L->prec, H->x(l), H->nc, accepted, s);
+  return vec_convert_gated(HMG_F64, H->cx64(), L->prec, x, H->nc, accepted, s);
 }
+static int coarse_cg64(hmg_hierarchy* H, size_t l, hipStream_t s) { return coarse_cg64_at(H, l, H->b(l), H->x(l), s); }
 
 // Coarsest level: x(l) from b(l) by the selected coarse solve.
 static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
@@ -1289,6 +1344,259 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   }
   if (nr / r0 > rtol && nr > atol) return finish(HMG_NOT_CONVERGED);
   return finish(HMG_OK);
+}
+
+// ================================================================== several right-hand sides
+// The V-cycle and PCG on blocks of nrhs vectors: every DG level applies its
+// operator to all vectors in one launch (the element geometry read once per
+// element for all of them); continuous FE levels, transfers and the coarse
+// solve take the vectors one after another.
+
+// Alg. 3 on nrhs vectors (vector r at r * ld); tmp: a block like x.
+static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, void* x, void* tmp, int ns,
+                       double lmax, int x_is_zero, hipStream_t s) {
+  const size_t es = L->elem_size();
+  if (L->space != HMG_DG) {
+    for (int r = 0; r < nrhs; ++r)
+      TRY(chebyshev(L, (const char*)b + r * ld * es, (char*)x + r * ld * es, ns, lmax, 0.06, 1.2, x_is_zero, s));
+    return HMG_OK;
+  }
+  std::vector<double> sig, th;
+  cheb_coeffs(ns, lmax, 0.06, 1.2, sig, th);
+  const int pr = L->prec;
+  const int64_t n = L->n_dofs, all = ld * nrhs;
+  void *cur, *oth;
+  if (x_is_zero) {
+    if (((ns - 1) & 1) == 0) {
+      cur = x;
+      oth = tmp;
+    } else {
+      cur = tmp;
+      oth = x;
+    }
+    TRY(vec_mul3_b(pr, th[0], L->dinv(), b, cur, n, ld, nrhs, s));
+    TRY(vec_fill(pr, oth, 0.0, all, s));
+  } else {
+    if ((ns & 1) == 0) {
+      cur = x;
+      oth = tmp;
+    } else {
+      TRY(vec_copy(pr, x, tmp, all, s));
+      cur = tmp;
+      oth = x;
+    }
+    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, cur, 0.0, th[0], nullptr, s));
+    std::swap(cur, oth);
+  }
+  for (int j = 1; j < ns; ++j) {
+    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, oth, sig[j], th[j], nullptr, s));
+    std::swap(cur, oth);
+  }
+  if (cur != x) return fail(HMG_ERR_INVALID, "internal: Chebyshev buffer parity");
+  return HMG_OK;
+}
+
+// r_q = b_q - A x_q for nrhs vectors
+static int residual_v(const hmg_level* L, int nrhs, int64_t ld, const void* x, void* r, const void* b,
+                      hipStream_t s) {
+  if (L->space == HMG_DG) return launch_operator_batched(L, OP_RESID, nrhs, ld, x, r, b, nullptr, 0, 0, nullptr, s);
+  const size_t o = ld * L->elem_size();
+  for (int q = 0; q < nrhs; ++q)
+    TRY(launch_operator(L, OP_RESID, (const char*)x + q * o, (char*)r + q * o, (const char*)b + q * o, nullptr, 0, 0,
+                        nullptr, s));
+  return HMG_OK;
+}
+
+// Coarsest level of the several-vector V-cycle: each vector by the selected
+// coarse solve (exact, smoothing only or the FP64 iterative solve).
+static int coarse_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
+  hmg_level* L = H->lv[l];
+  const int64_t ld = H->ldl[l];
+  const size_t o = ld * L->elem_size();
+  int* skip = (int*)(H->scal() + 24);
+  for (int q = 0; q < nrhs; ++q) {
+    const void* b = (const char*)H->bb(l) + q * o;
+    void* x = (char*)H->xb(l) + q * o;
+    switch (H->coarse_mode) {
+      case HMG_COARSE_SMOOTH:
+        TRY(chebyshev(L, b, x, H->ns, H->lmax_c, 0.06, 1.2, 1, s));
+        break;
+      case HMG_COARSE_CG:
+        TRY(set_flag(skip, 0, s));
+        if (H->own_coarse64) TRY(set_flag(skip + 2, 0, s));
+        TRY(coarse_cg64_at(H, l, b, x, s));
+        break;
+      case HMG_COARSE_EXACT:
+        TRY(coarse_gemv(L->prec, H->ainv(), b, x, (int)H->nc, s));
+        break;
+      default:
+        return fail(HMG_ERR_UNSUPPORTED, "several right-hand sides: exact, iterative or smoothing coarse solve");
+    }
+  }
+  return HMG_OK;
+}
+
+// Alg. 2 on level l for the blocks bb(l) -> xb(l), nrhs vectors.
+static int vcycle_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
+  hmg_level* L = H->lv[l];
+  if (l + 1 == H->lv.size()) return coarse_v(H, l, nrhs, s);
+  const int64_t ld = H->ldl[l], ldc = H->ldl[l + 1];
+  const size_t o = ld * L->elem_size(), oc = ldc * H->lv[l + 1]->elem_size();
+  TRY(chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 1, s));
+  TRY(residual_v(L, nrhs, ld, H->xb(l), H->rb(l), H->bb(l), s));
+  for (int q = 0; q < nrhs; ++q)
+    TRY(restrict_(H->tr[l], (const char*)H->rb(l) + q * o, (char*)H->bb(l + 1) + q * oc, s));
+  TRY(vcycle_v(H, l + 1, nrhs, s));
+  for (int q = 0; q < nrhs; ++q)
+    TRY(prolongate_add(H->tr[l], (const char*)H->xb(l + 1) + q * oc, (char*)H->xb(l) + q * o, s));
+  return chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 0, s);
+}
+
+// z_q = M^{-1} r_q (FP64 blocks, ldr and ldz values apart).
+static int precondition_v(hmg_hierarchy* H, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz,
+                          hipStream_t s) {
+  const int pr = H->mg_prec;
+  const int64_t n = H->lv[0]->n_dofs;
+  TRY(vec_convert_b(HMG_F64, r, ldr, pr, H->bb(0), H->ldl[0], n, nrhs, s));
+  TRY(vcycle_v(H, 0, nrhs, s));
+  return vec_convert_b(pr, H->xb(0), H->ldl[0], HMG_F64, z, ldz, n, nrhs, s);
+}
+
+static int check_rhs_block(const hmg_hierarchy* H, int nrhs, int64_t ld) {
+  if (!H || !H->bound) return fail(HMG_ERR_WORKSPACE, "hierarchy missing or not bound");
+  // without a reservation the vectors are solved one after another
+  if (nrhs < 1 || nrhs > (H->max_rhs > 1 ? H->max_rhs : kMaxRhs))
+    return fail(HMG_ERR_INVALID, "nrhs must be 1..max_rhs (hmg_hierarchy_set_max_rhs before bind)");
+  if (ld < H->fine64->n_dofs || (ld * 8) % 256) return fail(HMG_ERR_INVALID, "ld must be >= n_dofs, ld * 8 a multiple of 256");
+  if (nrhs > 1 && H->coarse_mode == HMG_COARSE_LEARNED)
+    return fail(HMG_ERR_UNSUPPORTED, "several right-hand sides with the learned coarse solve");
+  return HMG_OK;
+}
+
+extern "C" int hmg_hierarchy_set_max_rhs(hmg_hierarchy* H, int max_rhs) {
+  if (!H) return fail(HMG_ERR_INVALID, "hierarchy is NULL");
+  if (H->bound) return fail(HMG_ERR_INVALID, "set the number of right-hand sides before bind");
+  if (max_rhs < 1 || max_rhs > kMaxRhs) return fail(HMG_ERR_INVALID, "max_rhs must be 1..64");
+  H->max_rhs = max_rhs;
+  hierarchy_layout(H);
+  return HMG_OK;
+}
+
+extern "C" int hmg_vcycle_batched(hmg_hierarchy* H, int nrhs, const double* b, double* x, int64_t ld, hipStream_t s) {
+  TRY(check_rhs_block(H, nrhs, ld));
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(x, "x"));
+  if (ranges_overlap(b, x, (size_t)(ld * (nrhs - 1) + H->fine64->n_dofs) * 8))
+    return fail(HMG_ERR_INVALID, "b and x must not overlap");
+  if (nrhs == 1 || H->max_rhs == 1) {
+    for (int q = 0; q < nrhs; ++q) TRY(precondition(H, b + q * ld, x + q * ld, s));
+    return HMG_OK;
+  }
+  return precondition_v(H, nrhs, b, ld, x, ld, s);
+}
+
+extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b, double* x, int64_t ld, double rtol,
+                                     double atol, int maxit, hmg_solve_stats* st, hipStream_t s) {
+  TRY(check_rhs_block(H, nrhs, ld));
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(x, "x"));
+  if (maxit < 0) return fail(HMG_ERR_INVALID, "maxit < 0");
+  if (ranges_overlap(b, x, (size_t)(ld * (nrhs - 1) + H->fine64->n_dofs) * 8))
+    return fail(HMG_ERR_INVALID, "b and x must not overlap");
+  if (nrhs == 1 || H->max_rhs == 1) {  // one at a time
+    int worst = HMG_OK;
+    for (int q = 0; q < nrhs; ++q) {
+      const int rc = hmg_pcg_solve(H, b + q * ld, x + q * ld, rtol, atol, maxit, st ? st + q : nullptr, s);
+      if (rc < 0) return rc;
+      worst = std::max(worst, rc);
+    }
+    return worst;
+  }
+  const hmg_level* A = H->fine64;
+  const int64_t n = A->n_dofs, L = H->ld64;
+  double *B = H->cgb(0), *X = H->cgb(1), *R = H->cgb(2), *P = H->cgb(3), *V = H->cgb(4), *Z = H->cgb(5);
+  // scalars per vector: 0 previous delta, 1 delta = r.z, 2 p.Ap, 3 r.r, 4 z.Ap
+  double *s0 = H->scalb(0), *s1 = H->scalb(1), *s2 = H->scalb(2), *s3 = H->scalb(3), *s4 = H->scalb(4);
+  double* part = H->partb();
+  int* act = H->actb();
+  std::vector<hmg_solve_stats> stats(nrhs, hmg_solve_stats{0, 0, 0, 0, 0});
+  std::vector<int> active(nrhs, 1);
+  std::vector<double> r0(nrhs), hs(2 * nrhs);
+  auto finish = [&](int code) {
+    for (int q = 0; q < nrhs; ++q) {
+      if (stats[q].iters > 0 && stats[q].r0 > 0) {
+        stats[q].rho = std::pow(stats[q].rn / stats[q].r0, 1.0 / stats[q].iters);
+        stats[q].n10 = -10.0 / std::log10(stats[q].rho);
+      }
+      if (st) st[q] = stats[q];
+    }
+    return code;
+  };
+  auto upload_active = [&]() -> int {
+    HMG_HIP(hipMemcpyAsync(act, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    return HMG_OK;
+  };
+  TRY(vec_convert_b(HMG_F64, b, ld, HMG_F64, B, L, n, nrhs, s));
+  TRY(vec_convert_b(HMG_F64, x, ld, HMG_F64, X, L, n, nrhs, s));
+  TRY(launch_operator_batched(A, OP_RESID, nrhs, L, X, R, B, nullptr, 0, 0, nullptr, s));
+  TRY(vec_dot_b(R, R, n, L, nrhs, part, s3, s));
+  HMG_HIP(hipMemcpyAsync(hs.data(), s3, nrhs * 8, hipMemcpyDeviceToHost, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  int n_active = 0;
+  for (int q = 0; q < nrhs; ++q) {
+    r0[q] = std::sqrt(hs[q]);
+    stats[q].r0 = stats[q].rn = r0[q];
+    if (!std::isfinite(r0[q])) return finish(fail(HMG_ERR_NONFINITE, "initial residual is not finite"));
+    active[q] = (r0[q] > 0 && r0[q] > atol) ? 1 : 0;
+    n_active += active[q];
+  }
+  if (n_active == 0) return finish(HMG_OK);
+  TRY(upload_active());
+  TRY(precondition_v(H, nrhs, R, L, Z, L, s));
+  TRY(vec_copy(HMG_F64, Z, P, L * nrhs, s));
+  TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
+  int it = 0;
+  while (n_active > 0 && it < maxit) {
+    if (it > 0) {
+      TRY(precondition_v(H, nrhs, R, L, Z, L, s));
+      TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
+      if (H->flexible) {
+        TRY(vec_dot_b(Z, V, n, L, nrhs, part, s4, s));
+        TRY(cg_update_p_b(P, Z, s4, s2, n, L, nrhs, act, true, s));
+      } else {
+        TRY(cg_update_p_b(P, Z, s1, s0, n, L, nrhs, act, false, s));
+      }
+    }
+    TRY(launch_operator_batched(A, OP_APPLY, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s));
+    TRY(vec_dot_b(P, V, n, L, nrhs, part, s2, s));
+    TRY(cg_update_xr_b(X, R, P, V, s1, s2, n, L, nrhs, part, s3, s0, act, s));
+    HMG_HIP(hipMemcpyAsync(hs.data(), s2, nrhs * 8, hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipMemcpyAsync(hs.data() + nrhs, s3, nrhs * 8, hipMemcpyDeviceToHost, s));
+    HMG_HIP(hipStreamSynchronize(s));
+    ++it;
+    bool changed = false;
+    for (int q = 0; q < nrhs; ++q) {
+      if (!active[q]) continue;
+      const double nr = std::sqrt(hs[nrhs + q]);
+      stats[q].iters = it;
+      stats[q].rn = nr;
+      if (!(hs[q] > 0)) {
+        TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
+        return finish(fail(HMG_ERR_BREAKDOWN, "p^T A p <= 0: operator not SPD"));
+      }
+      if (!std::isfinite(nr)) return finish(fail(HMG_ERR_NONFINITE, "residual is not finite"));
+      if (!(nr / r0[q] > rtol && nr > atol)) {
+        active[q] = 0;
+        --n_active;
+        changed = true;
+      }
+    }
+    if (changed && n_active > 0) TRY(upload_active());
+  }
+  TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
+  HMG_HIP(hipStreamSynchronize(s));
+  return finish(n_active > 0 ? HMG_NOT_CONVERGED : HMG_OK);
 }
 
 extern "C" int hmg_hierarchy_set_coarse(hmg_hierarchy* H, int mode, hmg_net* net, double accept) {

@@ -205,6 +205,131 @@ int cg_update_p(double* p, const double* z, const double* num, const double* den
   hipLaunchKernelGGL(k_cg_p, grid_for(n), kBlock, 0, s, p, z, num, den, n, negate ? 1 : 0);
   return check_launch("cg_p");
 }
+// ------------------------------------------------------------------ several vectors
+// Vector r of a block starts r * ld values after the first; blockIdx.y = r.
+// Per-vector scalars are arrays indexed by r; active[r] == 0 freezes vector r
+// (a converged solve of a batch).
+static unsigned grid_for_b(int64_t n) {
+  unsigned g = grid_for(n, 8);
+  return g > (unsigned)kPartialsB ? (unsigned)kPartialsB : g;
+}
+template <typename A, typename B>
+__global__ void k_convert_b(const A* x, int64_t ldx, B* y, int64_t ldy, int64_t n) {
+  const A* xr = x + blockIdx.y * ldx;
+  B* yr = y + blockIdx.y * ldy;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    yr[i] = (B)xr[i];
+}
+template <typename T>
+__global__ void k_mul3_b(T a, const T* d, const T* b, T* z, int64_t n, int64_t ld) {
+  const T* br = b + blockIdx.y * ld;
+  T* zr = z + blockIdx.y * ld;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    zr[i] = a * d[i] * br[i];
+}
+// partials[r * gridDim.x + block] of x_r . y_r
+__global__ void k_dot_b(const double* x, const double* y, int64_t n, int64_t ld, double* partials) {
+  const double* xr = x + blockIdx.y * ld;
+  const double* yr = y + blockIdx.y * ld;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += xr[i] * yr[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+// out[r] = sum of partials[r * np .. r * np + np), one block per vector
+__global__ void k_reduce_b(const double* partials, int np, double* out) {
+  const double* pr = partials + (int64_t)blockIdx.x * np;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += pr[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+// omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; partials of r_r . r_r;
+// save[r] = num[r]
+__global__ void k_cg_xr_b(double* x, double* r, const double* p, const double* v, const double* num,
+                          const double* den, int64_t n, int64_t ld, double* partials, double* save,
+                          const int* active) {
+  const int q = blockIdx.y;
+  const int64_t o = q * ld;
+  double acc = 0.0;
+  if (active[q]) {
+    const double omega = num[q] / den[q];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      x[o + i] += omega * p[o + i];
+      const double ri = r[o + i] - omega * v[o + i];
+      r[o + i] = ri;
+      acc += ri * ri;
+    }
+  } else {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+      acc += r[o + i] * r[o + i];
+  }
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) {
+    partials[q * gridDim.x + blockIdx.x] = s;
+    if (blockIdx.x == 0 && save && active[q]) save[q] = num[q];
+  }
+}
+// p_r = z_r + beta_r p_r, beta_r = (+-) num[r] / den[r]
+__global__ void k_cg_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld,
+                         int neg, const int* active) {
+  const int q = blockIdx.y;
+  if (!active[q]) return;
+  const double beta = (neg ? -num[q] : num[q]) / den[q];
+  const int64_t o = q * ld;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[o + i] = z[o + i] + beta * p[o + i];
+}
+
+int vec_convert_b(int from, const void* x, int64_t ldx, int to, void* y, int64_t ldy, int64_t n, int nrhs,
+                  hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return HMG_OK;
+  const dim3 g(grid_for(n), nrhs);
+  if (from == HMG_F64 && to == HMG_F64)
+    hipLaunchKernelGGL((k_convert_b<double, double>), g, kBlock, 0, s, (const double*)x, ldx, (double*)y, ldy, n);
+  else if (from == HMG_F64)
+    hipLaunchKernelGGL((k_convert_b<double, float>), g, kBlock, 0, s, (const double*)x, ldx, (float*)y, ldy, n);
+  else if (to == HMG_F64)
+    hipLaunchKernelGGL((k_convert_b<float, double>), g, kBlock, 0, s, (const float*)x, ldx, (double*)y, ldy, n);
+  else
+    hipLaunchKernelGGL((k_convert_b<float, float>), g, kBlock, 0, s, (const float*)x, ldx, (float*)y, ldy, n);
+  return check_launch("convert_b");
+}
+int vec_mul3_b(int prec, double a, const void* d, const void* b, void* z, int64_t n, int64_t ld, int nrhs,
+               hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return HMG_OK;
+  const dim3 g(grid_for(n), nrhs);
+  PREC_DISPATCH(prec,
+                hipLaunchKernelGGL(k_mul3_b<double>, g, kBlock, 0, s, a, (const double*)d, (const double*)b,
+                                   (double*)z, n, ld),
+                hipLaunchKernelGGL(k_mul3_b<float>, g, kBlock, 0, s, (float)a, (const float*)d, (const float*)b,
+                                   (float*)z, n, ld));
+  return check_launch("mul3_b");
+}
+int vec_dot_b(const double* x, const double* y, int64_t n, int64_t ld, int nrhs, double* partials, double* out,
+              hipStream_t s) {
+  const unsigned g = grid_for_b(n);
+  hipLaunchKernelGGL(k_dot_b, dim3(g, nrhs), kBlock, 0, s, x, y, n, ld, partials);
+  TRY(check_launch("dot_b"));
+  hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)partials, (int)g, out);
+  return check_launch("reduce_b");
+}
+int cg_update_xr_b(double* x, double* r, const double* p, const double* v, const double* num, const double* den,
+                   int64_t n, int64_t ld, int nrhs, double* partials, double* rr, double* save, const int* active,
+                   hipStream_t s) {
+  const unsigned g = grid_for_b(n);
+  hipLaunchKernelGGL(k_cg_xr_b, dim3(g, nrhs), kBlock, 0, s, x, r, p, v, num, den, n, ld, partials, save, active);
+  TRY(check_launch("cg_xr_b"));
+  hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)partials, (int)g, rr);
+  return check_launch("reduce_b");
+}
+int cg_update_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld, int nrhs,
+                  const int* active, bool negate, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p_b, dim3(grid_for(n), nrhs), kBlock, 0, s, p, z, num, den, n, ld, negate ? 1 : 0, active);
+  return check_launch("cg_p_b");
+}
+
 int vec_splitmix(int prec, uint64_t seed, void* x, int64_t n, hipStream_t s) {
   if (n <= 0) return HMG_OK;
   PREC_DISPATCH(prec, hipLaunchKernelGGL(k_splitmix<double>, grid_for(n), kBlock, 0, s, seed, (double*)x, n),

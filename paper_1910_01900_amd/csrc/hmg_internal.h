@@ -163,6 +163,7 @@ namespace hmg {
 constexpr int kPartials = 1024;  // max blocks of a reduction
 constexpr int kTmpVecs = 4;      // level temporaries (Chebyshev, lambda_max)
 constexpr int kMaxRhs = 64;      // vectors per batched launch
+constexpr int kPartialsB = 256;  // max blocks per vector of a several-vector reduction
 
 // ---------------------------------------------------------------- kernel launchers
 enum OpMode { OP_APPLY = 0, OP_RESID = 1, OP_CHEB = 2, OP_DOT = 3 };
@@ -326,6 +327,24 @@ int cg_update_xr(double* x, double* r, const double* p, const double* v, const d
 // p = z + beta p, beta = *num / *den (negated if `negate`)
 int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
                 hipStream_t s, bool negate = false);
+
+// Several vectors (vector r starts r * ld values after the first), one
+// launch each; per-vector FP64 scalars are arrays indexed by r and
+// active[r] == 0 leaves vector r unchanged.
+int vec_convert_b(int from, const void* x, int64_t ldx, int to, void* y, int64_t ldy, int64_t n, int nrhs,
+                  hipStream_t s);
+int vec_mul3_b(int prec, double a, const void* d, const void* b, void* z, int64_t n, int64_t ld, int nrhs,
+               hipStream_t s);  // z_r = a d .* b_r
+// out[r] = x_r . y_r (partials: nrhs * kPartialsB values)
+int vec_dot_b(const double* x, const double* y, int64_t n, int64_t ld, int nrhs, double* partials, double* out,
+              hipStream_t s);
+// omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; rr[r] = r_r . r_r; save[r] = num[r]
+int cg_update_xr_b(double* x, double* r, const double* p, const double* v, const double* num, const double* den,
+                   int64_t n, int64_t ld, int nrhs, double* partials, double* rr, double* save, const int* active,
+                   hipStream_t s);
+// p_r = z_r + beta_r p_r, beta_r = num[r] / den[r] (negated if `negate`)
+int cg_update_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld, int nrhs,
+                  const int* active, bool negate, hipStream_t s);
 
 // transfers (element-local tensor-product kernels)
 // DG p / h: fine += P coarse, coarse = P^T fine

@@ -94,6 +94,10 @@ def lib():
             "hmg_pcg_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int,
                                         C.POINTER(SolveStats), _P]),
             "hmg_rhs_sine": (C.c_int, [_P, C.c_double, _P, _P]),
+            "hmg_hierarchy_set_max_rhs": (C.c_int, [_P, C.c_int]),
+            "hmg_vcycle_batched": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
+            "hmg_pcg_solve_batched": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_int,
+                                                C.POINTER(SolveStats), _P]),
             "hmg_net_create": (C.c_int, [C.c_int, C.c_int, C.c_uint64, C.POINTER(_P)]),
             "hmg_net_query": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
             "hmg_net_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
@@ -512,12 +516,15 @@ class Hierarchy:
     """Hybrid multigrid hierarchy + FP64 PCG (hmg_hierarchy)."""
 
     def __init__(self, mesh, strategy="cph", pseq=1, h_min=4, smoother_degree=5, mg_prec=F64,
-                 lmax_seed=1, graph=False):
+                 lmax_seed=1, graph=False, max_rhs=1):
         self.mesh = mesh
         self._h = C.c_void_p()
         desc = mesh.desc()
         check(lib().hmg_hierarchy_create(C.byref(desc), strategy.encode(), pseq, h_min, smoother_degree,
                                          mg_prec, lmax_seed, C.byref(self._h)))
+        self.max_rhs = max_rhs
+        if max_rhs != 1:
+            check(lib().hmg_hierarchy_set_max_rhs(self._h, max_rhs))
         n, ws = C.c_int64(), C.c_size_t()
         check(lib().hmg_hierarchy_query(self._h, C.byref(n), C.byref(ws)))
         self.n_dofs, self.ws_bytes = n.value, ws.value
@@ -629,6 +636,37 @@ class Hierarchy:
         check(code, allow=(0, 1) if allow_not_converged else (0,))
         return x, {"iters": st.iters, "r0": st.r0, "rn": st.rn, "rho": st.rho, "n10": st.n10,
                    "status": STATUS.get(code, code)}
+
+    def vectors(self, nrhs):
+        """nrhs zero FP64 vectors as rows of one [nrhs, ld] tensor, ld padded to 256 bytes."""
+        torch = _torch()
+        ld = (self.n_dofs + 31) // 32 * 32
+        return torch.zeros(nrhs, ld, dtype=torch.float64, device="cuda")
+
+    def vcycle_batched(self, B, X=None):
+        """X[q] = M^{-1} B[q] for every row (2-D tensors of FP64 rows)."""
+        X = self.vectors(B.shape[0]) if X is None else X
+        if B.shape[0] != X.shape[0] or B.stride(0) != X.stride(0):
+            raise ValueError("B and X need the same rows and row stride")
+        n, dt = self.n_dofs, _torch().float64
+        check(lib().hmg_vcycle_batched(self._h, B.shape[0], rows(B, dt, n, "B"), rows(X, dt, n, "X"), B.stride(0),
+                                       stream()))
+        return X
+
+    def solve_batched(self, B, X=None, rtol=1e-10, atol=0.0, maxit=200, allow_not_converged=False):
+        """PCG on every row of B at once (hmg_pcg_solve_batched); X holds the
+        start vectors (zeros if None).  Returns X and a list of stats."""
+        X = self.vectors(B.shape[0]) if X is None else X
+        if B.shape[0] != X.shape[0] or B.stride(0) != X.stride(0):
+            raise ValueError("B and X need the same rows and row stride")
+        nrhs = B.shape[0]
+        st = (SolveStats * nrhs)()
+        n, dt = self.n_dofs, _torch().float64
+        code = lib().hmg_pcg_solve_batched(self._h, nrhs, rows(B, dt, n, "B"), rows(X, dt, n, "X"), B.stride(0),
+                                           rtol, atol, maxit, st, stream())
+        check(code, allow=(0, 1) if allow_not_converged else (0,))
+        return X, [{"iters": s.iters, "r0": s.r0, "rn": s.rn, "rho": s.rho, "n10": s.n10,
+                    "status": STATUS.get(code, code)} for s in st]
 
     def __del__(self):
         if getattr(self, "_h", None) and self._h.value and _lib is not None:

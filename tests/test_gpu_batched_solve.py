@@ -1,0 +1,110 @@
+"""Several right-hand sides solved together (hmg_pcg_solve_batched,
+hmg_vcycle_batched): every vector's final residual recomputed with the
+oracle's operator, iteration counts against one-at-a-time solves, the
+batched V-cycle against single V-cycles, per-vector stopping (a zero
+right-hand side, vectors of different scale, start vectors), and the
+argument errors."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import meshes, rel_inf, to_np
+from oracle import sipg
+from paper_1910_01900_amd import hmg
+from paper_1910_01900_amd.inputs import tau_scale, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _block(H, seeds, scale=None):
+    B = H.vectors(len(seeds))
+    for q, sd in enumerate(seeds):
+        v = uniform(sd, H.n_dofs) * (1.0 if scale is None else scale[q])
+        B[q, :H.n_dofs] = torch.as_tensor(v)
+    return B
+
+
+def _oracle_residual(om, k, b, x):
+    return np.linalg.norm(b - sipg.apply(om, k, x).ravel()) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("mg_prec", [hmg.F64, hmg.F32])
+def test_batched_solve_residuals_and_iterations(mg_prec):
+    k, nel = 3, (4, 4, 4)
+    hm, om = meshes(nel, k, True, bc=(0, 0, 0, 1, 0, 0))
+    print("batched solve k=%d nel=%s prec=%d" % (k, nel, mg_prec), flush=True)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=mg_prec, max_rhs=4)
+    B = _block(H, [60, 61, 62])
+    X, st = H.solve_batched(B, rtol=1e-10)
+    for q in range(3):
+        b, x = to_np(B[q, :H.n_dofs]), to_np(X[q, :H.n_dofs])
+        res = _oracle_residual(om, k, b, x)
+        _, s1 = H.solve(B[q, :H.n_dofs].contiguous(), rtol=1e-10)
+        print("rhs %d: batched %d its (res %.2e), single %d its" % (q, st[q]["iters"], res, s1["iters"]))
+        assert res <= 1.05e-10
+        assert abs(st[q]["iters"] - s1["iters"]) <= 1
+        assert st[q]["rn"] / st[q]["r0"] <= 1e-10
+
+
+def test_batched_solve_of_the_k7_workload_at_reduced_size():
+    """k = 7, curvilinear, penalty scale U[1, 10], FP32 V-cycle in FP64 CG,
+    two right-hand sides (2^3 elements, 4,096 DoFs each)."""
+    k, nel = 7, (2, 2, 2)
+    hm, om = meshes(nel, k, True, tau_scale=tau_scale(5, 8))
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=hmg.F32, max_rhs=2)
+    B = _block(H, [63, 64])
+    X, st = H.solve_batched(B, rtol=1e-10)
+    A = sipg.assemble(om, k)
+    for q in range(2):
+        b, x = to_np(B[q, :H.n_dofs]), to_np(X[q, :H.n_dofs])
+        res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        allow = 1e-12 * np.linalg.norm(abs(A) @ np.abs(x)) / np.linalg.norm(b)
+        print("k7 rhs %d: %s, oracle residual %.3e (allowance %.1e)" % (q, st[q], res, allow))
+        assert res <= 1.05e-10 + allow
+
+
+@pytest.mark.parametrize("mg_prec", [hmg.F64, hmg.F32])
+def test_batched_vcycle_equals_single(mg_prec):
+    hm, _ = meshes((4, 4, 2), 4, True)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=mg_prec, max_rhs=3)
+    B = _block(H, [65, 66, 67])
+    X = H.vcycle_batched(B)
+    for q in range(3):
+        x1 = H.vcycle(B[q, :H.n_dofs].contiguous())
+        d = rel_inf(to_np(X[q, :H.n_dofs]), to_np(x1))
+        print("vector %d: rel diff %.2e (bitwise %s)" % (q, d, bool(torch.equal(X[q, :H.n_dofs], x1))))
+        assert d <= 1e-15
+
+
+def test_batched_solve_stops_each_vector_on_its_own():
+    hm, om = meshes((4, 4, 4), 2, False)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=hmg.F32, max_rhs=4)
+    B = _block(H, [68, 69, 70, 71], scale=[1.0, 1e-6, 0.0, 1.0])
+    X = H.vectors(4)
+    x0 = uniform(72, H.n_dofs)
+    X[3, :H.n_dofs] = torch.as_tensor(x0)  # a start vector
+    X, st = H.solve_batched(B, X, rtol=1e-10)
+    assert st[2]["iters"] == 0 and bool((X[2] == 0).all())  # zero right-hand side: nothing to do
+    # the scaled right-hand side needs the same iterations (relative criterion)
+    assert abs(st[1]["iters"] - st[0]["iters"]) <= 1
+    for q in (0, 1, 3):
+        b, x = to_np(B[q, :H.n_dofs]), to_np(X[q, :H.n_dofs])
+        assert _oracle_residual(om, 2, b, x) <= 1.05e-10 * (1.0 if q != 3 else np.linalg.norm(
+            b - sipg.apply(om, 2, x0).ravel()) / np.linalg.norm(b))
+    # padding between vectors is left alone
+    assert bool((X[:, H.n_dofs:] == 0).all())
+
+
+def test_batched_solve_argument_errors():
+    hm, _ = meshes((4, 4, 4), 2, False)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, max_rhs=2)
+    B = _block(H, [73, 74, 75])
+    with pytest.raises(hmg.HmgError) as ei:  # more vectors than reserved
+        H.solve_batched(B)
+    assert ei.value.code == -1
+    with pytest.raises(ValueError):  # FP32 block
+        H.solve_batched(B[:2].float())
+    H1 = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1)
+    # no reservation: the vectors are solved one after another
+    X, st = H1.solve_batched(B[:2])
+    assert all(s["rn"] / s["r0"] <= 1e-10 for s in st)

@@ -18,7 +18,7 @@ def test_exports_every_declared_symbol():
     assert len(declared) >= 25
     missing = [s for s in declared if s not in exported]
     assert not missing, missing
-    assert hmg.lib().hmg_version() == 300
+    assert hmg.lib().hmg_version() == 400
 
 
 def _create(mesh, space=hmg.DG, prec=hmg.F64):
@@ -231,3 +231,39 @@ def test_network_and_coarse_mode_arguments_host():
     assert lib.hmg_hierarchy_coarse_solve_batch(H, None, None, 1, None) == -6  # not bound
     lib.hmg_hierarchy_destroy(H)
     lib.hmg_net_destroy(n)
+
+
+def test_max_rhs_reserves_workspace_host():
+    """hmg_hierarchy_set_max_rhs (before bind): range checks, and the
+    workspace grows by the per-level blocks (b, x, r, Chebyshev temporary
+    of max_rhs vectors each) and the six FP64 CG blocks."""
+    lib = hmg.lib()
+    m = hmg.Mesh((8, 8, 8), 3, deformed=True, amp=0.05)
+    h = C.c_void_p()
+    d = m.desc()
+    assert lib.hmg_hierarchy_create(C.byref(d), b"cph", 1, 4, 5, hmg.F32, 1, C.byref(h)) == 0
+    n, ws1 = C.c_int64(), C.c_size_t()
+    assert lib.hmg_hierarchy_query(h, C.byref(n), C.byref(ws1)) == 0
+    for bad in (0, 65, -3):
+        assert lib.hmg_hierarchy_set_max_rhs(h, bad) == -1
+    assert lib.hmg_hierarchy_set_max_rhs(h, 4) == 0
+    ws4 = C.c_size_t()
+    assert lib.hmg_hierarchy_query(h, C.byref(n), C.byref(ws4)) == 0
+    ld64 = (n.value + 31) // 32 * 32
+    assert ws4.value - ws1.value >= 6 * 4 * ld64 * 8
+    levels = C.c_int()
+    lib.hmg_hierarchy_levels(h, C.byref(levels))
+    extra = 0
+    for l in range(levels.value):
+        info = hmg.LevelInfo()
+        lib.hmg_hierarchy_level_info(h, l, C.byref(info))
+        extra += 4 * 4 * ((info.n_dofs + 63) // 64 * 64) * 4  # FP32 levels
+    assert ws4.value - ws1.value >= 6 * 4 * ld64 * 8 + extra
+    assert lib.hmg_hierarchy_set_max_rhs(h, 1) == 0
+    ws = C.c_size_t()
+    lib.hmg_hierarchy_query(h, C.byref(n), C.byref(ws))
+    assert ws.value == ws1.value
+    # a batched solve before bind is refused
+    st = (hmg.SolveStats * 2)()
+    assert lib.hmg_pcg_solve_batched(h, 2, None, None, ld64, 1e-10, 0.0, 10, st, None) == -6
+    lib.hmg_hierarchy_destroy(h)
