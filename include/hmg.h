@@ -65,7 +65,8 @@ const char* hmg_last_error(void);
  * 0.3.0 (300): the iterative coarse solve (HMG_COARSE_CG,
  * hmg_hierarchy_set_coarse_cg) for coarse levels without a dense inverse;
  * 0.4.0 (400): several right-hand sides per solve (hmg_pcg_solve_batched,
- * hmg_vcycle_batched), the FP64 iterative coarse solve. */
+ * hmg_vcycle_batched), the operator apply without allocation
+ * (hmg_operator_apply_noalloc), the FP64 iterative coarse solve. */
 int hmg_version(void);
 
 /*
@@ -118,6 +119,24 @@ void hmg_level_destroy(hmg_level* L);
  * u and v must not overlap.  v is overwritten.
  */
 int hmg_operator_apply(const hmg_level* L, const void* u, void* v, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory at call time (work recorded
+ * into HIP graphs, tight serving loops, harnesses that forbid allocation):
+ * the operator of hmg_operator_apply, v = A u, with nothing allocated and no
+ * workspace beyond the level's bound one.  On a continuous FE level the
+ * element-local results (n_el (k+1)^3 values of the level precision) go to
+ * a static device array of HMG_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every GPU it runs on until the process ends; levels needing more
+ * return HMG_ERR_UNSUPPORTED before any launch.  DG levels need no such
+ * buffer (the call equals hmg_operator_apply).  Results are bitwise equal
+ * to hmg_operator_apply.  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must
+ * be ordered by the caller.  Nothing in the array needs clearing: every
+ * call writes all the values it reads.
+ */
+#define HMG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hmg_operator_apply_noalloc(const hmg_level* L, const void* u, void* v, hipStream_t stream);
 
 /* r = b - A u (the residual of Alg. 2).  r must not overlap u. */
 int hmg_residual(const hmg_level* L, const void* b, const void* u, void* r, hipStream_t stream);

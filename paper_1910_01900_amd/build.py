@@ -32,7 +32,7 @@ def _units():
         obj = os.path.join(BUILD, src + ".o")
         units.append((obj, [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + COMMON +
                       ["-c", os.path.join(CSRC, src), "-o", obj]))
-    for src in ("aux_kernels", "net_kernels"):
+    for src in ("aux_kernels", "net_kernels", "noalloc"):
         obj = os.path.join(BUILD, src + ".o")
         units.append((obj, [HIPCC] + DEVICE + COMMON + ["-c", os.path.join(CSRC, src + ".hip"), "-o", obj]))
     for k in DEGREES:

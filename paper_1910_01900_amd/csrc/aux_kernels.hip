@@ -523,11 +523,12 @@ static void launch_fe_sum(int mode, dim3 g, dim3 blk, const FeGeo& G, const T* d
 
 template <typename T>
 static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                    const void* xold, double sigma, double theta, hipStream_t s, const int* skip) {
+                    const void* xold, double sigma, double theta, hipStream_t s, const int* skip,
+                    const void* scratch) {
   FeGeo G = fe_geo(L->mesh, L->k);
   if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
   const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
-  const T* dg = (const T*)L->scratch();
+  const T* dg = (const T*)(scratch ? scratch : L->scratch());
   const T* di = (const T*)L->dinv();
   switch (G.k) {
     case 1: launch_fe_sum<T, 1>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
@@ -542,9 +543,10 @@ static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, cons
   return check_launch("fe_sum");
 }
 int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                const void* xold, double sigma, double theta, hipStream_t s, const int* skip) {
-  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s, skip);
-  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s, skip);
+                const void* xold, double sigma, double theta, hipStream_t s, const int* skip,
+                const void* scratch) {
+  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch);
+  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch);
 }
 
 // ------------------------------------------------------------------ gated CG (coarse solve)

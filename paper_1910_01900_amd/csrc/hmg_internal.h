@@ -281,6 +281,12 @@ int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, 
                             const void* b, const void* xold, double sigma, double theta, int* nparts,
                             hipStream_t s);
 
+// launch_operator (OP_APPLY) with the element-local results of a continuous
+// FE level written to and summed from `scratch` (at least n_dg values of
+// the level precision) instead of the level's own buffer; DG levels use
+// no such buffer and ignore it.
+int launch_operator_scratch(const hmg_level* L, const void* u, void* out, void* scratch, hipStream_t s);
+
 // launch_operator with a device gate: on continuous FE levels every kernel
 // of the apply returns at once while *skip != 0 (DG levels ignore it).
 int launch_operator_gated(const hmg_level* L, int mode, const void* u, void* out, const void* b,
@@ -360,8 +366,10 @@ int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int we
 int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
              hipStream_t s);
 // FE operator node sum with a mode (see launch_operator)
+// (scratch: the element-local results, NULL for the level's own buffer)
 int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
-                const void* xold, double sigma, double theta, hipStream_t s, const int* skip = nullptr);
+                const void* xold, double sigma, double theta, hipStream_t s, const int* skip = nullptr,
+                const void* scratch = nullptr);
 // coarse dense FP64 inverse apply: x = Ainv b (b, x of prec), n unknowns
 int coarse_gemv(int prec, const double* Ainv, const void* b, void* x, int n, hipStream_t s);
 // SplitMix64 uniform [-1,1) vector

@@ -76,14 +76,15 @@ static constexpr int kTileY = 4;
 template <int N, typename T, bool CURVED, bool FE>
 static int run_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                   const void* xold, double sigma, double theta, int* nparts, int nrhs, int64_t ld,
-                  const int* skip, hipStream_t s) {
+                  const int* skip, void* scratch, hipStream_t s) {
   using C = Cfg<N, CURVED, FE>;
   OpArgs<T> a = make_args<T>(L);
   a.skip = FE ? skip : nullptr;
   a.nrhs = nrhs;
   a.ld = ld;
   a.u = (const T*)u;
-  a.out = (T*)(FE ? L->scratch() : out);
+  if (FE && !scratch) scratch = L->scratch();
+  a.out = (T*)(FE ? scratch : out);
   a.b = (const T*)b;
   a.xold = (const T*)xold;
   a.sigma = (T)sigma;
@@ -117,21 +118,21 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   }
   int rc = check_launch("op_kernel");
   if (rc) return rc;
-  if (FE) return fe_node_sum(L, mode, u, out, b, xold, sigma, theta, s, skip);
+  if (FE) return fe_node_sum(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch);
   return HMG_OK;
 }
 
 template <int N, typename T>
 static int dispatch_op(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                        const void* xold, double sigma, double theta, int* nparts, int nrhs, int64_t ld,
-                       const int* skip, hipStream_t s) {
+                       const int* skip, void* sc, hipStream_t s) {
   const bool curved = L->mesh.curved, fe = L->space == HMG_FE;
   if (curved) {
-    if (fe) return run_op<N, T, true, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
-    return run_op<N, T, true, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+    if (fe) return run_op<N, T, true, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
+    return run_op<N, T, true, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
   }
-  if (fe) return run_op<N, T, false, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
-  return run_op<N, T, false, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+  if (fe) return run_op<N, T, false, true>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
+  return run_op<N, T, false, false>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
 }
 
 template <int N, typename T, bool CURVED, bool P>
@@ -180,10 +181,11 @@ static int occ_multi(int mode) {
 #ifdef HMG_ONLY_N
 int HMG_CAT(op_launch_n, HMG_ONLY_N)(const hmg_level* L, int mode, const void* u, void* out,
                                       const void* b, const void* xold, double sigma, double theta,
-                                      int* nparts, int nrhs, int64_t ld, const int* skip, hipStream_t s) {
+                                      int* nparts, int nrhs, int64_t ld, const int* skip, void* sc,
+                                      hipStream_t s) {
   if (L->prec == HMG_F64)
-    return dispatch_op<HMG_ONLY_N, double>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
-  return dispatch_op<HMG_ONLY_N, float>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+    return dispatch_op<HMG_ONLY_N, double>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
+  return dispatch_op<HMG_ONLY_N, float>(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
 }
 int HMG_CAT(multi_launch_n, HMG_ONLY_N)(int prec, bool curved, int mode, const MultiLaunch& m, hipStream_t s) {
   if (prec == HMG_F64)
@@ -201,7 +203,7 @@ int HMG_CAT(multi_occupancy_n, HMG_ONLY_N)(int prec, bool curved, int mode) {
 #ifdef HMG_DISPATCH_ONLY
 #define HMG_DECL(N)                                                                          \
   int op_launch_n##N(const hmg_level*, int, const void*, void*, const void*, const void*,    \
-                     double, double, int*, int, int64_t, const int*, hipStream_t);            \
+                     double, double, int*, int, int64_t, const int*, void*, hipStream_t);     \
   int multi_launch_n##N(int, bool, int, const MultiLaunch&, hipStream_t);                     \
   int multi_occupancy_n##N(int, bool, int);
 HMG_DECL(2)
@@ -218,13 +220,14 @@ int launch_operator(const hmg_level* L, int mode, const void* u, void* out, cons
 }
 
 static int launch_any(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out, const void* b,
-                      const void* xold, double sigma, double theta, int* nparts, const int* skip, hipStream_t s) {
+                      const void* xold, double sigma, double theta, int* nparts, const int* skip, void* sc,
+                      hipStream_t s) {
   if (L->n_el == 0 || nrhs == 0) return HMG_OK;
   if (nrhs > 1 && (L->space != HMG_DG || mode == OP_DOT))
     return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: DG levels, apply/residual/Chebyshev only");
   switch (L->n) {
 #define HMG_CASE(N) \
-  case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, s);
+  case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
     HMG_CASE(2) HMG_CASE(3) HMG_CASE(4) HMG_CASE(5) HMG_CASE(6) HMG_CASE(7) HMG_CASE(8)
 #undef HMG_CASE
   }
@@ -234,12 +237,16 @@ static int launch_any(const hmg_level* L, int mode, int nrhs, int64_t ld, const 
 int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
                             const void* b, const void* xold, double sigma, double theta, int* nparts,
                             hipStream_t s) {
-  return launch_any(L, mode, nrhs, ld, u, out, b, xold, sigma, theta, nparts, nullptr, s);
+  return launch_any(L, mode, nrhs, ld, u, out, b, xold, sigma, theta, nparts, nullptr, nullptr, s);
 }
 
 int launch_operator_gated(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                           const int* skip, hipStream_t s) {
-  return launch_any(L, mode, 1, L->n_dofs, u, out, b, nullptr, 0, 0, nullptr, skip, s);
+  return launch_any(L, mode, 1, L->n_dofs, u, out, b, nullptr, 0, 0, nullptr, skip, nullptr, s);
+}
+
+int launch_operator_scratch(const hmg_level* L, const void* u, void* out, void* scratch, hipStream_t s) {
+  return launch_any(L, OP_APPLY, 1, L->n_dofs, u, out, nullptr, nullptr, 0, 0, nullptr, nullptr, scratch, s);
 }
 
 int multi_launch(int n, int prec, bool curved, int mode, const MultiLaunch& m, hipStream_t s) {

@@ -67,6 +67,7 @@ def lib():
             "hmg_level_bind": (C.c_int, [_P, _P, C.c_size_t, _P]),
             "hmg_level_destroy": (None, [_P]),
             "hmg_operator_apply": (C.c_int, [_P, _P, _P, _P]),
+            "hmg_operator_apply_noalloc": (C.c_int, [_P, _P, _P, _P]),
             "hmg_residual": (C.c_int, [_P, _P, _P, _P, _P]),
             "hmg_operator_apply_batched": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
             "hmg_residual_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int64, _P]),
@@ -272,6 +273,13 @@ class Level:
         v = self.vector() if v is None else v
         n, dt = self.n_dofs, self.dtype
         check(lib().hmg_operator_apply(self._h, vec(u, dt, n, "u"), vec(v, dt, n, "v"), stream()))
+        return v
+
+    def apply_noalloc(self, u, v):
+        """v = A u through hmg_operator_apply_noalloc (no allocation; the FE
+        element-local results in the library's static device buffer)."""
+        n, dt = self.n_dofs, self.dtype
+        check(lib().hmg_operator_apply_noalloc(self._h, vec(u, dt, n, "u"), vec(v, dt, n, "v"), stream()))
         return v
 
     def residual(self, b, u, r=None):
