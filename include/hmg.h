@@ -277,11 +277,11 @@ int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, dou
 /*
  * Several right-hand sides solved together (Alg. 1 and Alg. 2 for each
  * vector, with its own scalars): the vectors travel through every level of
- * the V-cycle as one block, and on DG levels (the finest, with its stored
- * geometry) every operator application of the smoother, the residual and
- * the outer CG takes all vectors in one launch, reading the element
- * geometry once for all of them.  Continuous FE levels, transfers and the
- * coarse solve take the vectors one after another.
+ * the V-cycle as one block: every operator application of the smoothers,
+ * the residuals and the outer CG takes all vectors in one launch, reading
+ * the element geometry once for all of them (on continuous FE levels the
+ * node sums then follow vector by vector); transfers and the coarse solve
+ * take the vectors one after another.
  * set_max_rhs (1..64, default 1) reserves workspace for up to max_rhs
  * vectors and must precede hmg_hierarchy_query and _bind.
  * Vector q of b and x starts q*ld values after the first (FP64, device;

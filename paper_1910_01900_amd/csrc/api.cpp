@@ -681,7 +681,7 @@ struct hmg_hierarchy {
   // values apart, and FP64 CG blocks (b, x, r, p, v, z) ld64 values apart
   int max_rhs = 1;
   std::vector<int64_t> ldl;
-  std::vector<size_t> off_bb, off_xb, off_rb, off_tb;
+  std::vector<size_t> off_bb, off_xb, off_rb, off_tb, off_sb;  // off_sb: FE element-local results
   int64_t ld64 = 0;
   size_t off_cgb = 0, off_partb = 0, off_scalb = 0, off_actb = 0;
   char* ws = nullptr;
@@ -724,6 +724,7 @@ struct hmg_hierarchy {
   void* xb(int l) const { return ws + off_xb[l]; }
   void* rb(int l) const { return ws + off_rb[l]; }
   void* tb(int l) const { return ws + off_tb[l]; }
+  void* sb(int l) const { return lv[l]->space == HMG_FE ? (void*)(ws + off_sb[l]) : nullptr; }
   double* cgb(int i) const { return (double*)(ws + off_cgb) + (size_t)i * max_rhs * ld64; }
   double* partb() const { return (double*)(ws + off_partb); }
   double* scalb(int i) const { return (double*)(ws + off_scalb) + (size_t)i * max_rhs; }  // 0..5
@@ -866,6 +867,7 @@ static void hierarchy_layout(hmg_hierarchy* H) {
   H->off_xb.clear();
   H->off_rb.clear();
   H->off_tb.clear();
+  H->off_sb.clear();
   H->ldl.clear();
   for (auto* L : H->lv) H->off_lv.push_back(take(L->ws_bytes));
   for (auto* T : H->tr) H->off_tr.push_back(take(T->ws_bytes));
@@ -892,6 +894,7 @@ static void hierarchy_layout(hmg_hierarchy* H) {
       H->off_xb.push_back(take(m * ld * L->elem_size()));
       H->off_rb.push_back(take(m * ld * L->elem_size()));
       H->off_tb.push_back(take(m * ld * L->elem_size()));
+      H->off_sb.push_back(take(L->space == HMG_FE ? m * L->n_dg * L->elem_size() : 0));
     }
     H->ld64 = block_ld(H->fine64->n_dofs, 8);
     H->off_cgb = take(6 * m * H->ld64 * 8);
@@ -1347,16 +1350,18 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
 }
 
 // ================================================================== several right-hand sides
-// The V-cycle and PCG on blocks of nrhs vectors: every DG level applies its
+// The V-cycle and PCG on blocks of nrhs vectors: every level applies its
 // operator to all vectors in one launch (the element geometry read once per
-// element for all of them); continuous FE levels, transfers and the coarse
-// solve take the vectors one after another.
+// element for all of them; the node sums of continuous FE levels follow
+// vector by vector); transfers and the coarse solve take the vectors one
+// after another.
 
-// Alg. 3 on nrhs vectors (vector r at r * ld); tmp: a block like x.
+// Alg. 3 on nrhs vectors (vector r at r * ld); tmp: a block like x;
+// fe: the element-local results block of a continuous FE level.
 static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, void* x, void* tmp, int ns,
-                       double lmax, int x_is_zero, hipStream_t s) {
+                       double lmax, int x_is_zero, void* fe, hipStream_t s) {
   const size_t es = L->elem_size();
-  if (L->space != HMG_DG) {
+  if (L->space != HMG_DG && !fe) {
     for (int r = 0; r < nrhs; ++r)
       TRY(chebyshev(L, (const char*)b + r * ld * es, (char*)x + r * ld * es, ns, lmax, 0.06, 1.2, x_is_zero, s));
     return HMG_OK;
@@ -1385,11 +1390,11 @@ static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, 
       cur = tmp;
       oth = x;
     }
-    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, cur, 0.0, th[0], nullptr, s));
+    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, cur, 0.0, th[0], nullptr, s, fe));
     std::swap(cur, oth);
   }
   for (int j = 1; j < ns; ++j) {
-    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, oth, sig[j], th[j], nullptr, s));
+    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, oth, sig[j], th[j], nullptr, s, fe));
     std::swap(cur, oth);
   }
   if (cur != x) return fail(HMG_ERR_INVALID, "internal: Chebyshev buffer parity");
@@ -1397,9 +1402,10 @@ static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, 
 }
 
 // r_q = b_q - A x_q for nrhs vectors
-static int residual_v(const hmg_level* L, int nrhs, int64_t ld, const void* x, void* r, const void* b,
+static int residual_v(const hmg_level* L, int nrhs, int64_t ld, const void* x, void* r, const void* b, void* fe,
                       hipStream_t s) {
-  if (L->space == HMG_DG) return launch_operator_batched(L, OP_RESID, nrhs, ld, x, r, b, nullptr, 0, 0, nullptr, s);
+  if (L->space == HMG_DG || fe)
+    return launch_operator_batched(L, OP_RESID, nrhs, ld, x, r, b, nullptr, 0, 0, nullptr, s, fe);
   const size_t o = ld * L->elem_size();
   for (int q = 0; q < nrhs; ++q)
     TRY(launch_operator(L, OP_RESID, (const char*)x + q * o, (char*)r + q * o, (const char*)b + q * o, nullptr, 0, 0,
@@ -1442,14 +1448,14 @@ static int vcycle_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
   if (l + 1 == H->lv.size()) return coarse_v(H, l, nrhs, s);
   const int64_t ld = H->ldl[l], ldc = H->ldl[l + 1];
   const size_t o = ld * L->elem_size(), oc = ldc * H->lv[l + 1]->elem_size();
-  TRY(chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 1, s));
-  TRY(residual_v(L, nrhs, ld, H->xb(l), H->rb(l), H->bb(l), s));
+  TRY(chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 1, H->sb(l), s));
+  TRY(residual_v(L, nrhs, ld, H->xb(l), H->rb(l), H->bb(l), H->sb(l), s));
   for (int q = 0; q < nrhs; ++q)
     TRY(restrict_(H->tr[l], (const char*)H->rb(l) + q * o, (char*)H->bb(l + 1) + q * oc, s));
   TRY(vcycle_v(H, l + 1, nrhs, s));
   for (int q = 0; q < nrhs; ++q)
     TRY(prolongate_add(H->tr[l], (const char*)H->xb(l + 1) + q * oc, (char*)H->xb(l) + q * o, s));
-  return chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 0, s);
+  return chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 0, H->sb(l), s);
 }
 
 // z_q = M^{-1} r_q (FP64 blocks, ldr and ldz values apart).

@@ -274,12 +274,13 @@ int fused_occupancy(int prec, int mode);
 // OP_DOT : out = A u, partials[blk] = sum u.(A u) (for p^T A p).
 int launch_operator(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, int* nparts, hipStream_t s);
-// The same for nrhs vectors at once (DG levels; OP_APPLY, OP_RESID, OP_CHEB):
-// vector r of u, out, b, xold starts r*ld values after the first; dinv is
-// shared.
+// The same for nrhs vectors at once (OP_APPLY, OP_RESID, OP_CHEB): vector r
+// of u, out, b, xold starts r*ld values after the first; dinv is shared.
+// Continuous FE levels with nrhs > 1 need fe_results, a block of nrhs *
+// n_dg values of the level precision for the element-local results.
 int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
                             const void* b, const void* xold, double sigma, double theta, int* nparts,
-                            hipStream_t s);
+                            hipStream_t s, void* fe_results = nullptr);
 
 // launch_operator (OP_APPLY) with the element-local results of a continuous
 // FE level written to and summed from `scratch` (at least n_dg values of

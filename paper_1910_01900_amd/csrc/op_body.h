@@ -729,21 +729,24 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = v;
     }
   } else {
-    // continuous FE levels take one vector; element and node indices fit
-    // in 32 bits (the level's node count is checked on the host)
-    const unsigned e0 = (unsigned)it0;
+    // continuous FE levels: work item = (element, vector), vector fastest,
+    // vector r of the input r * ld values after the first; element and node
+    // indices fit in 32 bits (the level's node count is checked on the host)
     constexpr int k = N - 1;
     const int Mx = a.Nx * k + 1, My = a.Ny * k + 1, Mz = a.Nz * k + 1;
     for (int idx = lane; idx < nload; idx += 64) {
       const int li = idx / N3, p = idx - li * N3;
-      const unsigned ee = e0 + li, rr = ee / (unsigned)a.Nx, ez = rr / (unsigned)a.Ny;
+      const int64_t item = it0 + li;
+      const int64_t elv = a.nrhs == 1 ? item : item / a.nrhs;
+      const T* const uv = a.u + (a.nrhs == 1 ? 0 : (item - elv * a.nrhs) * a.ld);
+      const unsigned ee = (unsigned)elv, rr = ee / (unsigned)a.Nx, ez = rr / (unsigned)a.Ny;
       const int gx = (int)(ee - rr * a.Nx) * k + p % N;
       const int gy = (int)(rr - ez * a.Ny) * k + (p / N) % N;
       const int gz = (int)ez * k + p / NT;
       const int m = a.bcmask;
       const bool fixed = (gx == 0 && !(m & 1)) || (gx == Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
                          (gy == My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == Mz - 1 && !(m & 32));
-      W0[li * PER + vpos_of<N>(p)] = fixed ? T(0) : a.u[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
+      W0[li * PER + vpos_of<N>(p)] = fixed ? T(0) : uv[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
     }
   }
   wave_sync();
@@ -977,7 +980,8 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     const int64_t item = it0 + li;
     const int64_t el = a.nrhs == 1 ? item : item / a.nrhs;
     const int64_t gv = el * N3 + (idx - li * N3);  // offset inside one vector
-    const int64_t g = gv + (a.nrhs == 1 ? 0 : (item - el * a.nrhs) * a.ld);
+    // FE levels write element-local results, n_el n^3 values per vector
+    const int64_t g = gv + (a.nrhs == 1 ? 0 : (item - el * a.nrhs) * (FE ? a.nel * N3 : a.ld));
     if constexpr (FE || MODE == OP_APPLY) {
       a.out[g] = val;
     } else if constexpr (MODE == OP_RESID) {

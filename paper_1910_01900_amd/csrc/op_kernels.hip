@@ -118,7 +118,15 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   }
   int rc = check_launch("op_kernel");
   if (rc) return rc;
-  if (FE) return fe_node_sum(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch);
+  if (FE) {  // node sums vector by vector (element-local results n_dg values apart)
+    const size_t es = sizeof(T);
+    for (int r = 0; r < nrhs; ++r) {
+      const size_t o = (size_t)r * ld * es;
+      auto at = [&](const void* p) { return p ? (const void*)((const char*)p + o) : nullptr; };
+      TRY(fe_node_sum(L, mode, at(u), (char*)out + o, at(b), at(xold), sigma, theta, s, skip,
+                      (const char*)scratch + (size_t)r * L->n_dg * es));
+    }
+  }
   return HMG_OK;
 }
 
@@ -223,8 +231,9 @@ static int launch_any(const hmg_level* L, int mode, int nrhs, int64_t ld, const 
                       const void* xold, double sigma, double theta, int* nparts, const int* skip, void* sc,
                       hipStream_t s) {
   if (L->n_el == 0 || nrhs == 0) return HMG_OK;
-  if (nrhs > 1 && (L->space != HMG_DG || mode == OP_DOT))
-    return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: DG levels, apply/residual/Chebyshev only");
+  if (nrhs > 1 && mode == OP_DOT) return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: apply/residual/Chebyshev only");
+  if (nrhs > 1 && L->space != HMG_DG && !sc)
+    return fail(HMG_ERR_UNSUPPORTED, "several vectors at once on a continuous FE level need a results block");
   switch (L->n) {
 #define HMG_CASE(N) \
   case N: return op_launch_n##N(L, mode, u, out, b, xold, sigma, theta, nparts, nrhs, ld, skip, sc, s);
@@ -236,8 +245,8 @@ static int launch_any(const hmg_level* L, int mode, int nrhs, int64_t ld, const 
 
 int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
                             const void* b, const void* xold, double sigma, double theta, int* nparts,
-                            hipStream_t s) {
-  return launch_any(L, mode, nrhs, ld, u, out, b, xold, sigma, theta, nparts, nullptr, nullptr, s);
+                            hipStream_t s, void* fe_results) {
+  return launch_any(L, mode, nrhs, ld, u, out, b, xold, sigma, theta, nparts, nullptr, fe_results, s);
 }
 
 int launch_operator_gated(const hmg_level* L, int mode, const void* u, void* out, const void* b,
