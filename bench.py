@@ -226,6 +226,68 @@ def multi_mesh_bench(prec, nrhs=4, reps=10, cheb_degree=5):
     return out
 
 
+def multi_solve_bench(nrhs=4, count=64):
+    """The 64-mesh batch as a solve (multi_64: Cartesian unit cubes N_i^3,
+    N_i ~ U{4..24}, k_i ~ U{2..7}, nrhs right-hand sides U[-1,1] each,
+    streams 300 + 4 i + q): per mesh an FP64 PCG with an FP32 cph V-cycle to
+    1e-10, the nrhs vectors solved together against one after another."""
+    import torch
+    from paper_1910_01900_amd import hmg
+    from paper_1910_01900_amd.inputs import multi_meshes, uniform
+    spec = multi_meshes(count)
+    t0 = time.time()
+    work = []
+    for i, (N, k) in enumerate(spec):
+        H = hmg.Hierarchy(hmg.Mesh((N, N, N), k), "cph", pseq=1, h_min=4, mg_prec=hmg.F32, max_rhs=nrhs)
+        B = H.vectors(nrhs)
+        for q in range(nrhs):
+            B[q, :H.n_dofs] = torch.as_tensor(uniform(300 + 4 * i + q, H.n_dofs))
+        work.append((H, B, H.vectors(nrhs)))
+    log("multi_64 solve: %d hierarchies in %.1f s" % (len(work), time.time() - t0))
+    dofs = nrhs * sum(H.n_dofs for H, _, _ in work)
+
+    def batched():
+        its = []
+        for H, B, X in work:
+            X.zero_()
+            _, st = H.solve_batched(B, X, rtol=1e-10, maxit=200)
+            its.append(max(s["iters"] for s in st))
+        return its
+
+    def sequential():
+        for H, B, X in work:
+            for q in range(nrhs):
+                X[q].zero_()
+                H.solve(B[q, :H.n_dofs], X[q, :H.n_dofs], rtol=1e-10, maxit=200)
+
+    out = {"meshes": len(work), "nrhs": nrhs, "dofs": dofs}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        fn()
+        best = 1e30
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t1)
+            if name == "batched":
+                out["max_iterations"] = max(r)
+        out[name + "_ms"] = 1e3 * best
+        out[name + "_ns_per_dof"] = 1e9 * best / dofs
+    # every vector's final residual with the FP64 operator of its mesh
+    worst = 0.0
+    for H, B, X in work:
+        L = hmg.Level(H.mesh, prec=hmg.F64)
+        for q in range(nrhs):
+            r = L.residual(B[q, :H.n_dofs], X[q, :H.n_dofs])
+            worst = max(worst, float(torch.linalg.norm(r) / torch.linalg.norm(B[q, :H.n_dofs])))
+    out["max_final_rel_residual"] = worst
+    out["batched_vs_sequential_speedup"] = out["sequential_ms"] / out["batched_ms"]
+    del work
+    torch.cuda.empty_cache()
+    return out
+
+
 def tables_bench():
     """The paper's printed n10 tables (Tables 5-8, p = 1..7; the cited values
     in tests/golden/paper_tables_n10.json) re-run with the library's solver:
@@ -448,6 +510,8 @@ def main():
         for name, prec in (("fp64", hmg.F64), ("fp32", hmg.F32)):
             res[name] = multi_mesh_bench(prec)
             log("multi_64 %s:" % name, json.dumps(res[name]))
+        res["solve"] = multi_solve_bench()
+        log("multi_64 solve:", json.dumps(res["solve"]))
         print(json.dumps({"workload": "multi_64", **res}), flush=True)
         return
 
@@ -519,6 +583,8 @@ def main():
                    m["per_vector_ms"], m["chebyshev_degree"], m["chebyshev_batch_ms"],
                    m["chebyshev_per_vector_ms"]))
         out["multi_mesh"] = {"workload": "multi_64", **multi}
+        out["multi_mesh"]["solve"] = multi_solve_bench()
+        log("multi_64 solve:", json.dumps(out["multi_mesh"]["solve"]))
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(WORKLOADS[a.workload], res["u_host"])

@@ -108,3 +108,18 @@ def test_batched_solve_argument_errors():
     # no reservation: the vectors are solved one after another
     X, st = H1.solve_batched(B[:2])
     assert all(s["rn"] / s["r0"] <= 1e-10 for s in st)
+
+
+def test_batch_of_meshes_of_uneven_size_and_degree():
+    """A small batch in the manner of the 64-mesh workload: Cartesian and
+    curvilinear meshes of different sizes and degrees, two right-hand sides
+    each, every vector's residual recomputed with the oracle."""
+    for i, (nel, k, curved) in enumerate((((3, 3, 3), 2, False), ((4, 4, 4), 5, True), ((5, 4, 3), 3, True))):
+        hm, om = meshes(nel, k, curved)
+        H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=hmg.F32, max_rhs=2)
+        B = _block(H, [80 + 2 * i, 81 + 2 * i])
+        X, st = H.solve_batched(B, rtol=1e-10)
+        for q in range(2):
+            res = _oracle_residual(om, k, to_np(B[q, :H.n_dofs]), to_np(X[q, :H.n_dofs]))
+            print("mesh %s k=%d rhs %d: %d its, oracle residual %.2e" % (nel, k, q, st[q]["iters"], res))
+            assert res <= 1.05e-10
