@@ -44,12 +44,12 @@ struct Cfg {
   static constexpr int EW = op_elems_per_wave(N);  // elements per wavefront
   static constexpr int WAVES = kOpWaves;
   static constexpr int EB = EW * WAVES;  // elements per workgroup
-  // LDS values per element: curved uses 4 arrays (value/flux x, y, z) and,
-  // for DG, 18 n^2 neighbour face values; affine uses 3 arrays and 4 n^2
-  // face values.
+  // LDS values per element: curved DG uses 4 arrays (value/flux x, y, z)
+  // and 18 n^2 neighbour face values, curved FE 3 (its z-derivative stays in
+  // registers); affine uses 3 arrays and 4 n^2 face values.
   // Padded to PER = 9 (mod 16) values so that the lines of the elements
   // sharing a wavefront fall on different LDS banks.
-  static constexpr int PER0 = CURVED ? (FE ? 4 * N3 : (4 * N3 > 18 * NT ? 4 * N3 : 18 * NT))
+  static constexpr int PER0 = CURVED ? (FE ? 3 * N3 : (4 * N3 > 18 * NT ? 4 * N3 : 18 * NT))
                                      : (FE ? 3 * N3 : (3 * N3 > N3 + 4 * NT ? 3 * N3 : N3 + 4 * NT));
   static constexpr int PER = PER0 + ((9 - PER0 % 16) + 16) % 16;
   static constexpr int LT = TabOff(N).lane_size();
@@ -157,15 +157,17 @@ __device__ __forceinline__ int lidx(int t, int m) {
 }
 
 // Position of node (i, j, l) of an element in its LDS arrays.  For n = 8
-// the x index is XOR-swizzled with (j + l) mod 8: the 64 lanes of an x-line
-// access (one i, all j, l) then spread over the banks instead of meeting 8
-// at a time on the same bank (x-lines are 8 values apart), and y and z line
-// accesses stay at most two-way conflicted.  Other degrees keep the plain
-// x-fastest order, whose line accesses are already at most two-way.
+// the plain order puts the lanes of an x-line access (one i, all j, l) on
+// 8 banks and those of a y-line access on 8 or 16, so both indices are
+// XOR-swizzled with l, the x index also with bits of j: every line access
+// of every direction (64 lanes, two indices varying) then falls on
+// distinct banks, for 4- and 8-byte values and for 32 or 64 banks (checked
+// exhaustively on the host).  Other degrees keep the plain x-fastest order,
+// whose line accesses are at most two-way conflicted.
 template <int N>
 __device__ __forceinline__ int vpos(int i, int j, int l) {
   if constexpr (N == 8)
-    return (i ^ ((j + l) & 7)) + N * j + N * N * l;
+    return (i ^ l ^ (2 * ((j >> 2) & 1)) ^ (6 * ((j >> 1) & 1))) + N * (j ^ l) + N * N * l;
   else
     return i + N * j + N * N * l;
 }
@@ -612,10 +614,12 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   if constexpr (IN_LOOP) asm volatile("" : "+v"(lane));
   const int le = lane / NT, t = lane - le * NT;
   const int64_t nitems = a.nel * a.nrhs;
-  const int64_t it = it0 + le;
+  // one element per wavefront (n >= 6): the item, its element and all its
+  // index arithmetic are the same on every lane and stay in scalar registers
+  const int64_t it = EW == 1 ? it0 : it0 + le;
   const int64_t e = a.nrhs == 1 ? it : it / a.nrhs;
   const T* const ub = a.u + (a.nrhs == 1 ? 0 : (it - e * a.nrhs) * a.ld);  // this lane's vector
-  const bool act = (le < EW) && (it < nitems);
+  const bool act = (le < EW) && (it0 + le < nitems);
   T* const R = W0 + (le < EW ? le : 0) * PER;
   T* const LT = W0 + EW * PER;
   const ElemInfo I = elem_info(a, e);
@@ -643,7 +647,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
 #pragma unroll
       for (int j = 0; j < OWN_PER_LANE; ++j) {
         const int idx = lane + 64 * j;
-        const int li = idx / N3;
+        const int li = EW == 1 ? 0 : idx / N3;
         own[j] = idx < nload ? a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)] : T(0);
       }
     }
@@ -716,14 +720,14 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     for (int j = 0; j < OWN_PER_LANE; ++j) {
       const int idx = lane + 64 * j;
       if (idx < nload) {
-        const int li = idx / N3;
+        const int li = EW == 1 ? 0 : idx / N3;
         W0[li * PER + vpos_of<N>(idx - li * N3)] = own[j];
         if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = own[j];
       }
     }
   } else if constexpr (!FE) {
     for (int idx = lane; idx < nload; idx += 64) {
-      const int li = idx / N3;
+      const int li = EW == 1 ? 0 : idx / N3;
       const T v = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
       W0[li * PER + vpos_of<N>(idx - li * N3)] = v;
       if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = v;
@@ -735,7 +739,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     constexpr int k = N - 1;
     const int Mx = a.Nx * k + 1, My = a.Ny * k + 1, Mz = a.Nz * k + 1;
     for (int idx = lane; idx < nload; idx += 64) {
-      const int li = idx / N3, p = idx - li * N3;
+      const int li = EW == 1 ? 0 : idx / N3, p = idx - li * N3;
       const int64_t item = it0 + li;
       const int64_t elv = a.nrhs == 1 ? item : item / a.nrhs;
       const T* const uv = a.u + (a.nrhs == 1 ? 0 : (item - elv * a.nrhs) * a.ld);
@@ -802,7 +806,10 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       for (int m = 0; m < N; ++m) v[m] = cx * v1[m] + v2[m] + vacc[m];
     }
   } else {
-    T* const Dg = R + 3 * N3;
+    // FE levels have no face data: the z-derivative is formed from the
+    // lane's own z-line in the metric phase, and the z-flux then takes the
+    // place of the Gauss-point values (three arrays instead of four)
+    T* const Dg = FE ? A : R + 3 * N3;
     // ---- curved: interpolation to Gauss points, x then y then z
     if (act) {
       const cptr<T> c = fresh(a.tabs);
@@ -822,12 +829,15 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     wave_sync();
     if (act) {
       const cptr<T> c = fresh(a.tabs);
-      T x[N], uq[N], gz[N];
+      T x[N], uq[N];
+      [[maybe_unused]] T gz[N];
       read_line<N, T, 2>(A, t, x);
       eo_apply<N, T, 1>(c + O.eo(EO_S), x, uq);
-      eo_apply<N, T, -1>(c + O.eo(EO_D), uq, gz);
       write_line<N, T, 2>(A, t, uq);
-      write_line<N, T, 2>(Dg, t, gz);
+      if constexpr (!FE) {
+        eo_apply<N, T, -1>(c + O.eo(EO_D), uq, gz);
+        write_line<N, T, 2>(Dg, t, gz);
+      }
     }
     wave_sync();
     if (act) {  // collocation derivatives in x (-> B) and y (-> Cc)
@@ -878,11 +888,21 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // ---- quadrature-point operator on z-lines, z-face tests
     if (act) {
       T vq[N], fx[N], fy[N], fz[N];
+      [[maybe_unused]] T gzl[N];
+      if constexpr (FE) {  // z-derivative of the lane's own z-line
+        const cptr<T> c = fresh(a.tabs);
+        T x[N];
+        read_line<N, T, 2>(A, t, x);
+        eo_apply<N, T, -1>(c + O.eo(EO_D), x, gzl);
+      }
       const T* G = a.metric + e * 6 * N3 + t;
 #pragma unroll
       for (int m = 0; m < N; ++m) {
         const int o = sidx<N, 2>(t, m);
-        const T gx = B[o], gy = Cc[o], g3 = Dg[o];
+        const T gx = B[o], gy = Cc[o];
+        T g3;
+        if constexpr (FE) g3 = gzl[m];
+        else g3 = Dg[o];
         const T* Gm = G + NT * m;
         // stored order 00, 11, 22, 01, 02, 12
         const T g00 = Gm[0], g11 = Gm[N3], g22 = Gm[2 * N3];
@@ -975,7 +995,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   // ---- coalesced epilogue over the wavefront's elements
   double acc = 0.0;
   for (int idx = lane; idx < nload; idx += 64) {
-    const int li = idx / N3;
+    const int li = EW == 1 ? 0 : idx / N3;
     const T val = W0[li * PER + vpos_of<N>(idx - li * N3)];
     const int64_t item = it0 + li;
     const int64_t el = a.nrhs == 1 ? item : item / a.nrhs;
@@ -1043,7 +1063,7 @@ __device__ __forceinline__ void multi_tile(const MultiArgs<T>& m, cptr<MeshEntry
   using C = Cfg<N, CURVED, false>;
   const int64_t c0 = (tile - E->tile0) * m.q;
   const int64_t c1 = c0 + m.q < E->chunks ? c0 + m.q : E->chunks;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
   for (int64_t c = c0; c < c1; ++c) {
     wave_sync();  // the previous chunk's LDS reads come first
     // an opaque copy of the entry pointer per chunk: the argument loads are

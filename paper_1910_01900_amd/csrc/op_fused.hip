@@ -52,7 +52,7 @@ __device__ __forceinline__ void fused_switch(const MultiArgs<T>& m, cptr<MeshEnt
 template <typename T, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(256) op_fused_kernel(const MultiArgs<T> m) {
   __shared__ T smem[kOpWaves * kFusedWave];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
   T* const W0 = smem + wave * kFusedWave;
   const cptr<MeshEntry<T>> tab = (cptr<MeshEntry<T>>)(uintptr_t)m.table;
   const cptr<int64_t> xcd = (cptr<int64_t>)(uintptr_t)m.xcd;

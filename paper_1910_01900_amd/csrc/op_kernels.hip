@@ -17,7 +17,7 @@ op_kernel(const OpArgs<T> a) {
   }
   constexpr int WL = op_wave_lds<N, T, CURVED, FE, MODE>();
   __shared__ T smem[C::WAVES * WL];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
   T* const W0 = smem + wave * WL;  // this wavefront's LDS
   const int64_t it0 = block_chunk(a, xcd_block()) * C::EB + (int64_t)wave * C::EW;  // first item of the wave
   load_lane_tables<T, C::LT>(a.tabs, W0 + C::EW * C::PER);
@@ -45,7 +45,7 @@ op_multi_kernel(const MultiArgs<T> m) {
   using C = Cfg<N, CURVED, false>;
   constexpr int WL = op_wave_lds<N, T, CURVED, false, MODE>();
   __shared__ T smem[C::WAVES * WL];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
   T* const W0 = smem + wave * WL;
   const cptr<MeshEntry<T>> tab = (cptr<MeshEntry<T>>)(uintptr_t)m.table;
   const cptr<int64_t> xcd = (cptr<int64_t>)(uintptr_t)m.xcd;

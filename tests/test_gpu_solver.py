@@ -116,8 +116,10 @@ def test_vcycle_matches_oracle(strategy, k, nel, deformed):
     import torch
     x = to_np(H.vcycle(torch.as_tensor(b, device="cuda")))
     err = rel_inf(x, oh.vcycle(b))
+    # one V-cycle is a fixed sequence of operator applies, transfers and the
+    # coarse solve, each within 1e-12 of the oracle's (measured 2e-15 to 8e-15)
     print("vcycle %s k=%d: rel err %.3e" % (strategy, k, err))
-    assert err < 1e-10
+    assert err < 1e-12
 
 
 def test_vcycle_fp32_close_to_fp64():
