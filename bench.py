@@ -321,7 +321,7 @@ def tables_bench():
             "seconds": time.time() - t0}
 
 
-def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16, h_min=12):
+def learned_bench(samples=20480, steps=3000, batch=64, lr=1e-3, grid=16, h_min=12):
     """Learned coarse-grid correction on the curvilinear 48^3 mesh, k = 5
     (23.9M DoFs), hierarchy cph down to Q1 on h_min^3, FP32 V-cycle.
     h_min = 12 (2,197 coarse nodes): PCG with the exact (dense) coarse
@@ -337,7 +337,7 @@ def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16, h_min=12
     from paper_1910_01900_amd.inputs import uniform
     mesh = hmg.Mesh((48, 48, 48), 5, deformed=True, amp=0.05)
     t0 = time.time()
-    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=h_min, smoother_degree=5, mg_prec=hmg.F32)
+    H = hmg.Hierarchy(mesh, "cph", pseq=1, h_min=h_min, smoother_degree=5, mg_prec=hmg.F32, max_rhs=8)
     info = H.coarse_info()
     log("learned: hierarchy in %.1f s, coarse nodes %s" % (time.time() - t0, info["nodes"]))
     N = H.n_dofs
@@ -369,16 +369,30 @@ def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16, h_min=12
         res[name] = {"solve_ms": ms, "iterations": st["iters"], "vcycle_ms": vcycle_ms()}
         log("learned: %s coarse solve: %.1f ms, %d iterations" % (name, ms, st["iters"]))
     H.set_coarse(base)
-    # training pairs from the method's own V-cycles and exact coarse solves
+    # training pairs from the method's own V-cycles and exact coarse solves:
+    # the coarse right-hand sides of batched solves of 8 seeded U[-1,1]
+    # right-hand sides (drawn on the GPU, generator seed 1000 + solve)
     t0 = time.time()
     R = torch.zeros((samples, info["n"]), dtype=torch.float64, device="cuda")
     H.capture(R)
     k = 0
+    B = H.vectors(8)
     while H.captured() < samples:
-        H.solve(torch.as_tensor(uniform(1000 + k, N), device="cuda"), rtol=1e-10, maxit=200)
+        g = torch.Generator(device="cuda").manual_seed(1000 + k)
+        B[:, :N].uniform_(-1.0, 1.0, generator=g)
+        H.solve_batched(B, rtol=1e-10, maxit=200)
         k += 1
+        if k % 25 == 0:
+            log("learned: %d of %d training pairs captured (%.0f s)" % (min(H.captured(), samples), samples,
+                                                                       time.time() - t0))
     H.capture(None)
-    E = H.coarse_solve_batch(R)
+    del B
+    t_capture = time.time() - t0
+    E = torch.empty_like(R)
+    for c0 in range(0, samples, 512):  # exact coarse solves (dense inverse, or FP64 CG to 1e-12)
+        E[c0:c0 + 512] = H.coarse_solve_batch(R[c0:c0 + 512].contiguous())
+        torch.cuda.synchronize()
+        log("learned: exact coarse solves %d of %d (%.0f s)" % (min(c0 + 512, samples), samples, time.time() - t0))
     inp, tgt = H.learned_data(grid, R, E)
     torch.cuda.synchronize()
     t_data = time.time() - t0
@@ -388,6 +402,8 @@ def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16, h_min=12
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
+        if i % 500 == 0:
+            log("learned: training step %d of %d" % (i, steps))
         idx = torch.randint(0, ntrain, (batch,), device="cuda", generator=g)
         net.train_step(inp[idx].contiguous(), tgt[idx].contiguous(), lr if i < steps * 3 // 4 else lr / 4)
     torch.cuda.synchronize()
@@ -404,7 +420,8 @@ def learned_bench(samples=1024, steps=1500, batch=64, lr=1e-3, grid=16, h_min=12
     log("learned: learned coarse solve: %.1f ms, %d iterations, %d fallbacks over 4 solves"
         % (ms, st["iters"], fb))
     out.update(res)
-    out["training"] = {"pairs": samples, "data_s": t_data, "steps": steps, "batch": batch,
+    out["training"] = {"pairs": samples, "data_s": t_data, "capture_s": t_capture, "capture_solves": k,
+                       "steps": steps, "batch": batch,
                        "ms_per_step": 1e3 * t_train / steps, "validation_loss": val,
                        "inference_ms": infer}
     del H, net, R, E, inp, tgt
@@ -474,6 +491,8 @@ def main():
                     help="only re-run the paper's printed n10 tables (Tables 5-8, p <= 7) and summarise")
     ap.add_argument("--learned-only", action="store_true",
                     help="only the learned coarse-grid correction on curved_k5_48")
+    ap.add_argument("--learned-case", choices=["both", "12", "24"], default="both",
+                    help="coarse level of the learned correction: Q1 on 12^3 (dense exact solve) or 24^3 (iterative)")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
                     help="only time the operator apply (and a 1 GiB copy used to calibrate "
                          "HBM counters); for profiling")
@@ -500,8 +519,11 @@ def main():
         return
 
     if a.learned_only:
-        res = {"coarse_12": learned_bench(),
-               "coarse_24": learned_bench(samples=1024, steps=2500, batch=32, grid=32, h_min=24)}
+        res = {}
+        if a.learned_case in ("both", "12"):
+            res["coarse_12"] = learned_bench()
+        if a.learned_case in ("both", "24"):
+            res["coarse_24"] = learned_bench(samples=4096, steps=3000, batch=32, grid=32, h_min=24)
         print(json.dumps(res), flush=True)
         return
 

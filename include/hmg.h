@@ -77,12 +77,16 @@ int hmg_version(void);
  *               are moved by x_i += deform_amp * prod_j sin(deform_waves*pi*s_j),
  *               s_j = (x_j - lo_j)/(hi_j - lo_j), represented by a degree-3
  *               (Q3) mapping interpolating the deformation at the 4^3 GLL
- *               support points of each element (Sec. 5.3: cubic mapping).
+ *               support points of each element (Sec. 5.3: cubic mapping),
+ *               or exactly (mapping_degree 0).
  *  bc[6]        per box face (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi):
  *               0 Dirichlet (weak, mirror principle, Sec. 2), 1 Neumann.
  *  ip_factor    multiplies the penalty tau_e (Sec. 2; Table 8 varies it).
  *  tau_scale    optional host array of N_el per-element penalty factors
  *               (copied during create; may be NULL).
+ *  mapping_degree  3: the degree-3 mapping above (Sec. 5.3); 0: the
+ *               analytic deformation itself (exact geometry).  Other values:
+ *               HMG_ERR_UNSUPPORTED.  (Added in 0.4.0: callers must set it.)
  */
 typedef struct {
   int32_t nel[3];
@@ -94,6 +98,7 @@ typedef struct {
   uint8_t bc[6];
   double ip_factor;
   const double* tau_scale;
+  int32_t mapping_degree;
 } hmg_mesh_desc;
 
 typedef struct hmg_level hmg_level;
@@ -372,8 +377,10 @@ int hmg_hierarchy_set_flexible(hmg_hierarchy* H, int enable);
  * scale of the learned correction (1 / mean free diagonal). */
 int hmg_hierarchy_coarse_info(const hmg_hierarchy* H, int64_t* n, int* Mx, int* My, int* Mz, double* scale);
 /* Copy the coarsest right-hand side of every following V-cycle (FP64, n
- * values each, at most capacity) to buf; capacity 0 stops.  V-cycles run
- * without recorded graphs while capturing. */
+ * values each, at most capacity) to buf; capacity 0 stops.  V-cycles of
+ * several right-hand sides (hmg_vcycle_batched, hmg_pcg_solve_batched)
+ * contribute one per vector.  V-cycles run without recorded graphs while
+ * capturing. */
 int hmg_hierarchy_capture(hmg_hierarchy* H, double* buf, int capacity);
 int hmg_hierarchy_captured(const hmg_hierarchy* H, int* count);
 /* E[s] = A_c^{-1} R[s] for count coarse vectors (FP64, n values each): the

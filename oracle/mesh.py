@@ -8,7 +8,8 @@ independently of the degree of the shape functions.
 Readings (the paper is silent on these):
   * the degree-3 mapping interpolates the analytic deformation at the 4^3
     GLL(3) support points of each element; shared faces share their
-    support points, so the mapped mesh is watertight;
+    support points, so the mapped mesh is watertight (mapping_degree 0
+    evaluates the analytic deformation itself instead);
   * the deformation is x_i += a * prod_j sin(w * pi * s_j) with
     s_j = (x_j - lo_j)/(hi_j - lo_j) the normalised undeformed coordinate
     and w half-waves per direction (w = 2 is the paper's cube deformation
@@ -38,6 +39,7 @@ class BoxMesh:
     waves: int = 1                  # half-waves per direction of the deformation
     bc: tuple = (0, 0, 0, 0, 0, 0)  # per box face: 0 Dirichlet, 1 Neumann
     tau_scale: np.ndarray = field(default=None)  # optional per-element factor
+    mapping_degree: int = 3         # 3: cubic interpolant of the deformation; 0: the deformation itself
 
     @property
     def n_el(self):
@@ -87,12 +89,47 @@ class BoxMesh:
 
     def map(self, elems, p1, p2, p3):
         """Physical points x[E, P, 3] and Jacobians J[E, P, 3, 3]
-        (J[r, s] = dx_r / dxi_s) at the reference tensor grid p1 x p2 x p3."""
+        (J[r, s] = dx_r / dxi_s) at the reference tensor grid p1 x p2 x p3
+        (first index fastest)."""
+        if self.mapping_degree == 0:
+            return self._map_exact(elems, p1, p2, p3)
         X = self.support_points(elems)
         V, G = basis.tabulate3(basis.gll_nodes(3), p1, p2, p3)
         x = np.einsum("pa,ear->epr", V, X)
         J = np.stack([np.einsum("pa,ear->epr", G[s], X) for s in range(3)], axis=-1)
         return x, J
+
+
+def _exact_map(mesh, elems, p1, p2, p3):
+    """The analytic element map: the undeformed point plus the deformation,
+    J = diag(h) + grad of the deformation (chain rule, ds_d/dxi_d = 1/N_d)."""
+    elems = np.asarray(elems)
+    ex, ey, ez = mesh.coords(elems)
+    h = (np.asarray(mesh.hi) - np.asarray(mesh.lo)) / np.asarray(mesh.nel)
+    g3, g2, g1 = np.meshgrid(p3, p2, p1, indexing="ij")  # x fastest after ravel
+    ref = np.stack([g1.ravel(), g2.ravel(), g3.ravel()], axis=-1)  # (P, 3)
+    base = np.stack([ex, ey, ez], axis=-1).astype(np.float64)  # (E, 3)
+    Xhat = np.asarray(mesh.lo) + (base[:, None, :] + ref[None, :, :]) * h  # (E, P, 3)
+    E, P = Xhat.shape[0], Xhat.shape[1]
+    J = np.zeros((E, P, 3, 3))
+    for d in range(3):
+        J[..., :, d] = 0.0
+        J[..., d, d] = h[d]
+    if mesh.deform == 0.0:
+        return Xhat, J
+    s = (Xhat - np.asarray(mesh.lo)) / (np.asarray(mesh.hi) - np.asarray(mesh.lo))
+    w = mesh.waves * np.pi
+    sn, cs = np.sin(w * s), np.cos(w * s)
+    bump = mesh.deform * np.prod(sn, axis=-1)
+    x = Xhat + bump[..., None]
+    for c in range(3):
+        others = np.prod(np.delete(sn, c, axis=-1), axis=-1)
+        dbump = mesh.deform * w * cs[..., c] * others / mesh.nel[c]  # d bump / d xi_c
+        J[..., :, c] += dbump[..., None]
+    return x, J
+
+
+BoxMesh._map_exact = _exact_map
 
 
 def face_ref_points(n, d, s):

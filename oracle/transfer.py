@@ -65,7 +65,7 @@ def coarse_mesh(mesh):
         for e in range(mesh.n_el):
             ex, ey, ez = (int(c) for c in mesh.coords(e))
             ts[ex // 2 + cn[0] * (ey // 2 + cn[1] * (ez // 2))] += fine[e] / 8.0
-    return BoxMesh(cn, mesh.lo, mesh.hi, mesh.deform, mesh.waves, mesh.bc, ts)
+    return BoxMesh(cn, mesh.lo, mesh.hi, mesh.deform, mesh.waves, mesh.bc, ts, mesh.mapping_degree)
 
 
 def dg_h(mesh_f, k):

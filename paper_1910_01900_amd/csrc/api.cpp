@@ -37,6 +37,9 @@ static int to_mesh(const hmg_mesh_desc* d, Mesh& m) {
   m.curved = d->deformed != 0;
   m.amp = d->deform_amp;
   m.waves = d->deform_waves < 1 ? 1 : d->deform_waves;
+  if (d->mapping_degree != 0 && d->mapping_degree != 3)
+    return fail(HMG_ERR_UNSUPPORTED, "mapping_degree must be 3 (cubic) or 0 (exact)");
+  m.mapdeg = d->mapping_degree;
   for (int f = 0; f < 6; ++f) {
     if (d->bc[f] > 1) return fail(HMG_ERR_INVALID, "bc must be 0 (Dirichlet) or 1 (Neumann)");
     m.bc[f] = d->bc[f];
@@ -547,7 +550,7 @@ static bool same_box(const Mesh& a, const Mesh& b) {
     if (a.lo[d] != b.lo[d] || a.hi[d] != b.hi[d]) return false;
   for (int f = 0; f < 6; ++f)
     if (a.bc[f] != b.bc[f]) return false;
-  return a.curved == b.curved && a.amp == b.amp && a.waves == b.waves;
+  return a.curved == b.curved && a.amp == b.amp && a.waves == b.waves && a.mapdeg == b.mapdeg;
 }
 
 extern "C" int hmg_transfer_create(const hmg_level* fine, const hmg_level* coarse, char kind,
@@ -1423,6 +1426,10 @@ static int coarse_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
   for (int q = 0; q < nrhs; ++q) {
     const void* b = (const char*)H->bb(l) + q * o;
     void* x = (char*)H->xb(l) + q * o;
+    if (H->cap_buf && H->cap_count < H->cap_capacity) {  // training data (hmg_hierarchy_capture)
+      TRY(vec_convert(L->prec, b, HMG_F64, H->cap_buf + (size_t)H->cap_count * H->nc, H->nc, s));
+      H->cap_count++;
+    }
     switch (H->coarse_mode) {
       case HMG_COARSE_SMOOTH:
         TRY(chebyshev(L, b, x, H->ns, H->lmax_c, 0.06, 1.2, 1, s));

@@ -94,6 +94,7 @@ struct Mesh {
   bool curved;
   double amp;
   int waves;
+  int mapdeg = 3;  // 3: Q3 interpolant of the deformation; 0: the deformation itself
   uint8_t bc[6];
   double ip;
   std::vector<double> tau_scale;  // empty = all ones

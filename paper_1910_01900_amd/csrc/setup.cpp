@@ -280,11 +280,60 @@ static void map_grid(const double X[192], const std::vector<double> pts[3], std:
       }
 }
 
-void map_point(const Mesh& m, int64_t e, const double xi[3], double x[3], double J[9]) {
+// x and J of the analytic map (the undeformed point plus the deformation;
+// J = diag(h) + gradient of the deformation, ds_d/dxi_d = 1/N_d) on the
+// tensor grid pts (first index fastest).
+static void exact_grid(const Mesh& m, int64_t e, const std::vector<double> pts[3], std::vector<double>& x,
+                       std::vector<double>& J) {
+  const int64_t ec[3] = {e % m.N[0], (e / m.N[0]) % m.N[1], e / ((int64_t)m.N[0] * m.N[1])};
+  const int n0 = (int)pts[0].size(), n1 = (int)pts[1].size(), n2 = (int)pts[2].size();
+  x.assign((size_t)n0 * n1 * n2 * 3, 0.0);
+  J.assign((size_t)n0 * n1 * n2 * 9, 0.0);
+  const double w = m.waves * M_PI;
+  for (int q2 = 0; q2 < n2; ++q2)
+    for (int q1 = 0; q1 < n1; ++q1)
+      for (int q0 = 0; q0 < n0; ++q0) {
+        const int p = q0 + n0 * (q1 + n1 * q2);
+        const double xi[3] = {pts[0][q0], pts[1][q1], pts[2][q2]};
+        double pt[3], sn[3], cs[3];
+        for (int d = 0; d < 3; ++d) {
+          pt[d] = m.lo[d] + (ec[d] + xi[d]) * m.h(d);
+          const double sd = (pt[d] - m.lo[d]) / (m.hi[d] - m.lo[d]);
+          sn[d] = std::sin(w * sd);
+          cs[d] = std::cos(w * sd);
+        }
+        const double bump = m.curved ? m.amp * sn[0] * sn[1] * sn[2] : 0.0;
+        for (int r = 0; r < 3; ++r) {
+          x[p * 3 + r] = pt[r] + bump;
+          J[p * 9 + r * 3 + r] = m.h(r);
+        }
+        if (m.curved)
+          for (int c = 0; c < 3; ++c) {
+            const double db = m.amp * w * cs[c] * sn[(c + 1) % 3] * sn[(c + 2) % 3] / m.N[c];
+            for (int r = 0; r < 3; ++r) J[p * 9 + r * 3 + c] += db;
+          }
+      }
+}
+
+// The map of element e: the Q3 interpolant of the deformation (Sec. 5.3:
+// cubic mapping) or, with mapping degree 0, the deformation itself.
+struct ElemMap {
+  const Mesh& m;
+  int64_t e;
   double X[192];
-  support_points(m, e, X);
+  ElemMap(const Mesh& mesh, int64_t el) : m(mesh), e(el) {
+    if (m.mapdeg != 0) support_points(m, e, X);
+  }
+  void grid(const std::vector<double> pts[3], std::vector<double>& x, std::vector<double>& J) const {
+    if (m.mapdeg != 0) map_grid(X, pts, x, J);
+    else exact_grid(m, e, pts, x, J);
+  }
+};
+
+void map_point(const Mesh& m, int64_t e, const double xi[3], double x[3], double J[9]) {
+  const ElemMap X(m, e);
   std::vector<double> pts[3] = {{xi[0]}, {xi[1]}, {xi[2]}}, xs, Js;
-  map_grid(X, pts, xs, Js);
+  X.grid(pts, xs, Js);
   for (int r = 0; r < 3; ++r) x[r] = xs[r];
   for (int r = 0; r < 9; ++r) J[r] = Js[r];
 }
@@ -360,10 +409,9 @@ int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g, bool faces) {
   if (m.curved) g.metric.assign((size_t)ne * 6 * n3, 0.0);
   // cell metric, volume and tau
   parallel_for(ne, [&](int64_t e) {
-    double X[192];
-    support_points(m, e, X);
+    const ElemMap X(m, e);
     std::vector<double> pts[3] = {b.gz, b.gz, b.gz}, x, J;
-    map_grid(X, pts, x, J);
+    X.grid(pts, x, J);
     double vol = 0.0;
     for (int q = 0; q < n3; ++q) {
       double Bi[9];
@@ -392,7 +440,7 @@ int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g, bool faces) {
       for (int s = 0; s < 2; ++s) {
         std::vector<double> fp[3], fx, fJ, nrm, dA, Ji;
         face_pts(b, d, s, fp);
-        map_grid(X, fp, fx, fJ);
+        X.grid(fp, fx, fJ);
         face_normals(fJ, b, d, s, nrm, dA, Ji);
         double a = 0.0;
         for (int q = 0; q < nf; ++q) a += dA[q];
@@ -423,19 +471,17 @@ int build_geometry(const Mesh& m, const Basis1D& b, Geometry& g, bool faces) {
       std::vector<double> nL, dAL, JiL, nR, dAR, JiR;
       bool hasL = p > 0, hasR = p < m.N[d];
       if (hasL) {
-        double X[192];
-        support_points(m, elem(p - 1), X);
+        const ElemMap X(m, elem(p - 1));
         std::vector<double> fp[3], fx, fJ;
         face_pts(b, d, 1, fp);
-        map_grid(X, fp, fx, fJ);
+        X.grid(fp, fx, fJ);
         face_normals(fJ, b, d, 1, nL, dAL, JiL);
       }
       if (hasR) {
-        double X[192];
-        support_points(m, elem(p), X);
+        const ElemMap X(m, elem(p));
         std::vector<double> fp[3], fx, fJ;
         face_pts(b, d, 0, fp);
-        map_grid(X, fp, fx, fJ);
+        X.grid(fp, fx, fJ);
         face_normals(fJ, b, d, 0, nR, dAR, JiR);
       }
       for (int q = 0; q < nf; ++q) {
@@ -469,10 +515,9 @@ int rhs_sine_host(const Mesh& m, const Basis1D& b, const Geometry& g, double fre
     return std::sin(freq * x[0]) * std::sin(freq * x[1]) * std::sin(freq * x[2]);
   };
   parallel_for(ne, [&](int64_t e) {
-    double X[192];
-    support_points(m, e, X);
+    const ElemMap X(m, e);
     std::vector<double> pts[3] = {b.gz, b.gz, b.gz}, x, J;
-    map_grid(X, pts, x, J);
+    X.grid(pts, x, J);
     std::vector<double> F(n3);
     for (int q = 0; q < n3; ++q) {
       double Bi[9];
@@ -498,7 +543,7 @@ int rhs_sine_host(const Mesh& m, const Basis1D& b, const Geometry& g, double fre
         if (!bnd || m.bc[2 * d + s] != 0) continue;
         std::vector<double> fp[3], fx, fJ, nrm, dA, Ji;
         face_pts(b, d, s, fp);
-        map_grid(X, fp, fx, fJ);
+        X.grid(fp, fx, fJ);
         face_normals(fJ, b, d, s, nrm, dA, Ji);
         int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
         for (int q = 0; q < nf; ++q) {

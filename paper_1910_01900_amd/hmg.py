@@ -31,7 +31,7 @@ class MeshDesc(C.Structure):
     _fields_ = [("nel", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("degree", C.c_int32), ("deformed", C.c_int32), ("deform_amp", C.c_double),
                 ("deform_waves", C.c_int32), ("bc", C.c_uint8 * 6), ("ip_factor", C.c_double),
-                ("tau_scale", C.POINTER(C.c_double))]
+                ("tau_scale", C.POINTER(C.c_double)), ("mapping_degree", C.c_int32)]
 
 
 class LevelInfo(C.Structure):
@@ -170,6 +170,7 @@ class Mesh:
     bc: tuple = (0, 0, 0, 0, 0, 0)
     ip: float = 1.0
     tau_scale: np.ndarray = field(default=None)
+    mapping: int = 3  # 3: cubic interpolant of the deformation (Sec. 5.3); 0: exact
 
     def desc(self):
         d = MeshDesc()
@@ -189,6 +190,7 @@ class Mesh:
             d.tau_scale = self._ts.ctypes.data_as(C.POINTER(C.c_double))
         else:
             d.tau_scale = None
+        d.mapping_degree = int(self.mapping)
         return d
 
     @property

@@ -9,10 +9,11 @@ from paper_1910_01900_amd import hmg
 
 
 def meshes(nel, k, deformed=False, amp=0.05, waves=1, bc=(0,) * 6, ip=1.0, tau_scale=None,
-           lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+           lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), mapping=3):
     a = amp if deformed else 0.0
-    hm = hmg.Mesh(tuple(nel), k, lo, hi, deformed, a, waves, tuple(bc), ip, tau_scale)
-    om = BoxMesh(tuple(nel), tuple(lo), tuple(hi), deform=a, waves=waves, bc=tuple(bc), tau_scale=tau_scale)
+    hm = hmg.Mesh(tuple(nel), k, lo, hi, deformed, a, waves, tuple(bc), ip, tau_scale, mapping)
+    om = BoxMesh(tuple(nel), tuple(lo), tuple(hi), deform=a, waves=waves, bc=tuple(bc), tau_scale=tau_scale,
+                 mapping_degree=mapping)
     return hm, om
 
 

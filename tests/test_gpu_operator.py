@@ -179,3 +179,30 @@ def test_lambda_max_matches_oracle(space):
     ref = solver.lanczos_lmax(A, 1.0 / A.diagonal(), rng.uniform_pm1(11, A.shape[0]), 20)
     got = L.lambda_max(20, 11)
     assert abs(got - ref) <= 1e-9 * ref
+
+
+@pytest.mark.parametrize("k", [2, 4, 7])
+@pytest.mark.parametrize("space", [hmg.DG, hmg.FE])
+def test_exact_mapping_matches_oracle(k, space):
+    """mapping_degree 0 (the analytic deformation instead of its cubic
+    interpolant): operator, diagonal and right-hand side against the oracle
+    with the same exact geometry, and different from the cubic mapping's."""
+    nel = (3, 2, 2) if k < 7 else (2, 2, 2)
+    hm, om = meshes(nel, k, True, amp=0.08, waves=2, bc=(0, 1, 0, 0, 1, 0), mapping=0)
+    print("exact mapping k=%d space=%d" % (k, space), flush=True)
+    L = hmg.Level(hm, space=space)
+    u = uniform(12, L.n_dofs)
+    v = to_np(L.apply(L.vector(u)))
+    A = sipg.assemble(om, k) if space == hmg.DG else ofe.assemble(om, k)
+    ref = A @ u
+    assert rel_inf(v, ref) < 1e-12
+    assert np.all(np.abs(v - ref) <= 1e-12 * (abs(A) @ np.abs(u)) + 1e-300)
+    assert rel_inf(to_np(L.diagonal()), A.diagonal()) < 1e-12
+    h3, _ = meshes(nel, k, True, amp=0.08, waves=2, bc=(0, 1, 0, 0, 1, 0))
+    v3 = to_np(hmg.Level(h3, space=space).apply(L.vector(u)))
+    assert rel_inf(v3, ref) > 1e-6  # the cubic interpolant is a different geometry
+    if space == hmg.DG:
+        freq = 2.5
+        uu = lambda X: np.prod(np.sin(freq * X), axis=-1)
+        b = to_np(L.rhs_sine(freq))
+        assert rel_inf(b, sipg.rhs(om, k, lambda X: 3 * freq ** 2 * uu(X), g=uu)) < 1e-12

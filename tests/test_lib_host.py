@@ -267,3 +267,21 @@ def test_max_rhs_reserves_workspace_host():
     st = (hmg.SolveStats * 2)()
     assert lib.hmg_pcg_solve_batched(h, 2, None, None, ld64, 1e-10, 0.0, 10, st, None) == -6
     lib.hmg_hierarchy_destroy(h)
+
+
+def test_mapping_degree_values_host():
+    """mapping_degree: 3 (cubic, Sec. 5.3) and 0 (exact) are accepted, other
+    values refused with HMG_ERR_UNSUPPORTED; the two mappings are different
+    geometries, so a transfer between levels of different mappings is refused."""
+    lib = hmg.lib()
+    hs = {}
+    for deg, code in ((3, 0), (0, 0), (2, -2), (1, -2)):
+        m = hmg.Mesh((2, 2, 2), 2, deformed=True, amp=0.05, mapping=deg)
+        c, h = _create(m)
+        assert c == code, (deg, lib.hmg_last_error())
+        if c == 0:
+            hs[deg] = h
+    T = C.c_void_p()
+    assert lib.hmg_transfer_create(hs[3], hs[0], b"c", C.byref(T)) == -1
+    for h in hs.values():
+        lib.hmg_level_destroy(h)

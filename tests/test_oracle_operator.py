@@ -232,3 +232,63 @@ def test_fe_operator_properties():
     assert np.linalg.eigvalsh(Ad).min() > 0
     An = fe.assemble(BoxMesh((2, 2, 2), deform=0.08, waves=2, bc=(1,) * 6), k)
     assert np.abs(An @ np.ones(An.shape[0])).max() < 1e-12 * abs(An).max()
+
+
+def test_exact_mapping_geometry():
+    """mapping_degree 0 (the analytic deformation instead of its cubic
+    interpolant): the Jacobian equals central differences of the map; the
+    map equals the cubic one at the 4^3 support points and is watertight
+    with unit axis normals on the boundary; the deformed box keeps volume 1
+    (to quadrature accuracy: det J is not a polynomial); amplitude 0 gives
+    the Cartesian geometry."""
+    m0 = BoxMesh((3, 2, 2), deform=0.08, waves=2, mapping_degree=0)
+    m3 = BoxMesh((3, 2, 2), deform=0.08, waves=2)
+    el = np.arange(m0.n_el)
+    g = basis.gll_nodes(3)
+    assert np.abs(m0.map(el, g, g, g)[0] - m3.map(el, g, g, g)[0]).max() < 1e-15
+    z = np.array([0.1, 0.37, 0.8])
+    _, J = m0.map(el, z, z, z)
+    for c in range(3):
+        zp, zm = [z, z, z], [z, z, z]
+        zp[c], zm[c] = z + 1e-6, z - 1e-6
+        fd = (m0.map(el, *zp)[0] - m0.map(el, *zm)[0]) / 2e-6
+        assert np.abs(fd - J[..., :, c]).max() < 1e-8
+    _, JxW, _ = cell_geometry(BoxMesh((3, 3, 3), deform=0.05, mapping_degree=0), 9)
+    assert abs(JxW.sum() - 1.0) < 1e-9
+    mesh = BoxMesh((3, 3, 3), deform=0.05, mapping_degree=0)
+    for d in range(3):
+        left = np.array([e for e in range(mesh.n_el) if mesh.neighbor(e, d, 1) >= 0])
+        right = np.array([mesh.neighbor(e, d, 1) for e in left])
+        _, nL, dAL, xL = face_geometry(mesh, 3, left, d, 1)
+        _, nR, dAR, xR = face_geometry(mesh, 3, right, d, 0)
+        assert np.abs(xL - xR).max() < 1e-14 and np.abs(nL + nR).max() < 1e-13
+        bnd = np.array([e for e in range(mesh.n_el) if mesh.neighbor(e, d, 0) < 0])
+        _, nb, _, _ = face_geometry(mesh, 3, bnd, d, 0)
+        ref = np.zeros(3)
+        ref[d] = -1
+        assert np.abs(nb - ref).max() < 1e-13
+    a = sipg.assemble(BoxMesh((2, 2, 2)), 2)
+    b = sipg.assemble(BoxMesh((2, 2, 2), mapping_degree=0), 2)
+    assert abs(a - b).max() < 1e-12 * abs(a).max()
+
+
+def test_exact_mapping_operator_properties():
+    """The SIPG matrix on the exactly mapped curvilinear mesh: symmetric,
+    positive definite with Dirichlet faces, A 1 = 0 with all-Neumann faces
+    (P3-P5 for mapping_degree 0), and h^(k+1) convergence (P7)."""
+    mesh = BoxMesh((2, 2, 2), deform=0.08, mapping_degree=0)
+    A = sipg.assemble(mesh, 2).toarray()
+    assert np.abs(A - A.T).max() < 1e-12 * np.abs(A).max()
+    assert np.linalg.eigvalsh(0.5 * (A + A.T))[0] > 0
+    An = sipg.assemble(BoxMesh((2, 2, 2), deform=0.08, mapping_degree=0, bc=(1,) * 6), 2)
+    one = np.ones(An.shape[0])
+    assert np.abs(An @ one).max() <= 1e-12 * (abs(An) @ one).max()
+    uex = lambda X: np.prod(np.sin(2 * np.pi * X), axis=-1)
+    f = lambda X: 12 * np.pi ** 2 * uex(X)
+    errs = []
+    for N in (2, 4, 8):
+        m = BoxMesh((N, N, N), deform=0.05, mapping_degree=0)
+        u = spla.spsolve(sipg.assemble(m, 2).tocsc(), sipg.rhs(m, 2, f, g=uex))
+        errs.append(sipg.l2_error(m, 2, u, uex))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] >= 3 - 0.3, (errs, rates)
