@@ -94,6 +94,33 @@ def test_fe_apply_degrees_3_and_7(k, deformed):
     assert np.all(np.abs(v - ref) <= 1e-12 * (abs(A) @ np.abs(u)))
 
 
+@pytest.mark.parametrize("k", [4, 7])
+def test_fe_residual_and_chebyshev_at_interior_nodes(k):
+    """FE levels with element-interior nodes (degree 4: 27 per element,
+    degree 7: 216): the cell kernel finishes those nodes itself (apply,
+    residual, Chebyshev update) and the node sum the shared ones; residual
+    componentwise and Chebyshev(3) from a zero and a nonzero start against
+    the oracle's assembled FE matrix, 18 curvilinear elements (a ragged
+    tail of workgroups) with mixed boundary conditions."""
+    from oracle import solver
+    hm, om = meshes((3, 2, 3), k, True, bc=(0, 1, 0, 0, 1, 0))
+    print("FE interior nodes k=%d" % k, flush=True)
+    L = hmg.Level(hm, space=hmg.FE)
+    A = ofe.assemble(om, k).tocsr()
+    u, b = uniform(13, L.n_dofs), uniform(14, L.n_dofs)
+    r = to_np(L.residual(L.vector(b), L.vector(u)))
+    bound = 1e-12 * (abs(A) @ np.abs(u)) + 2.0 ** -53 * np.abs(b)
+    assert np.all(np.abs(r - (b - A @ u)) <= bound)
+    dinv = 1.0 / A.diagonal()
+    for x_is_zero in (False, True):
+        x0 = np.zeros(L.n_dofs) if x_is_zero else u
+        x = L.vector(x0)
+        L.chebyshev(L.vector(b), x, 3, 1.7, x_is_zero=x_is_zero)
+        err = rel_inf(to_np(x), solver.chebyshev(A, dinv, b, x0, 3, 1.7))
+        print("Chebyshev(3) x_is_zero=%s: rel err %.2e" % (x_is_zero, err))
+        assert err < 1e-12
+
+
 @pytest.mark.parametrize("space", [hmg.DG, hmg.FE])
 @pytest.mark.parametrize("deformed", [False, True])
 def test_diagonal_matches_oracle(space, deformed):
