@@ -263,7 +263,7 @@ static int level_init(const Mesh& m, int space, int prec, hmg_level** out) {
   L->off_dinv = take(L->vec_bytes());
   L->off_tmp = take((size_t)kTmpVecs * L->vec_bytes());
   L->off_scratch = take(space == HMG_FE ? (size_t)L->n_dg * es : 0);
-  L->off_part = take((size_t)std::max<int64_t>(kPartials, L->n_el + 64) * 8);
+  L->off_part = take((size_t)op_partials_capacity(L->mesh.N[0], L->mesh.N[1], L->mesh.N[2]) * 8);
   L->off_scal = take(16 * 8);
   L->off_tabs = take((size_t)TabOff(L->n).size() * es);
   L->ws_bytes = off;

@@ -221,11 +221,29 @@ inline OpArgs<T> make_args(const hmg_level* L) {
   return a;
 }
 
-// Workgroup geometry of the DG operator kernels: 4 wavefronts of
-// 64 / n^2 elements (at least one).
+// Workgroup geometry of the operator kernels: 4 wavefronts whose lanes
+// form groups of op_group_lanes(n) lanes (one wavefront, or for
+// HMG_WIDE_GROUPS degrees the whole workgroup); a group owns
+// lanes / n^2 elements (at least one), n^2 lanes each.  Whole-workgroup
+// groups keep the lanes busy where n^2 leaves much of a wavefront over
+// (n = 6: 36 of 64 lanes, 7 elements on 252 of 256), at the price of
+// workgroup barriers between phases.
+#ifndef HMG_WIDE_GROUPS
+#define HMG_WIDE_GROUPS 0x40  // bit n: n = 6
+#endif
 constexpr int kOpWaves = 4;
-constexpr int op_elems_per_wave(int n) { return 64 / (n * n) >= 1 ? 64 / (n * n) : 1; }
-constexpr int op_elems_per_block(int n) { return kOpWaves * op_elems_per_wave(n); }
+constexpr int op_group_lanes(int n) { return ((HMG_WIDE_GROUPS >> n) & 1) ? 64 * kOpWaves : 64; }
+constexpr int op_elems_per_group(int n) {
+  return op_group_lanes(n) / (n * n) >= 1 ? op_group_lanes(n) / (n * n) : 1;
+}
+constexpr int op_elems_per_block(int n) { return 64 * kOpWaves / op_group_lanes(n) * op_elems_per_group(n); }
+// Wavefront partial sums an OP_DOT launch on a mesh of nx x ny x nz
+// elements can write: ceil(nx / EB) workgroups per x-row (EB >= 4), four
+// wavefronts each, at most n_el + 4 ny nz.
+inline int64_t op_partials_capacity(int nx, int ny, int nz) {
+  const int64_t c = (int64_t)nx * ny * nz + (int64_t)kOpWaves * ny * nz + 64;
+  return c > kPartials ? c : kPartials;
+}
 
 // One mesh of a multi-mesh launch (device table entry).  The work of a
 // launch is a list of tiles; a tile is q consecutive workgroup chunks

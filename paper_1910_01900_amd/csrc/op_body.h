@@ -1,14 +1,19 @@
 // Device side of the matrix-free SIPG / continuous-FE Laplace operator for
 // gfx950 (Sec. 4, eq:MatrixFreeAbstractNotation): workgroup geometry,
-// helpers and the per-wavefront operator body shared by the single-mesh and
+// helpers and the per-group operator body shared by the single-mesh and
 // the multi-mesh kernels.
 //
-// Work decomposition: every wavefront owns EW = 64 / n^2 elements outright
-// (n^2 lanes per element) and a private LDS region; all exchanges between
-// lanes stay inside the wavefront, so phases are separated by wavefront
-// fences instead of workgroup barriers and the four wavefronts of a
-// workgroup progress independently (the latency of one hides behind the
-// others).  Lane t of an element owns one line of n points along the
+// Work decomposition: lanes form groups (a wavefront, or at n = 6 the
+// whole 256-lane workgroup); a group owns EW = lanes / n^2 elements outright
+// (n^2 lanes per element) and a private LDS region, and all exchanges
+// between lanes stay inside the group.  Wavefront groups separate their
+// phases by wavefront fences instead of workgroup barriers, so the four
+// wavefronts of a workgroup progress independently (the latency of one
+// hides behind the others).  At n = 6 a wavefront would hold one element
+// on 36 of its 64 lanes; the workgroup group holds 7 on 252 of 256 lanes,
+// with workgroup barriers between phases (FP64 apply 13% faster, FP32 11%;
+// at n = 5 and 7, 78% and 77% of the lanes work either way and the
+// workgroup group measured no faster).  Lane t of an element owns one line of n points along the
 // direction of the current phase (x-lines: t = j + n*l, y-lines:
 // t = i + n*l, z-lines: t = i + n*j), so every 1-D contraction is a
 // register-only loop; LDS only changes the direction.
@@ -41,9 +46,12 @@ template <int N, bool CURVED, bool FE>
 struct Cfg {
   static constexpr int NT = N * N;
   static constexpr int N3 = N * N * N;
-  static constexpr int EW = op_elems_per_wave(N);  // elements per wavefront
   static constexpr int WAVES = kOpWaves;
-  static constexpr int EB = EW * WAVES;  // elements per workgroup
+  static constexpr int GL = op_group_lanes(N);        // lanes of a group (64 or the workgroup)
+  static constexpr int GROUPS = 64 * WAVES / GL;      // groups per workgroup
+  static constexpr int EW = op_elems_per_group(N);    // elements per group
+  static constexpr int EB = op_elems_per_block(N);    // elements per workgroup
+  static_assert(EB == EW * GROUPS, "workgroup geometry");
   // LDS values per element: curved DG uses 4 arrays (value/flux x, y, z)
   // and 18 n^2 neighbour face values, curved FE 3 (its z-derivative stays in
   // registers); affine uses 3 arrays and 4 n^2 face values.
@@ -76,16 +84,16 @@ template <int N, typename T, bool CURVED, bool FE, int MODE>
 constexpr bool keeps_input() {
   if (FE || (MODE != OP_CHEB && MODE != OP_DOT)) return false;
   using C = Cfg<N, CURVED, FE>;
-  constexpr int base = C::WAVES * (C::EW * C::PER + C::LT) * (int)sizeof(T);
-  constexpr int extra = C::WAVES * C::EW * C::N3 * (int)sizeof(T);
+  constexpr int base = C::GROUPS * (C::EW * C::PER + C::LT) * (int)sizeof(T);
+  constexpr int extra = C::GROUPS * C::EW * C::N3 * (int)sizeof(T);
   constexpr int vgpr_blocks = (CURVED && sizeof(T) == 8) ? C::WPE : 5;
   constexpr int b0 = 163840 / base, b1 = 163840 / (base + extra);
   return (b1 < vgpr_blocks ? b1 : vgpr_blocks) == (b0 < vgpr_blocks ? b0 : vgpr_blocks);
 }
-// LDS values of one wavefront: EW elements of PER, the lane tables, and the
+// LDS values of one group: EW elements of PER, the lane tables, and the
 // kept input values.
 template <int N, typename T, bool CURVED, bool FE, int MODE>
-constexpr int op_wave_lds() {
+constexpr int op_group_lds() {
   using C = Cfg<N, CURVED, FE>;
   return C::EW * C::PER + C::LT + (keeps_input<N, T, CURVED, FE, MODE>() ? C::EW * C::N3 : 0);
 }
@@ -113,15 +121,22 @@ __device__ __forceinline__ int xcd_block() {
   return x * per + min(x, rem) + y;
 }
 
-// Chunk of EB consecutive elements processed by logical workgroup b.  With
-// whole chunks per x-row, rows are visited in y-tiles of tile_y rows, z
-// before y inside a tile: the x, y and z neighbours of an element are then
+// Work items of logical workgroup b: up to EB consecutive items from the
+// returned first one; *count is how many (fewer at the end of the launch,
+// and at the end of an x-row).  With a.rowchunks = ceil(Nx / EB) chunks per
+// x-row (one vector), rows are visited in y-tiles of tile_y rows, z before
+// y inside a tile: the x, y and z neighbours of an element are then
 // processed close in time (a few dozen workgroups apart) and the shared
-// face geometry and neighbour values are still in L2.
+// face geometry and neighbour values are still in L2.  A row's last chunk
+// holds the Nx mod EB elements left over (if any).
 template <typename T>
-__device__ __forceinline__ int64_t block_chunk(const OpArgs<T>& a, int b) {
+__device__ __forceinline__ int64_t block_chunk(const OpArgs<T>& a, int b, int eb, int* count) {
   const int R = a.rowchunks;
-  if (R == 0) return b;
+  if (R == 0) {
+    const int64_t first = (int64_t)b * eb, left = a.nel * a.nrhs - first;
+    *count = left < eb ? (int)left : eb;
+    return first;
+  }
   // 32-bit: chunk counts are below 2^31 (checked at launch)
   const unsigned TY = a.tile_y, full = (unsigned)R * a.Nz * TY;
   const unsigned ty = (unsigned)b / full;
@@ -129,7 +144,9 @@ __device__ __forceinline__ int64_t block_chunk(const OpArgs<T>& a, int b) {
   const unsigned bp = (unsigned)b - ty * full;
   const unsigned r = bp / R, cx = bp - r * R;
   const unsigned z = r / th, yi = r - z * th;
-  return cx + (int64_t)R * ((ty * TY + yi) + (int64_t)a.Ny * z);
+  const int x0 = (int)cx * eb;
+  *count = a.Nx - x0 < eb ? a.Nx - x0 : eb;
+  return x0 + (int64_t)a.Nx * ((ty * TY + yi) + (int64_t)a.Ny * z);
 }
 
 // Pin a value in registers at this point: computations that feed stores
@@ -145,6 +162,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// Order LDS traffic between the lanes of a group of GL lanes (a wavefront,
+// or the whole workgroup).
+template <int GL>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (GL == 64) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
 }
 
 // Index of point m on the line of lane t along direction d (x-fastest n^3).
@@ -513,7 +540,7 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
       F[(2 * s + 1) * NT + t] = T(-0.5) * cdn * Pj;
     }
   }
-  wave_sync();
+  group_sync<op_group_lanes(N)>();
   T Z[4] = {0, 0, 0, 0};
   if (act) {
 #pragma unroll
@@ -523,11 +550,11 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) pin(Z[cc]);
   }
-  wave_sync();
+  group_sync<op_group_lanes(N)>();
   if (act)
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) F[cc * NT + t] = Z[cc];
-  wave_sync();
+  group_sync<op_group_lanes(N)>();
   T W[4] = {0, 0, 0, 0};
   if (act) {
     const T hab = a.h[da] * a.h[db];
@@ -539,11 +566,11 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
       pin(W[cc]);
     }
   }
-  wave_sync();
+  group_sync<op_group_lanes(N)>();
   if (act)
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) F[cc * NT + t] = W[cc];
-  wave_sync();
+  group_sync<op_group_lanes(N)>();
   // F[(2s) n^2 + node]: plane term at the end node; F[(2s+1) n^2 + node]:
   // weight of l_i'(s) along the normal line.  Add into this lane's x-line.
   if (act) {
@@ -566,7 +593,7 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
       }
     }
   }
-  wave_sync();
+  group_sync<op_group_lanes(N)>();
 }
 
 // Offset of the first value of work item `item` (element x vector) in the
@@ -578,62 +605,71 @@ __device__ __forceinline__ int64_t item_offset(const OpArgs<T>& a, int64_t item)
   const int64_t el = item / a.nrhs;
   return (item - el * a.nrhs) * a.ld + el * N3;
 }
-// ------------------------------------------------------------------ operator
-// Lane tables (the per-lane part of op_tables()) into a wavefront's LDS:
-// loads first, one round trip.
-template <typename T, int LTN>
-__device__ __forceinline__ void load_lane_tables(const T* tabs, T* LT) {
-  const int lane = threadIdx.x & 63;
-  constexpr int KL = (LTN + 63) / 64;
-  T lt[KL];
-#pragma unroll
-  for (int i = 0; i < KL; ++i) lt[i] = tabs[lane + 64 * i < LTN ? lane + 64 * i : 0];
-#pragma unroll
-  for (int i = 0; i < KL; ++i)
-    if (lane + 64 * i < LTN) LT[lane + 64 * i] = lt[i];
+// Work items of a launch in linear order from it0: how many are left
+// (the group takes at most its EW of them).
+template <typename T>
+__device__ __forceinline__ int group_count(const OpArgs<T>& a, int64_t it0) {
+  const int64_t left = a.nel * a.nrhs - it0;
+  return left <= 0 ? 0 : (left > 1024 ? 1024 : (int)left);
 }
 
-// One wavefront's share of a launch: the EW work items starting at it0.
-// Work items are (element, vector) pairs, vector fastest, so with several
-// vectors the slots of a wavefront share one element's geometry (the same
-// cache lines); items past the end are idle lanes.  W0 is the wavefront's
-// LDS region: EW * PER values, then the lane tables (filled by the caller).
-// Phases are separated by wave_sync().  Each phase is one `if (act)` block
-// whose global loads are issued together at its start (clamped addresses,
-// no per-face branches), so a phase costs one memory round trip.
-// Returns the wavefront's sum of u.(A u) in OP_DOT mode, 0 otherwise.
-// IN_LOOP (kernels that loop over tiles): the lane index is made opaque so
-// that lane arithmetic is redone per call instead of being hoisted out of
-// the loop, where it would stay live throughout.
+// ------------------------------------------------------------------ operator
+// Lane tables (the per-lane part of op_tables()) into a group's LDS (GL
+// lanes): loads first, one round trip.
+template <typename T, int LTN, int GL>
+__device__ __forceinline__ void load_lane_tables(const T* tabs, T* LT) {
+  const int lane = threadIdx.x & (GL - 1);
+  constexpr int KL = (LTN + GL - 1) / GL;
+  T lt[KL];
+#pragma unroll
+  for (int i = 0; i < KL; ++i) lt[i] = tabs[lane + GL * i < LTN ? lane + GL * i : 0];
+#pragma unroll
+  for (int i = 0; i < KL; ++i)
+    if (lane + GL * i < LTN) LT[lane + GL * i] = lt[i];
+}
+
+// One group's share of a launch: the work items it0 .. it0 + nv - 1 (at
+// most EW of them; nv <= 0: none).  Work items are (element, vector) pairs,
+// vector fastest, so with several vectors the slots of a group share one
+// element's geometry (the same cache lines); slots past nv are idle lanes.
+// W0 is the group's LDS region: EW * PER values, then the lane tables
+// (filled by the caller).  Phases are separated by group_sync().  Each
+// phase is one `if (act)` block whose global loads are issued together at
+// its start (clamped addresses, no per-face branches), so a phase costs one
+// memory round trip.  Returns the wavefront's sum of u.(A u) in OP_DOT
+// mode, 0 otherwise.  IN_LOOP (kernels that loop over tiles): the lane
+// index is made opaque so that lane arithmetic is redone per call instead
+// of being hoisted out of the loop, where it would stay live throughout.
 template <int N, typename T, bool CURVED, bool FE, int MODE, bool IN_LOOP = false>
-__device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0, T* const W0) {
+__device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0, const int nv, T* const W0) {
   using C = Cfg<N, CURVED, FE>;
-  constexpr int NT = C::NT, N3 = C::N3, EW = C::EW, PER = C::PER;
+  constexpr int NT = C::NT, N3 = C::N3, EW = C::EW, PER = C::PER, GL = C::GL;
   constexpr TabOff O(N);
-  int lane = threadIdx.x & 63;
+  int lane = threadIdx.x & (GL - 1);
   if constexpr (IN_LOOP) asm volatile("" : "+v"(lane));
   const int le = lane / NT, t = lane - le * NT;
-  const int64_t nitems = a.nel * a.nrhs;
-  // one element per wavefront (n >= 6): the item, its element and all its
+  // one element per wavefront (n = 8): the item, its element and all its
   // index arithmetic are the same on every lane and stay in scalar registers
   const int64_t it = EW == 1 ? it0 : it0 + le;
   const int64_t e = a.nrhs == 1 ? it : it / a.nrhs;
   const T* const ub = a.u + (a.nrhs == 1 ? 0 : (it - e * a.nrhs) * a.ld);  // this lane's vector
-  const bool act = (le < EW) && (it0 + le < nitems);
+  const bool act = (le < EW) && (le < nv);
   T* const R = W0 + (le < EW ? le : 0) * PER;
   T* const LT = W0 + EW * PER;
   const ElemInfo I = elem_info(a, e);
-  const int64_t left = nitems - it0;
-  const int nload = (int)(left <= 0 ? 0 : (left < EW ? left : EW)) * N3;
+  const int nload = (nv <= 0 ? 0 : (nv < EW ? nv : EW)) * N3;
   const int ta = t % N, tbb = t / N;
 
   // ---- neighbour traces (curved DG), before the own data occupies LDS.
-  // For n >= 7 and FP64 n = 5, 6 the own values are loaded into registers
+  // For n >= 7 and FP64 n = 5 the own values are loaded into registers
   // with the neighbour data (one round trip for both) and go to LDS once the
-  // neighbour phase is done (FP64 n = 6: 8% faster despite three spilled
-  // registers); elsewhere the registers would cost a wavefront per SIMD.
-  constexpr int OWN_PER_LANE = (EW * N3 + 63) / 64;
-  constexpr bool early_own = CURVED && !FE && (N >= 7 || ((N == 5 || N == 6) && sizeof(T) == 8));
+  // neighbour phase is done; elsewhere the registers would cost a wavefront
+  // per SIMD.  FP64 n = 6 with workgroup groups holds 6 values per lane
+  // (7 elements on 256 lanes), which spilled 11 registers and was 2-3%
+  // slower than loading them after the neighbour phase.
+  constexpr int OWN_PER_LANE = (EW * N3 + GL - 1) / GL;
+  constexpr bool early_own =
+      CURVED && !FE && (N >= 7 || (N == 5 && sizeof(T) == 8) || (N == 6 && sizeof(T) == 8 && GL == 64));
   [[maybe_unused]] T own[OWN_PER_LANE];
   T un[6], dnn[6];
   if constexpr (CURVED && !FE) {
@@ -646,7 +682,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     if constexpr (early_own) {
 #pragma unroll
       for (int j = 0; j < OWN_PER_LANE; ++j) {
-        const int idx = lane + 64 * j;
+        const int idx = lane + GL * j;
         const int li = EW == 1 ? 0 : idx / N3;
         own[j] = idx < nload ? a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)] : T(0);
       }
@@ -670,7 +706,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         }
       }
     }
-    wave_sync();
+    group_sync<GL>();
     T X[18];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -685,11 +721,11 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
           X[3 * f + 2] += sv * qq;
         }
     }
-    wave_sync();
+    group_sync<GL>();
     if (act)
 #pragma unroll
       for (int cc = 0; cc < 18; ++cc) R[cc * NT + t] = X[cc];
-    wave_sync();
+    group_sync<GL>();
 #pragma unroll
     for (int f = 0; f < 6; ++f) un[f] = dnn[f] = 0;
     if (act) {
@@ -698,7 +734,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       nb_finish<N, T, 1>(R, LT, t, I, cn, un, dnn);
       nb_finish<N, T, 2>(R, LT, t, I, cn, un, dnn);
     }
-    wave_sync();
+    group_sync<GL>();
   }
 
 
@@ -718,7 +754,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   if constexpr (early_own) {
 #pragma unroll
     for (int j = 0; j < OWN_PER_LANE; ++j) {
-      const int idx = lane + 64 * j;
+      const int idx = lane + GL * j;
       if (idx < nload) {
         const int li = EW == 1 ? 0 : idx / N3;
         W0[li * PER + vpos_of<N>(idx - li * N3)] = own[j];
@@ -726,7 +762,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       }
     }
   } else if constexpr (!FE) {
-    for (int idx = lane; idx < nload; idx += 64) {
+    for (int idx = lane; idx < nload; idx += GL) {
       const int li = EW == 1 ? 0 : idx / N3;
       const T v = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
       W0[li * PER + vpos_of<N>(idx - li * N3)] = v;
@@ -738,7 +774,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // indices fit in 32 bits (the level's node count is checked on the host)
     constexpr int k = N - 1;
     const int Mx = a.Nx * k + 1, My = a.Ny * k + 1, Mz = a.Nz * k + 1;
-    for (int idx = lane; idx < nload; idx += 64) {
+    for (int idx = lane; idx < nload; idx += GL) {
       const int li = EW == 1 ? 0 : idx / N3, p = idx - li * N3;
       const int64_t item = it0 + li;
       const int64_t elv = a.nrhs == 1 ? item : item / a.nrhs;
@@ -753,7 +789,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       W0[li * PER + vpos_of<N>(p)] = fixed ? T(0) : uv[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
     }
   }
-  wave_sync();
+  group_sync<GL>();
 
   T* const A = R;
   T* const B = R + N3;
@@ -780,7 +816,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       write_line<N, T, 2>(B, t, p);
       write_line<N, T, 2>(Cc, t, q);
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {  // y: r = M p, s = cy K p + cz M q
       const cptr<T> c = fresh(a.tabs);
       T p[N], q[N], r[N], s1[N], s2[N];
@@ -794,7 +830,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       write_line<N, T, 1>(B, t, r);
       write_line<N, T, 1>(Cc, t, s1);
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {  // x: v = cx K r + M s
       const cptr<T> c = fresh(a.tabs);
       T r[N], s[N], v1[N], v2[N];
@@ -818,7 +854,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       eo_apply<N, T, 1>(c + O.eo(EO_S), x, y);
       write_line<N, T, 0>(A, t, y);
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {
       const cptr<T> c = fresh(a.tabs);
       T x[N], y[N];
@@ -826,7 +862,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       eo_apply<N, T, 1>(c + O.eo(EO_S), x, y);
       write_line<N, T, 1>(A, t, y);
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {
       const cptr<T> c = fresh(a.tabs);
       T x[N], uq[N];
@@ -839,7 +875,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         write_line<N, T, 2>(Dg, t, gz);
       }
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {  // collocation derivatives in x (-> B) and y (-> Cc)
       const cptr<T> c = fresh(a.tabs);
       T x[N], y[N];
@@ -850,7 +886,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       eo_apply<N, T, -1>(c + O.eo(EO_D), x, y);
       write_line<N, T, 1>(Cc, t, y);
     }
-    wave_sync();
+    group_sync<GL>();
     // ---- face fluxes (DG): own traces by extrapolation
     // x- and y-face tests: the products of the own-side metric with gt are
     // formed in the flux phase (the metric is in registers there), so the
@@ -874,16 +910,16 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         te = a.tau[I.e];
       }
       if (act) own_flux<N, T, 0, true>(a, F0, te, R, t, I, un, dnn, vt, gt, gc0);
-      wave_sync();
+      group_sync<GL>();
       if constexpr (pf_faces)
         F2 = load_own_face<N, T, 2>(a, I, t);
       else
         F1 = load_own_face<N, T, 1>(a, I, t);
       if (act) own_flux<N, T, 1, true>(a, F1, te, R, t, I, un, dnn, vt, gt, gc1);
-      wave_sync();
+      group_sync<GL>();
       if constexpr (!pf_faces) F2 = load_own_face<N, T, 2>(a, I, t);
       if (act) own_flux<N, T, 2, pre_gc_z>(a, F2, te, R, t, I, un, dnn, vt, gt, gc2);
-      wave_sync();
+      group_sync<GL>();
     }
     // ---- quadrature-point operator on z-lines, z-face tests
     if (act) {
@@ -923,7 +959,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       write_line<N, T, 2>(Cc, t, fy);
       write_line<N, T, 2>(Dg, t, fz);
     }
-    wave_sync();
+    group_sync<GL>();
     if constexpr (!FE) {  // x-face tests along x-lines
       if (act) {
         T vq[N], fx[N], fy[N], fz[N];
@@ -937,7 +973,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
         write_line<N, T, 0>(Cc, t, fy);
         write_line<N, T, 0>(Dg, t, fz);
       }
-      wave_sync();
+      group_sync<GL>();
     }
     if (act) {  // y-face tests, then integration in y
       T fx[N], fy[N], fz[N], ay[N], by[N], cy[N], w2[N];
@@ -961,7 +997,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       write_line<N, T, 1>(B, t, by);
       write_line<N, T, 1>(Cc, t, cy);
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {  // integration in z
       const cptr<T> c = fresh(a.tabs);
       T ay[N], by[N], cy[N], az[N], bz[N], w2[N];
@@ -976,7 +1012,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       write_line<N, T, 2>(A, t, az);
       write_line<N, T, 2>(B, t, bz);
     }
-    wave_sync();
+    group_sync<GL>();
     if (act) {  // integration in x
       const cptr<T> c = fresh(a.tabs);
       T az[N], bz[N], w2[N];
@@ -988,13 +1024,13 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       for (int m = 0; m < N; ++m) v[m] += w2[m];
     }
   }
-  wave_sync();
+  group_sync<GL>();
   if (act) write_line<N, T, 0>(A, t, v);
-  wave_sync();
+  group_sync<GL>();
 
   // ---- coalesced epilogue over the wavefront's elements
   double acc = 0.0;
-  for (int idx = lane; idx < nload; idx += 64) {
+  for (int idx = lane; idx < nload; idx += GL) {
     const int li = EW == 1 ? 0 : idx / N3;
     const T val = W0[li * PER + vpos_of<N>(idx - li * N3)];
     const int64_t item = it0 + li;
@@ -1063,15 +1099,16 @@ __device__ __forceinline__ void multi_tile(const MultiArgs<T>& m, cptr<MeshEntry
   using C = Cfg<N, CURVED, false>;
   const int64_t c0 = (tile - E->tile0) * m.q;
   const int64_t c1 = c0 + m.q < E->chunks ? c0 + m.q : E->chunks;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / C::GL);  // group-uniform (scalar)
   for (int64_t c = c0; c < c1; ++c) {
-    wave_sync();  // the previous chunk's LDS reads come first
+    group_sync<C::GL>();  // the previous chunk's LDS reads come first
     // an opaque copy of the entry pointer per chunk: the argument loads are
     // not hoisted out of the loop (where they would stay live throughout)
     cptr<MeshEntry<T>> Ec = E;
     asm volatile("" : "+s"(Ec)::"memory");
     const OpArgs<T>& a = *(const OpArgs<T>*)&Ec->a;
-    op_items<N, T, CURVED, false, MODE, true>(a, c * C::EB + (int64_t)wave * C::EW, W0);
+    const int64_t it0 = c * C::EB + (int64_t)grp * C::EW;
+    op_items<N, T, CURVED, false, MODE, true>(a, it0, group_count(a, it0), W0);
   }
 }
 

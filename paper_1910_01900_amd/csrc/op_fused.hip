@@ -1,35 +1,41 @@
 // Multi-mesh operator launch over Cartesian DG meshes of any degree in ONE
 // kernel: each tile dispatches on its mesh's degree to the operator body of
-// that degree (op_body.h).  The LDS region of a wavefront is sized for the
-// largest degree, so residency is that of degree 7 for every tile; the
+// that degree (op_body.h).  The workgroup's LDS is sized for the largest
+// degree, so residency is that of the largest degree for every tile; the
 // batch scheduler weighs this against one launch per degree by timing both.
 #include "op_body.h"
 
 namespace hmg {
 
 template <int N>
-constexpr int fused_wave_lds() {  // the largest of the modes and precisions (in values)
-  return op_wave_lds<N, float, false, false, OP_CHEB>() > op_wave_lds<N, double, false, false, OP_CHEB>()
-             ? op_wave_lds<N, float, false, false, OP_CHEB>()
-             : op_wave_lds<N, double, false, false, OP_CHEB>();
+constexpr int fused_block_lds() {  // a workgroup's LDS at degree N, the larger precision (in values)
+  using C = Cfg<N, false, false>;
+  return C::GROUPS * (op_group_lds<N, float, false, false, OP_CHEB>() > op_group_lds<N, double, false, false, OP_CHEB>()
+                          ? op_group_lds<N, float, false, false, OP_CHEB>()
+                          : op_group_lds<N, double, false, false, OP_CHEB>());
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int kFusedWave =
-    cmax(cmax(cmax(fused_wave_lds<2>(), fused_wave_lds<3>()), cmax(fused_wave_lds<4>(), fused_wave_lds<5>())),
-         cmax(cmax(fused_wave_lds<6>(), fused_wave_lds<7>()), fused_wave_lds<8>()));
+constexpr int kFusedBlock =
+    cmax(cmax(cmax(fused_block_lds<2>(), fused_block_lds<3>()), cmax(fused_block_lds<4>(), fused_block_lds<5>())),
+         cmax(cmax(fused_block_lds<6>(), fused_block_lds<7>()), fused_block_lds<8>()));
 
 // One tile of mesh E (degree N): the lane tables of that degree into the
-// wavefront's LDS, then its chunks.
+// group's LDS, then its chunks.  The groups of consecutive tiles of
+// different degrees overlap in LDS: a workgroup barrier first.
 template <int N, typename T, int MODE, bool PERSIST>
-__device__ __forceinline__ void fused_tile(const MultiArgs<T>& m, cptr<MeshEntry<T>> E, int64_t tile, T* W0) {
+__device__ __forceinline__ void fused_tile(const MultiArgs<T>& m, cptr<MeshEntry<T>> E, int64_t tile, T* smem) {
   using C = Cfg<N, false, false>;
-  wave_sync();  // the previous tile's LDS reads come first
-  load_lane_tables<T, C::LT>(E->a.tabs, W0 + C::EW * C::PER);
+  constexpr int WL = op_group_lds<N, T, false, false, MODE>();
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / C::GL);  // group-uniform (scalar)
+  T* const W0 = smem + grp * WL;
+  __syncthreads();  // the previous tile's LDS reads come first
+  load_lane_tables<T, C::LT, C::GL>(E->a.tabs, W0 + C::EW * C::PER);
   if constexpr (PERSIST) {
     multi_tile<N, T, false, MODE>(m, E, tile, W0);
   } else {
     const OpArgs<T>& a = *(const OpArgs<T>*)&E->a;
-    op_items<N, T, false, false, MODE>(a, (tile - E->tile0) * C::EB + (int64_t)(threadIdx.x >> 6) * C::EW, W0);
+    const int64_t it0 = (tile - E->tile0) * C::EB + (int64_t)grp * C::EW;
+    op_items<N, T, false, false, MODE>(a, it0, group_count(a, it0), W0);
   }
 }
 
@@ -51,9 +57,8 @@ __device__ __forceinline__ void fused_switch(const MultiArgs<T>& m, cptr<MeshEnt
 // otherwise one workgroup per tile of one chunk.
 template <typename T, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(256) op_fused_kernel(const MultiArgs<T> m) {
-  __shared__ T smem[kOpWaves * kFusedWave];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
-  T* const W0 = smem + wave * kFusedWave;
+  __shared__ T smem[kFusedBlock];
+  T* const W0 = smem;  // each tile places its groups in it
   const cptr<MeshEntry<T>> tab = (cptr<MeshEntry<T>>)(uintptr_t)m.table;
   const cptr<int64_t> xcd = (cptr<int64_t>)(uintptr_t)m.xcd;
   const int x = blockIdx.x & 7;

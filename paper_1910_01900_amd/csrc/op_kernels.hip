@@ -15,15 +15,17 @@ op_kernel(const OpArgs<T> a) {
   if constexpr (FE) {
     if (a.skip && *a.skip) return;  // gated apply (iterative coarse solve)
   }
-  constexpr int WL = op_wave_lds<N, T, CURVED, FE, MODE>();
-  __shared__ T smem[C::WAVES * WL];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
-  T* const W0 = smem + wave * WL;  // this wavefront's LDS
-  const int64_t it0 = block_chunk(a, xcd_block()) * C::EB + (int64_t)wave * C::EW;  // first item of the wave
-  load_lane_tables<T, C::LT>(a.tabs, W0 + C::EW * C::PER);
-  const double acc = op_items<N, T, CURVED, FE, MODE>(a, it0, W0);
+  constexpr int WL = op_group_lds<N, T, CURVED, FE, MODE>();
+  __shared__ T smem[C::GROUPS * WL];
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / C::GL);  // group-uniform (scalar)
+  T* const W0 = smem + grp * WL;  // this group's LDS
+  int count;
+  const int64_t first = block_chunk(a, xcd_block(), C::EB, &count);
+  const int64_t it0 = first + (int64_t)grp * C::EW;  // first item of the group
+  load_lane_tables<T, C::LT, C::GL>(a.tabs, W0 + C::EW * C::PER);
+  const double acc = op_items<N, T, CURVED, FE, MODE>(a, it0, count - grp * C::EW, W0);
   if constexpr (!FE && MODE == OP_DOT)
-    if ((threadIdx.x & 63) == 0) a.partials[(int64_t)blockIdx.x * C::WAVES + wave] = acc;
+    if ((threadIdx.x & 63) == 0) a.partials[(int64_t)blockIdx.x * C::WAVES + (threadIdx.x >> 6)] = acc;
 }
 
 // ------------------------------------------------------------------ multi mesh
@@ -43,10 +45,10 @@ template <int N, typename T, bool CURVED, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<N, CURVED, false>::WPE)))
 op_multi_kernel(const MultiArgs<T> m) {
   using C = Cfg<N, CURVED, false>;
-  constexpr int WL = op_wave_lds<N, T, CURVED, false, MODE>();
-  __shared__ T smem[C::WAVES * WL];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
-  T* const W0 = smem + wave * WL;
+  constexpr int WL = op_group_lds<N, T, CURVED, false, MODE>();
+  __shared__ T smem[C::GROUPS * WL];
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / C::GL);  // group-uniform (scalar)
+  T* const W0 = smem + grp * WL;
   const cptr<MeshEntry<T>> tab = (cptr<MeshEntry<T>>)(uintptr_t)m.table;
   const cptr<int64_t> xcd = (cptr<int64_t>)(uintptr_t)m.xcd;
   const int x = blockIdx.x & 7;
@@ -54,7 +56,7 @@ op_multi_kernel(const MultiArgs<T> m) {
   int64_t tile = xcd[x] + (blockIdx.x >> 3);
   if (tile >= end) return;
   // every mesh of the launch has the same degree and precision: one table
-  load_lane_tables<T, C::LT>(tab[0].a.tabs, W0 + C::EW * C::PER);
+  load_lane_tables<T, C::LT, C::GL>(tab[0].a.tabs, W0 + C::EW * C::PER);
   int mi = find_mesh(tab, m.count, tile);
   if constexpr (PERSIST) {
     const int64_t stride = gridDim.x >> 3;
@@ -65,7 +67,8 @@ op_multi_kernel(const MultiArgs<T> m) {
   } else {
     const cptr<MeshEntry<T>> E = tab + mi;
     const OpArgs<T>& a = *(const OpArgs<T>*)&E->a;
-    op_items<N, T, CURVED, false, MODE>(a, (tile - E->tile0) * C::EB + (int64_t)wave * C::EW, W0);
+    const int64_t it0 = (tile - E->tile0) * C::EB + (int64_t)grp * C::EW;
+    op_items<N, T, CURVED, false, MODE>(a, it0, group_count(a, it0), W0);
   }
 }
 
@@ -89,14 +92,18 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   a.xold = (const T*)xold;
   a.sigma = (T)sigma;
   a.theta = (T)theta;
-  if (nrhs == 1 && a.Nx % C::EB == 0) {
-    a.rowchunks = a.Nx / C::EB;
+  if (nrhs == 1) {  // tiled order, rows of ceil(Nx / EB) chunks
+    a.rowchunks = (a.Nx + C::EB - 1) / C::EB;
     a.tile_y = kTileY;
   }
-  const int64_t nb = (L->n_el * nrhs + C::EB - 1) / C::EB;
+  const int64_t nb = nrhs == 1 ? (int64_t)a.rowchunks * a.Ny * a.Nz : (L->n_el * nrhs + C::EB - 1) / C::EB;
   if (nb > INT32_MAX / C::WAVES) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
-  // one partial per wavefront; the level's partials buffer holds n_el + 64
-  if (nparts) *nparts = (int)nb * C::WAVES;
+  // one partial per wavefront, within the level's partials buffer
+  if (nparts) {
+    if (nb * C::WAVES > op_partials_capacity(a.Nx, a.Ny, a.Nz))
+      return fail(HMG_ERR_WORKSPACE, "operator partial sums exceed their buffer");
+    *nparts = (int)nb * C::WAVES;
+  }
   dim3 grid((unsigned)nb), block(64 * C::WAVES);
   if (FE) {
     hipLaunchKernelGGL((op_kernel<N, T, CURVED, true, OP_APPLY>), grid, block, 0, s, a);

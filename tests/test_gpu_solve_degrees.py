@@ -1,5 +1,5 @@
-"""GPU parity at the degrees of the large workloads (k = 4 on 64^3, k = 7 on
-48^3): componentwise bounds of the operator, the residual and Chebyshev
+"""GPU parity at the degrees of the large workloads (k = 4 on 64^3, k = 5 and
+k = 7 on 48^3): componentwise bounds of the operator, the residual and Chebyshev
 epilogues fused into the operator kernel (Alg. 2 residual, Alg. 3 update,
 including the variant that keeps the input in LDS), in FP64 and FP32, on
 curvilinear meshes with per-element penalty scales, against the oracle's
@@ -40,9 +40,10 @@ from paper_1910_01900_amd.inputs import tau_scale, uniform
 pytestmark = pytest.mark.gpu
 
 # curvilinear meshes with penalty scales U[1, 10] and mixed boundary
-# conditions; k = 4: 12 elements (1.5 workgroups of 8), k = 7: 8 elements
-# (2 workgroups of 4)
-CASES = {4: (3, 2, 2), 7: (2, 2, 2)}
+# conditions; k = 4: 12 elements (1.5 workgroups of 8), k = 5: 18 elements
+# in x-rows of 9 (workgroups of 7 elements: a full and a 2-element chunk
+# per row), k = 7: 8 elements (2 workgroups of 4)
+CASES = {4: (3, 2, 2), 5: (9, 2, 1), 7: (2, 2, 2)}
 EPS32 = 2.0 ** -24
 
 
@@ -72,7 +73,7 @@ def _c(k, prec):
     return 1e-12 if prec == hmg.F64 else fp32_bound(k) * lebesgue_end(k + 1)
 
 
-@pytest.mark.parametrize("k", [4, 7])
+@pytest.mark.parametrize("k", [4, 5, 7])
 @pytest.mark.parametrize("prec", [hmg.F64, hmg.F32])
 def test_operator_componentwise(k, prec):
     hm, _, A, absA = oracle_case(k)
@@ -86,7 +87,7 @@ def test_operator_componentwise(k, prec):
     assert ratio <= 1.0
 
 
-@pytest.mark.parametrize("k", [4, 7])
+@pytest.mark.parametrize("k", [4, 5, 7])
 @pytest.mark.parametrize("prec", [hmg.F64, hmg.F32])
 def test_residual_componentwise(k, prec):
     hm, _, A, absA = oracle_case(k)
@@ -102,7 +103,7 @@ def test_residual_componentwise(k, prec):
     assert ratio <= 1.0
 
 
-@pytest.mark.parametrize("k", [4, 7])
+@pytest.mark.parametrize("k", [4, 5, 7])
 @pytest.mark.parametrize("prec", [hmg.F64, hmg.F32])
 @pytest.mark.parametrize("x_is_zero", [False, True])
 def test_chebyshev_steps(k, prec, x_is_zero):
