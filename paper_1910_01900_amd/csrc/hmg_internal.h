@@ -237,6 +237,8 @@ constexpr int op_elems_per_group(int n) {
   return op_group_lanes(n) / (n * n) >= 1 ? op_group_lanes(n) / (n * n) : 1;
 }
 constexpr int op_elems_per_block(int n) { return 64 * kOpWaves / op_group_lanes(n) * op_elems_per_group(n); }
+// LDS values of one n^3 array of an element (n = 8: rows of 9, planes of 72).
+constexpr int lds_array_size(int n) { return n == 8 ? 8 * 72 : n * n * n; }
 // Wavefront partial sums an OP_DOT launch on a mesh of nx x ny x nz
 // elements can write: ceil(nx / EB) workgroups per x-row (EB >= 4), four
 // wavefronts each, at most n_el + 4 ny nz.

@@ -46,6 +46,7 @@ template <int N, bool CURVED, bool FE>
 struct Cfg {
   static constexpr int NT = N * N;
   static constexpr int N3 = N * N * N;
+  static constexpr int AS = lds_array_size(N);  // LDS values of one n^3 array (padded)
   static constexpr int WAVES = kOpWaves;
   static constexpr int GL = op_group_lanes(N);        // lanes of a group (64 or the workgroup)
   static constexpr int GROUPS = 64 * WAVES / GL;      // groups per workgroup
@@ -57,8 +58,8 @@ struct Cfg {
   // registers); affine uses 3 arrays and 4 n^2 face values.
   // Padded to PER = 9 (mod 16) values so that the lines of the elements
   // sharing a wavefront fall on different LDS banks.
-  static constexpr int PER0 = CURVED ? (FE ? 3 * N3 : (4 * N3 > 18 * NT ? 4 * N3 : 18 * NT))
-                                     : (FE ? 3 * N3 : (3 * N3 > N3 + 4 * NT ? 3 * N3 : N3 + 4 * NT));
+  static constexpr int PER0 = CURVED ? (FE ? 3 * AS : (4 * AS > 18 * NT ? 4 * AS : 18 * NT))
+                                     : (FE ? 3 * AS : (3 * AS > AS + 4 * NT ? 3 * AS : AS + 4 * NT));
   static constexpr int PER = PER0 + ((9 - PER0 % 16) + 16) % 16;
   static constexpr int LT = TabOff(N).lane_size();
   // minimum waves per SIMD the register allocation must allow (n >= 7: LDS
@@ -185,16 +186,17 @@ __device__ __forceinline__ int lidx(int t, int m) {
 
 // Position of node (i, j, l) of an element in its LDS arrays.  For n = 8
 // the plain order puts the lanes of an x-line access (one i, all j, l) on
-// 8 banks and those of a y-line access on 8 or 16, so both indices are
-// XOR-swizzled with l, the x index also with bits of j: every line access
-// of every direction (64 lanes, two indices varying) then falls on
-// distinct banks, for 4- and 8-byte values and for 32 or 64 banks (checked
-// exhaustively on the host).  Other degrees keep the plain x-fastest order,
-// whose line accesses are at most two-way conflicted.
+// 8 banks and those of a y-line access on 8 or 16; rows padded to 9 values
+// and planes to 72 put x- and y-line accesses on distinct banks and z-line
+// accesses at most two to a bank (4- and 8-byte values, 32 or 64 banks,
+// checked exhaustively on the host), and every point of a line is its
+// lane's base address plus a constant, an instruction offset.  Other
+// degrees keep the plain x-fastest order, whose line accesses are at most
+// two-way conflicted.
 template <int N>
 __device__ __forceinline__ int vpos(int i, int j, int l) {
   if constexpr (N == 8)
-    return (i ^ l ^ (2 * ((j >> 2) & 1)) ^ (6 * ((j >> 1) & 1))) + N * (j ^ l) + N * N * l;
+    return i + 9 * j + 72 * l;
   else
     return i + N * j + N * N * l;
 }
@@ -420,9 +422,10 @@ __device__ __forceinline__ void own_flux(const OpArgs<T>& a, const OwnFace<T>& F
   const auto& tn = F.tn;
   T uq[N], g0[N], g1[N], g2[N];
   read_line<N, T, d>(R, t, uq);
-  read_line<N, T, d>(R + N3, t, g0);
-  read_line<N, T, d>(R + 2 * N3, t, g1);
-  read_line<N, T, d>(R + 3 * N3, t, g2);
+  constexpr int AS = lds_array_size(N);
+  read_line<N, T, d>(R + AS, t, g0);
+  read_line<N, T, d>(R + 2 * AS, t, g1);
+  read_line<N, T, d>(R + 3 * AS, t, g2);
   const cptr<T> c = fresh(a.tabs);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -792,8 +795,8 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   group_sync<GL>();
 
   T* const A = R;
-  T* const B = R + N3;
-  T* const Cc = R + 2 * N3;
+  T* const B = R + C::AS;
+  T* const Cc = R + 2 * C::AS;
   T v[N];
 
   if constexpr (!CURVED) {
@@ -845,7 +848,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     // FE levels have no face data: the z-derivative is formed from the
     // lane's own z-line in the metric phase, and the z-flux then takes the
     // place of the Gauss-point values (three arrays instead of four)
-    T* const Dg = FE ? A : R + 3 * N3;
+    T* const Dg = FE ? A : R + 3 * C::AS;
     // ---- curved: interpolation to Gauss points, x then y then z
     if (act) {
       const cptr<T> c = fresh(a.tabs);
