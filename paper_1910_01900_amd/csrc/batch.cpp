@@ -208,6 +208,7 @@ void fill_tables(const hmg_batch* B, std::vector<char>& host) {
         MeshEntry<T>& e = E[(size_t)(f * kNq + qi) * cnt + gi];
         e.a = make_args<T>(L);
         e.a.nrhs = B->nrhs;
+        e.a.inv_nrhs = 1.0 / B->nrhs;
         e.a.ld = B->ld[m];
         e.off = B->off[m];
         e.tile0 = B->tile0[f][qi][gi];
@@ -265,7 +266,7 @@ extern "C" int hmg_batch_create(const hmg_level* const* levels, int count, int n
     }
     const int64_t eb = op_elems_per_block(L->n);
     const int64_t ch = (L->n_el * nrhs + eb - 1) / eb;
-    if (ch > INT32_MAX / kOpWaves) {
+    if (ch > INT32_MAX / kOpWaves || L->n_el * nrhs >= ((int64_t)1 << 31)) {
       delete B;
       return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
     }

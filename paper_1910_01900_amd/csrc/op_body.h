@@ -599,13 +599,25 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
   group_sync<op_group_lanes(N)>();
 }
 
+// Element of work item `item` = element * nrhs + vector.  With several
+// vectors, items are below 2^31 and nrhs <= 64 (both checked at launch), and
+// the quotient comes from the host's FP64 1/nrhs instead of an integer
+// division: (item + 1/2) / nrhs lies at least 1/(2 nrhs) >= 2^-7 from an
+// integer, and the two rounded FP64 operations move it by less than 2^-21,
+// so truncation gives the exact quotient.
+template <typename T>
+__device__ __forceinline__ int64_t item_elem(const OpArgs<T>& a, int64_t item) {
+  if (a.nrhs == 1) return item;
+  return (int64_t)(unsigned)(((double)(unsigned)item + 0.5) * a.inv_nrhs);
+}
+
 // Offset of the first value of work item `item` (element x vector) in the
 // vectors of a launch.
 template <int N, typename T>
 __device__ __forceinline__ int64_t item_offset(const OpArgs<T>& a, int64_t item) {
   constexpr int N3 = N * N * N;
   if (a.nrhs == 1) return item * N3;
-  const int64_t el = item / a.nrhs;
+  const int64_t el = item_elem(a, item);
   return (item - el * a.nrhs) * a.ld + el * N3;
 }
 // Work items of a launch in linear order from it0: how many are left
@@ -654,7 +666,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   // one element per wavefront (n = 8): the item, its element and all its
   // index arithmetic are the same on every lane and stay in scalar registers
   const int64_t it = EW == 1 ? it0 : it0 + le;
-  const int64_t e = a.nrhs == 1 ? it : it / a.nrhs;
+  const int64_t e = item_elem(a, it);
   const T* const ub = a.u + (a.nrhs == 1 ? 0 : (it - e * a.nrhs) * a.ld);  // this lane's vector
   const bool act = (le < EW) && (le < nv);
   T* const R = W0 + (le < EW ? le : 0) * PER;
@@ -780,7 +792,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     for (int idx = lane; idx < nload; idx += GL) {
       const int li = EW == 1 ? 0 : idx / N3, p = idx - li * N3;
       const int64_t item = it0 + li;
-      const int64_t elv = a.nrhs == 1 ? item : item / a.nrhs;
+      const int64_t elv = item_elem(a, item);
       const T* const uv = a.u + (a.nrhs == 1 ? 0 : (item - elv * a.nrhs) * a.ld);
       const unsigned ee = (unsigned)elv, rr = ee / (unsigned)a.Nx, ez = rr / (unsigned)a.Ny;
       const int gx = (int)(ee - rr * a.Nx) * k + p % N;
@@ -1037,7 +1049,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     const int li = EW == 1 ? 0 : idx / N3;
     const T val = W0[li * PER + vpos_of<N>(idx - li * N3)];
     const int64_t item = it0 + li;
-    const int64_t el = a.nrhs == 1 ? item : item / a.nrhs;
+    const int64_t el = item_elem(a, item);
     const int64_t gv = el * N3 + (idx - li * N3);  // offset inside one vector
     // FE levels write element-local results, n_el n^3 values per vector
     const int64_t g = gv + (a.nrhs == 1 ? 0 : (item - el * a.nrhs) * (FE ? a.nel * N3 : a.ld));

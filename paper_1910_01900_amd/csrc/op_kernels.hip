@@ -84,6 +84,7 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   OpArgs<T> a = make_args<T>(L);
   a.skip = FE ? skip : nullptr;
   a.nrhs = nrhs;
+  a.inv_nrhs = 1.0 / nrhs;
   a.ld = ld;
   a.u = (const T*)u;
   if (FE && !scratch) scratch = L->scratch();
@@ -96,6 +97,8 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
     a.rowchunks = (a.Nx + C::EB - 1) / C::EB;
     a.tile_y = kTileY;
   }
+  if (nrhs > 1 && (nrhs > 64 || L->n_el * nrhs >= ((int64_t)1 << 31)))
+    return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: at most 64, and fewer than 2^31 element-vectors");
   const int64_t nb = nrhs == 1 ? (int64_t)a.rowchunks * a.Ny * a.Nz : (L->n_el * nrhs + C::EB - 1) / C::EB;
   if (nb > INT32_MAX / C::WAVES) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
   // one partial per wavefront, within the level's partials buffer
