@@ -480,6 +480,20 @@ static int chebyshev(const hmg_level* L, const void* b, void* x, int ns, double 
   const int64_t n = L->n_dofs;
   void* tmp = L->tmp(0);
   void *cur, *oth;
+  if (!x_is_zero && (ns & 1) && ns >= 3) {
+    // odd degree from a nonzero start without copying x: iterates 1, 3, ..
+    // go to tmp and 2, 4, .. back to x, iterate ns - 1 to tmp(1), the last to x
+    // (each step writes a buffer other than its input; out may alias x_old)
+    void* const tmp2 = L->tmp(1);
+    void *prev = x, *at = x;
+    for (int j = 0; j < ns; ++j) {
+      void* out = j == ns - 1 ? x : (j == ns - 2 ? tmp2 : ((j & 1) ? x : tmp));
+      TRY(launch_operator(L, OP_CHEB, at, out, b, j == 0 ? at : prev, j == 0 ? 0.0 : sig[j], th[j], nullptr, s));
+      prev = at;
+      at = out;
+    }
+    return HMG_OK;
+  }
   if (x_is_zero) {
     // x_1 = theta_0 D^{-1} b, x_0 = 0; ns-1 swaps follow
     if (((ns - 1) & 1) == 0) {
@@ -1362,7 +1376,7 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
 // Alg. 3 on nrhs vectors (vector r at r * ld); tmp: a block like x;
 // fe: the element-local results block of a continuous FE level.
 static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, void* x, void* tmp, int ns,
-                       double lmax, int x_is_zero, void* fe, hipStream_t s) {
+                       double lmax, int x_is_zero, void* fe, hipStream_t s, void* tmp2 = nullptr) {
   const size_t es = L->elem_size();
   if (L->space != HMG_DG && !fe) {
     for (int r = 0; r < nrhs; ++r)
@@ -1374,6 +1388,18 @@ static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, 
   const int pr = L->prec;
   const int64_t n = L->n_dofs, all = ld * nrhs;
   void *cur, *oth;
+  if (!x_is_zero && (ns & 1) && ns >= 3 && tmp2) {
+    // odd degree from a nonzero start without copying x (see chebyshev)
+    void *prev = x, *at = x;
+    for (int j = 0; j < ns; ++j) {
+      void* out = j == ns - 1 ? x : (j == ns - 2 ? tmp2 : ((j & 1) ? x : tmp));
+      TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, at, out, b, j == 0 ? at : prev, j == 0 ? 0.0 : sig[j],
+                                  th[j], nullptr, s, fe));
+      prev = at;
+      at = out;
+    }
+    return HMG_OK;
+  }
   if (x_is_zero) {
     if (((ns - 1) & 1) == 0) {
       cur = x;
@@ -1462,7 +1488,8 @@ static int vcycle_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
   TRY(vcycle_v(H, l + 1, nrhs, s));
   for (int q = 0; q < nrhs; ++q)
     TRY(prolongate_add(H->tr[l], (const char*)H->xb(l + 1) + q * oc, (char*)H->xb(l) + q * o, s));
-  return chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 0, H->sb(l), s);
+  // post-smoothing: the residual block is free again and serves as the third buffer
+  return chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 0, H->sb(l), s, H->rb(l));
 }
 
 // z_q = M^{-1} r_q (FP64 blocks, ldr and ldz values apart).

@@ -443,10 +443,22 @@ static dim3 node_grid(const FeGeo& G) {
 template <typename T, int MODE, int K>
 __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* dg, const T* u, T* out, const T* b,
                                                               const T* dinv, const T* xold, T sigma, T theta,
-                                                              const int* skip) {
+                                                              const int* skip, int nrhs, int64_t ld,
+                                                              int64_t dgs) {
   if (skip && *skip) return;  // gated apply (iterative coarse solve)
-  const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
+  // grid z = node plane x vector, vector fastest: the vectors of one plane
+  // run together and share the lines of dinv in L2
+  const unsigned zr = blockIdx.z, uz = nrhs == 1 ? zr : zr / (unsigned)nrhs;
+  const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = (int)uz;
   if (gx >= G.Mx || gy >= G.My) return;
+  if (nrhs > 1) {  // vector r: its node vectors r * ld values on, its element-local results r * dgs
+    const int64_t r = zr - uz * (unsigned)nrhs;
+    u += r * ld;
+    out += r * ld;
+    if (MODE != OP_APPLY) b += r * ld;
+    if (MODE == OP_CHEB) xold += r * ld;
+    dg += r * dgs;
+  }
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
   // node-vector loads first, in flight with the gather
   T x = 0, xo = 0, di = 0, bi = 0;
@@ -505,48 +517,54 @@ __global__ void k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add
 template <typename T, int K>
 static void launch_fe_sum(int mode, dim3 g, dim3 blk, const FeGeo& G, const T* dg, const void* u, void* out,
                           const void* b, const T* di, const void* xold, double sigma, double theta, hipStream_t s,
-                          const int* skip) {
+                          const int* skip, int nrhs, int64_t ld, int64_t dgs) {
   switch (mode) {
     case OP_RESID:
       hipLaunchKernelGGL((k_fe_sum<T, OP_RESID, K>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip, nrhs, ld, dgs);
       break;
     case OP_CHEB:
       hipLaunchKernelGGL((k_fe_sum<T, OP_CHEB, K>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip, nrhs, ld, dgs);
       break;
     default:
       hipLaunchKernelGGL((k_fe_sum<T, OP_APPLY, K>), g, blk, 0, s, G, dg, (const T*)u, (T*)out,
-                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip);
+                         (const T*)b, di, (const T*)xold, (T)sigma, (T)theta, skip, nrhs, ld, dgs);
   }
 }
 
 template <typename T>
 static int fe_sum_t(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, hipStream_t s, const int* skip,
-                    const void* scratch) {
+                    const void* scratch, int nrhs, int64_t ld) {
   FeGeo G = fe_geo(L->mesh, L->k);
-  if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
-  const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
+  if ((int64_t)G.Mz * nrhs > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
+  dim3 g = node_grid(G);
+  g.z *= (unsigned)nrhs;
+  const dim3 blk(kNodeBx, kNodeBy);
   const T* dg = (const T*)(scratch ? scratch : L->scratch());
   const T* di = (const T*)L->dinv();
+  const int64_t dgs = L->n_dg;
+#define HMG_FE_SUM(K) launch_fe_sum<T, K>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip, nrhs, ld, dgs)
   switch (G.k) {
-    case 1: launch_fe_sum<T, 1>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    case 2: launch_fe_sum<T, 2>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    case 3: launch_fe_sum<T, 3>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    case 4: launch_fe_sum<T, 4>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    case 5: launch_fe_sum<T, 5>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    case 6: launch_fe_sum<T, 6>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    case 7: launch_fe_sum<T, 7>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip); break;
-    default: launch_fe_sum<T, 0>(mode, g, blk, G, dg, u, out, b, di, xold, sigma, theta, s, skip);
+    case 1: HMG_FE_SUM(1); break;
+    case 2: HMG_FE_SUM(2); break;
+    case 3: HMG_FE_SUM(3); break;
+    case 4: HMG_FE_SUM(4); break;
+    case 5: HMG_FE_SUM(5); break;
+    case 6: HMG_FE_SUM(6); break;
+    case 7: HMG_FE_SUM(7); break;
+    default: HMG_FE_SUM(0);
   }
+#undef HMG_FE_SUM
   return check_launch("fe_sum");
 }
 int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                 const void* xold, double sigma, double theta, hipStream_t s, const int* skip,
-                const void* scratch) {
-  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch);
-  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch);
+                const void* scratch, int nrhs, int64_t ld) {
+  if (nrhs < 1) return HMG_OK;
+  if (L->prec == HMG_F64) return fe_sum_t<double>(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch, nrhs, ld);
+  return fe_sum_t<float>(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch, nrhs, ld);
 }
 
 // ------------------------------------------------------------------ gated CG (coarse solve)

@@ -389,11 +389,13 @@ int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int we
                 int add, hipStream_t s);
 int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
              hipStream_t s);
-// FE operator node sum with a mode (see launch_operator)
+// FE operator node sum with a mode (see launch_operator) for nrhs vectors
+// in one launch: vector r of u, out, b, xold starts r * ld values after the
+// first, its element-local results r * n_dg values after the first
 // (scratch: the element-local results, NULL for the level's own buffer)
 int fe_node_sum(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                 const void* xold, double sigma, double theta, hipStream_t s, const int* skip = nullptr,
-                const void* scratch = nullptr);
+                const void* scratch = nullptr, int nrhs = 1, int64_t ld = 0);
 // coarse dense FP64 inverse apply: x = Ainv b (b, x of prec), n unknowns
 int coarse_gemv(int prec, const double* Ainv, const void* b, void* x, int n, hipStream_t s);
 // SplitMix64 uniform [-1,1) vector

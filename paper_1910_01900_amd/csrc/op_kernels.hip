@@ -128,13 +128,18 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
   }
   int rc = check_launch("op_kernel");
   if (rc) return rc;
-  if (FE) {  // node sums vector by vector (element-local results n_dg values apart)
-    const size_t es = sizeof(T);
-    for (int r = 0; r < nrhs; ++r) {
-      const size_t o = (size_t)r * ld * es;
-      auto at = [&](const void* p) { return p ? (const void*)((const char*)p + o) : nullptr; };
-      TRY(fe_node_sum(L, mode, at(u), (char*)out + o, at(b), at(xold), sigma, theta, s, skip,
-                      (const char*)scratch + (size_t)r * L->n_dg * es));
+  if (FE) {  // node sums of all vectors in one launch (element-local results n_dg values apart)
+    const int64_t Mz = (int64_t)a.Nz * (N - 1) + 1;
+    if (Mz * nrhs <= 65535) {
+      TRY(fe_node_sum(L, mode, u, out, b, xold, sigma, theta, s, skip, scratch, nrhs, ld));
+    } else {  // too many node planes for one grid: vector by vector
+      const size_t es = sizeof(T);
+      for (int r = 0; r < nrhs; ++r) {
+        const size_t o = (size_t)r * ld * es;
+        auto at = [&](const void* p) { return p ? (const void*)((const char*)p + o) : nullptr; };
+        TRY(fe_node_sum(L, mode, at(u), (char*)out + o, at(b), at(xold), sigma, theta, s, skip,
+                        (const char*)scratch + (size_t)r * L->n_dg * es));
+      }
     }
   }
   return HMG_OK;
