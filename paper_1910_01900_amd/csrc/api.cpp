@@ -480,6 +480,7 @@ static int chebyshev(const hmg_level* L, const void* b, void* x, int ns, double 
   const int64_t n = L->n_dofs;
   void* tmp = L->tmp(0);
   void *cur, *oth;
+  bool x0_zero = false;
   if (!x_is_zero && (ns & 1) && ns >= 3) {
     // odd degree from a nonzero start without copying x: iterates 1, 3, ..
     // go to tmp and 2, 4, .. back to x, iterate ns - 1 to tmp(1), the last to x
@@ -504,7 +505,7 @@ static int chebyshev(const hmg_level* L, const void* b, void* x, int ns, double 
       oth = x;
     }
     TRY(vec_mul3(pr, th[0], L->dinv(), b, cur, n, s));
-    TRY(vec_fill(pr, oth, 0.0, n, s));
+    x0_zero = true;  // the second step reads x_0 = 0 as a NULL x_old (nothing to clear)
   } else {
     // ns swaps follow the first step
     if ((ns & 1) == 0) {
@@ -519,7 +520,7 @@ static int chebyshev(const hmg_level* L, const void* b, void* x, int ns, double 
     std::swap(cur, oth);
   }
   for (int j = 1; j < ns; ++j) {
-    TRY(launch_operator(L, OP_CHEB, cur, oth, b, oth, sig[j], th[j], nullptr, s));
+    TRY(launch_operator(L, OP_CHEB, cur, oth, b, j == 1 && x0_zero ? nullptr : oth, sig[j], th[j], nullptr, s));
     std::swap(cur, oth);
   }
   if (cur != x) return fail(HMG_ERR_INVALID, "internal: Chebyshev buffer parity");
@@ -1388,6 +1389,7 @@ static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, 
   const int pr = L->prec;
   const int64_t n = L->n_dofs, all = ld * nrhs;
   void *cur, *oth;
+  bool x0_zero = false;
   if (!x_is_zero && (ns & 1) && ns >= 3 && tmp2) {
     // odd degree from a nonzero start without copying x (see chebyshev)
     void *prev = x, *at = x;
@@ -1409,7 +1411,7 @@ static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, 
       oth = x;
     }
     TRY(vec_mul3_b(pr, th[0], L->dinv(), b, cur, n, ld, nrhs, s));
-    TRY(vec_fill(pr, oth, 0.0, all, s));
+    x0_zero = true;  // the second step reads x_0 = 0 as a NULL x_old (nothing to clear)
   } else {
     if ((ns & 1) == 0) {
       cur = x;
@@ -1423,7 +1425,8 @@ static int chebyshev_v(const hmg_level* L, int nrhs, int64_t ld, const void* b, 
     std::swap(cur, oth);
   }
   for (int j = 1; j < ns; ++j) {
-    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, oth, sig[j], th[j], nullptr, s, fe));
+    TRY(launch_operator_batched(L, OP_CHEB, nrhs, ld, cur, oth, b, j == 1 && x0_zero ? nullptr : oth, sig[j], th[j],
+                                nullptr, s, fe));
     std::swap(cur, oth);
   }
   if (cur != x) return fail(HMG_ERR_INVALID, "internal: Chebyshev buffer parity");

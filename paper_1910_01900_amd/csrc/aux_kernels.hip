@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
     u += r * ld;
     out += r * ld;
     if (MODE != OP_APPLY) b += r * ld;
-    if (MODE == OP_CHEB) xold += r * ld;
+    if (MODE == OP_CHEB && xold) xold += r * ld;
     dg += r * dgs;
   }
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
@@ -464,7 +464,7 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
   T x = 0, xo = 0, di = 0, bi = 0;
   if (MODE == OP_CHEB) {
     x = u[i];
-    xo = xold[i];
+    xo = xold ? xold[i] : T(0);  // NULL: x_old = 0
     di = dinv[i];
   }
   if (MODE != OP_APPLY) bi = b[i];

@@ -293,7 +293,7 @@ int multi_occupancy(int n, int prec, bool curved, int mode);
 int fused_occupancy(int prec, int mode);
 
 // DG: out = f(A u); FE: cell part into scratch, then node sum with the mode.
-// OP_CHEB: out = u + sigma (u - xold) + theta dinv (b - A u)  (out may alias xold)
+// OP_CHEB: out = u + sigma (u - xold) + theta dinv (b - A u)  (out may alias xold; xold NULL: x_old = 0)
 // OP_DOT : out = A u, partials[blk] = sum u.(A u) (for p^T A p).
 int launch_operator(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, int* nparts, hipStream_t s);

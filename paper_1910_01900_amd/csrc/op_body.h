@@ -1061,7 +1061,8 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       T x;
       if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) x = LT[C::LT + idx];  // kept in LDS
       else x = a.u[g];
-      a.out[g] = x + a.sigma * (x - a.xold[g]) + a.theta * a.dinv[gv] * (a.b[g] - val);
+      const T xo = a.xold ? a.xold[g] : T(0);  // NULL: x_old = 0 (second step from a zero start)
+      a.out[g] = x + a.sigma * (x - xo) + a.theta * a.dinv[gv] * (a.b[g] - val);
     } else {
       a.out[g] = val;
       if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) acc += (double)LT[C::LT + idx] * (double)val;
