@@ -491,6 +491,8 @@ def main():
                     help="only re-run the paper's printed n10 tables (Tables 5-8, p <= 7) and summarise")
     ap.add_argument("--learned-only", action="store_true",
                     help="only the learned coarse-grid correction on curved_k5_48")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the warm-up and timed solve steps of the workload (for kernel traces of the solve)")
     ap.add_argument("--learned-case", choices=["both", "12", "24"], default="both",
                     help="coarse level of the learned correction: Q1 on 12^3 (dense exact solve) or 24^3 (iterative)")
     ap.add_argument("--apply-only", choices=["f64", "f32"], default=None,
@@ -564,6 +566,9 @@ def main():
         return
 
     res = run_workload(a, a.workload, hmg, timed=True)
+    if a.solve_only:
+        print(json.dumps({"workload": a.workload, **res}), flush=True)
+        return
     out = {
         "metric": METRIC,
         "value": res["value"],
@@ -675,6 +680,9 @@ def run_workload(a, name, hmg, timed):
     if not timed:
         total = min(times) * steps
     res = {"value": nrhs * N * steps / total, "ms_per_step": 1e3 * total / steps}
+    if a.solve_only:
+        res["iterations"] = [st["iters"] for st in stats]
+        return res
     if nrhs > 1:
         # the same right-hand sides one after another, and the single solve of stream 3
         Xs = H.vectors(nrhs)
