@@ -153,7 +153,8 @@ int hmg_residual(const hmg_level* L, const void* b, const void* u, void* r, hipS
  * The element geometry is read once for all vectors of an element.
  * 1 <= nrhs <= 64; ld >= the level's DoF count, ld * value size a multiple
  * of 256 bytes.  Results equal nrhs separate hmg_operator_apply calls.
- * The u and v ranges must not overlap.  HMG_ERR_UNSUPPORTED on FE levels.
+ * The u and v ranges must not overlap.  HMG_ERR_UNSUPPORTED on FE levels
+ * and when the level's element count times nrhs reaches 2^31.
  */
 int hmg_operator_apply_batched(const hmg_level* L, int nrhs, const void* u, void* v, int64_t ld,
                                hipStream_t stream);
@@ -285,8 +286,9 @@ int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, dou
  * the V-cycle as one block: every operator application of the smoothers,
  * the residuals and the outer CG takes all vectors in one launch, reading
  * the element geometry once for all of them (on continuous FE levels the
- * node sums then follow vector by vector); transfers and the coarse solve
- * take the vectors one after another.
+ * node sums of all vectors follow as one launch); transfers and the coarse
+ * solve take the vectors one after another.  A level whose element count
+ * times nrhs reaches 2^31 returns HMG_ERR_UNSUPPORTED.
  * set_max_rhs (1..64, default 1) reserves workspace for up to max_rhs
  * vectors and must precede hmg_hierarchy_query and _bind.
  * Vector q of b and x starts q*ld values after the first (FP64, device;
