@@ -479,39 +479,46 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
     out[i] = x + sigma * (x - xo) + theta * di * (bi - v);
   }
 }
-// fe (+)= free * w * E^T dg
-template <typename T>
+// fe (+)= free * w * E^T dg.  K > 0: the degree at compile time (constant
+// divisions); 0: G.k.
+template <typename T, int K>
 __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_c_sum(FeGeo G, const T* dg, T* fe, int weight_mult, int add) {
   const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
   if (gx >= G.Mx || gy >= G.My) return;
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
   int mult;
-  T v = node_gather_sum(G, dg, gx, gy, gz, &mult);
+  T v = node_gather_sum<T, K>(G, dg, gx, gy, gz, &mult);
   if (weight_mult) v /= (T)mult;
   if (node_fixed(G, gx, gy, gz)) v = 0;
   fe[i] = add ? fe[i] + v : v;
 }
-// dg (+)= E (free * w * fe); one thread per DG value (count < 2^31)
-template <typename T>
-__global__ void k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add) {
-  const int n = G.k + 1, n2 = n * n, n3 = n2 * n;
-  const unsigned ndg = (unsigned)G.Nx * G.Ny * G.Nz * n3;
-  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < ndg; i += gridDim.x * blockDim.x) {
-    const unsigned e = i / n3, p = i - e * n3;
-    const unsigned er = e / G.Nx, ex = e - er * G.Nx, ez = er / G.Ny, ey = er - ez * G.Ny;
-    const unsigned pz = p / n2, pr = p - pz * n2, py = pr / n, px = pr - py * n;
-    const int gx = ex * G.k + px, gy = ey * G.k + py, gz = ez * G.k + pz;
-    T v = 0;
-    if (!node_fixed(G, gx, gy, gz)) {
-      v = fe[gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz)];
-      if (weight_mult) {
-        const int mult = (1 + node_axis(gx, G.k, G.Nx).two) * (1 + node_axis(gy, G.k, G.Ny).two) *
-                         (1 + node_axis(gz, G.k, G.Nz).two);
-        v /= (T)mult;
-      }
+// dg (+)= E (free * w * fe), one thread per DG value: grid x over the
+// Nx n^3 values of one x-row of elements, y = ey, z = ez, so the element
+// and local node come without run-time divisions (K > 0: the degree at
+// compile time).  A node is shared along an axis when it is the element's
+// first node and the element is not the first, or its last node and the
+// element is not the last.
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlock) k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add) {
+  const int k = K ? K : G.k, n = k + 1, n2 = n * n, n3 = n2 * n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;  // value within the row
+  if (i >= G.Nx * n3) return;
+  const int ey = blockIdx.y, ez = blockIdx.z;
+  const int ex = i / n3, p = i - ex * n3;
+  const int pz = p / n2, pr = p - pz * n2, py = pr / n, px = pr - py * n;
+  const int gx = ex * k + px, gy = ey * k + py, gz = ez * k + pz;
+  const int64_t o = (int64_t)(ez * G.Ny + ey) * G.Nx * n3 + i;
+  T v = 0;
+  if (!node_fixed(G, gx, gy, gz)) {
+    v = fe[gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz)];
+    if (weight_mult) {
+      const int sx = (px == 0 && ex > 0) || (px == k && ex < G.Nx - 1);
+      const int sy = (py == 0 && ey > 0) || (py == k && ey < G.Ny - 1);
+      const int sz = (pz == 0 && ez > 0) || (pz == k && ez < G.Nz - 1);
+      v /= (T)((1 + sx) * (1 + sy) * (1 + sz));
     }
-    dg[i] = add ? dg[i] + v : v;
   }
+  dg[o] = add ? dg[o] + v : v;
 }
 
 template <typename T, int K>
@@ -688,23 +695,48 @@ int set_flag(int* flag, int v, hipStream_t s) {
   return check_launch("set_flag");
 }
 
+template <typename T, int K>
+static void launch_c(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add,
+                     hipStream_t s) {
+  if (inject) {
+    const int n3 = (G.k + 1) * (G.k + 1) * (G.k + 1);
+    const dim3 g((unsigned)((G.Nx * n3 + kBlock - 1) / kBlock), (unsigned)G.Ny, (unsigned)G.Nz);
+    hipLaunchKernelGGL((k_c_inject<T, K>), g, dim3(kBlock), 0, s, G, (const T*)src, (T*)dst, weight_mult, add);
+  } else {
+    hipLaunchKernelGGL((k_c_sum<T, K>), node_grid(G), dim3(kNodeBx, kNodeBy), 0, s, G, (const T*)src, (T*)dst,
+                       weight_mult, add);
+  }
+}
+template <typename T>
+static void launch_c_k(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add,
+                       hipStream_t s) {
+  switch (G.k) {
+    case 1: launch_c<T, 1>(inject, G, src, dst, weight_mult, add, s); break;
+    case 2: launch_c<T, 2>(inject, G, src, dst, weight_mult, add, s); break;
+    case 3: launch_c<T, 3>(inject, G, src, dst, weight_mult, add, s); break;
+    case 4: launch_c<T, 4>(inject, G, src, dst, weight_mult, add, s); break;
+    case 5: launch_c<T, 5>(inject, G, src, dst, weight_mult, add, s); break;
+    case 6: launch_c<T, 6>(inject, G, src, dst, weight_mult, add, s); break;
+    case 7: launch_c<T, 7>(inject, G, src, dst, weight_mult, add, s); break;
+    default: launch_c<T, 0>(inject, G, src, dst, weight_mult, add, s);
+  }
+}
 int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int weight_mult, int add,
                 hipStream_t s) {
   FeGeo G = fe_geo(m, k);
-  const int64_t ndg = m.n_el() * (int64_t)(k + 1) * (k + 1) * (k + 1);
-  if (ndg >= (int64_t)1 << 31) return fail(HMG_ERR_UNSUPPORTED, "DG vector too long for the injection kernel");
-  const unsigned g = grid_for(ndg);
-  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_inject<double>, g, kBlock, 0, s, G, (const double*)fe, (double*)dg, weight_mult, add),
-                hipLaunchKernelGGL(k_c_inject<float>, g, kBlock, 0, s, G, (const float*)fe, (float*)dg, weight_mult, add));
+  const int64_t n3 = (int64_t)(k + 1) * (k + 1) * (k + 1);
+  if (m.n_el() * n3 >= (int64_t)1 << 31) return fail(HMG_ERR_UNSUPPORTED, "DG vector too long for the injection kernel");
+  if (G.Ny > 65535 || G.Nz > 65535) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for the injection grid");
+  if (prec == HMG_F64) launch_c_k<double>(true, G, fe, dg, weight_mult, add, s);
+  else launch_c_k<float>(true, G, fe, dg, weight_mult, add, s);
   return check_launch("c_inject");
 }
 int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
              hipStream_t s) {
   FeGeo G = fe_geo(m, k);
   if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
-  const dim3 g = node_grid(G), blk(kNodeBx, kNodeBy);
-  PREC_DISPATCH(prec, hipLaunchKernelGGL(k_c_sum<double>, g, blk, 0, s, G, (const double*)dg, (double*)fe, weight_mult, add),
-                hipLaunchKernelGGL(k_c_sum<float>, g, blk, 0, s, G, (const float*)dg, (float*)fe, weight_mult, add));
+  if (prec == HMG_F64) launch_c_k<double>(false, G, dg, fe, weight_mult, add, s);
+  else launch_c_k<float>(false, G, dg, fe, weight_mult, add, s);
   return check_launch("c_sum");
 }
 

@@ -78,12 +78,13 @@ def test_fe_apply_matches_oracle(k, deformed):
     assert np.all(np.abs(v - ref) <= 1e-12 * (abs(A) @ np.abs(u)))
 
 
-@pytest.mark.parametrize("k", [3, 7])
+@pytest.mark.parametrize("k", [3, 5, 6, 7])
 @pytest.mark.parametrize("deformed", [False, True])
-def test_fe_apply_degrees_3_and_7(k, deformed):
-    """FE levels of degree 3 and 7 (degree 7: the XOR-swizzled LDS layout on
-    the gather path) on 18 elements: 4.5 workgroups at one element per
-    wavefront (k = 7), a ragged tail."""
+def test_fe_apply_degrees_3_to_7(k, deformed):
+    """FE levels of degree 3, 5, 6 and 7 on 18 elements in x-rows of 3:
+    degree 5 runs 7 elements per 256-lane workgroup group (one partial
+    chunk per row), degree 7 the padded n = 8 LDS layout on the gather path
+    at one element per wavefront (4.5 workgroups, a ragged tail)."""
     hm, om = meshes((3, 2, 3), k, deformed, bc=(0, 1, 0, 0, 1, 0))
     L = hmg.Level(hm, space=hmg.FE)
     u = uniform(3, L.n_dofs)
