@@ -191,6 +191,7 @@ struct OpArgs {
   T h[3];
   const int* skip;        // continuous FE levels: the launch does nothing while *skip != 0 (NULL: never)
   double inv_nrhs;        // 1 / nrhs (the item -> element quotient, see item_elem)
+  double inv_nx, inv_ny;  // 1 / Nx, 1 / Ny (element coordinates, see exact_div)
 };
 
 // The level's constant arguments (vectors unset, one vector, linear order).
@@ -217,6 +218,8 @@ inline OpArgs<T> make_args(const hmg_level* L) {
   a.tile_y = 1;
   a.nrhs = 1;
   a.inv_nrhs = 1.0;
+  a.inv_nx = 1.0 / a.Nx;
+  a.inv_ny = 1.0 / a.Ny;
   a.ld = L->n_dofs;
   for (int d = 0; d < 3; ++d) a.h[d] = (T)L->mesh.h(d);
   a.skip = nullptr;
@@ -263,8 +266,8 @@ struct MeshEntry {
 };
 // The host writes the table that the kernels read: the layout must agree in
 // the host and the device compilation.
-static_assert(sizeof(MeshEntry<double>) == 232 && sizeof(MeshEntry<float>) == 216, "MeshEntry layout");
-static_assert(offsetof(MeshEntry<double>, off) == 200 && offsetof(MeshEntry<float>, off) == 184, "MeshEntry layout");
+static_assert(sizeof(MeshEntry<double>) == 248 && sizeof(MeshEntry<float>) == 232, "MeshEntry layout");
+static_assert(offsetof(MeshEntry<double>, off) == 216 && offsetof(MeshEntry<float>, off) == 200, "MeshEntry layout");
 static_assert(offsetof(OpArgs<double>, ld) == 152 && offsetof(OpArgs<float>, h) == 152, "OpArgs layout");
 
 // One multi-mesh launch: meshes table[0..count) (device memory, vector

@@ -13,10 +13,10 @@
 // on 36 of its 64 lanes; the workgroup group holds 7 on 252 of 256 lanes,
 // with workgroup barriers between phases (FP64 apply 13% faster, FP32 11%;
 // at n = 5 and 7, 78% and 77% of the lanes work either way and the
-// workgroup group measured no faster).  Lane t of an element owns one line of n points along the
-// direction of the current phase (x-lines: t = j + n*l, y-lines:
-// t = i + n*l, z-lines: t = i + n*j), so every 1-D contraction is a
-// register-only loop; LDS only changes the direction.
+// workgroup group measured no faster).  Lane t of an element owns one line
+// of n points along the direction of the current phase (x-lines:
+// t = j + n*l, y-lines: t = i + n*l, z-lines: t = i + n*j), so every 1-D
+// contraction is a register-only loop; LDS only changes the direction.
 //
 // 1-D contractions use the even-odd decomposition of the centro-symmetric
 // (S, M, K) and skew (D, Sp) tables (Sec. 4 sum factorization), with the
@@ -283,12 +283,20 @@ struct ElemInfo {
   int fidx[3];
 };
 
+// x / d for x < 2^31 from the host's FP64 inv = 1/d: (x + 1/2) / d lies at
+// least 1/(2d) from an integer and the two rounded FP64 operations move it by
+// less than 2^-20 / d, so truncation gives the exact quotient (three VALU
+// instructions instead of an integer division by a run-time value).
+__device__ __forceinline__ unsigned exact_div(unsigned x, double inv) {
+  return (unsigned)(((double)x + 0.5) * inv);
+}
+
 template <typename T>
 __device__ __forceinline__ ElemInfo elem_info(const OpArgs<T>& a, int64_t e) {
   ElemInfo I;
   I.e = e < a.nel ? e : a.nel - 1;
-  // element counts are below 2^31 (checked at level creation): 32-bit division
-  const unsigned ue = (unsigned)I.e, r = ue / (unsigned)a.Nx, uz = r / (unsigned)a.Ny;
+  // element counts are below 2^31 (checked at level creation)
+  const unsigned ue = (unsigned)I.e, r = exact_div(ue, a.inv_nx), uz = exact_div(r, a.inv_ny);
   const int ex = (int)(ue - r * a.Nx), ey = (int)(r - uz * a.Ny), ez = (int)uz;
   I.hb = (ex > 0) | ((ex + 1 < a.Nx) << 1) | ((ey > 0) << 2) | ((ey + 1 < a.Ny) << 3) | ((ez > 0) << 4) |
          ((ez + 1 < a.Nz) << 5);
@@ -608,7 +616,7 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
 template <typename T>
 __device__ __forceinline__ int64_t item_elem(const OpArgs<T>& a, int64_t item) {
   if (a.nrhs == 1) return item;
-  return (int64_t)(unsigned)(((double)(unsigned)item + 0.5) * a.inv_nrhs);
+  return (int64_t)exact_div((unsigned)item, a.inv_nrhs);
 }
 
 // Offset of the first value of work item `item` (element x vector) in the
@@ -794,7 +802,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       const int64_t item = it0 + li;
       const int64_t elv = item_elem(a, item);
       const T* const uv = a.u + (a.nrhs == 1 ? 0 : (item - elv * a.nrhs) * a.ld);
-      const unsigned ee = (unsigned)elv, rr = ee / (unsigned)a.Nx, ez = rr / (unsigned)a.Ny;
+      const unsigned ee = (unsigned)elv, rr = exact_div(ee, a.inv_nx), ez = exact_div(rr, a.inv_ny);
       const int gx = (int)(ee - rr * a.Nx) * k + p % N;
       const int gy = (int)(rr - ez * a.Ny) * k + (p / N) % N;
       const int gz = (int)ez * k + p / NT;
