@@ -1596,24 +1596,46 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
   }
   if (n_active == 0) return finish(HMG_OK);
   TRY(upload_active());
-  TRY(precondition_v(H, nrhs, R, L, Z, L, s));
-  TRY(vec_copy(HMG_F64, Z, P, L * nrhs, s));
-  TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
+  // FP32 V-cycle inside standard CG: the CG update also writes the residual
+  // in FP32 straight into the V-cycle's right-hand side block, and the
+  // V-cycle's FP32 result enters r.z and the direction update directly
+  // (widened exactly, as the conversion to an FP64 z would), so z is never
+  // stored in FP64 (same arithmetic, three vector passes fewer per iteration)
+  const bool zf = !H->flexible && H->mg_prec == HMG_F32;
+  float* const r32 = zf ? (float*)H->bb(0) : nullptr;
+  const float* const z32 = zf ? (const float*)H->xb(0) : nullptr;
+  const int64_t l32 = H->ldl[0];
+  if (zf) {
+    TRY(vec_convert_b(HMG_F64, R, L, HMG_F32, r32, l32, n, nrhs, s));
+    TRY(vcycle_v(H, 0, nrhs, s));
+    TRY(cg_update_p_zf_b(P, z32, nullptr, nullptr, n, L, l32, nrhs, act, s));
+    TRY(vec_dot_zf_b(R, z32, n, L, l32, nrhs, part, s1, s));
+  } else {
+    TRY(precondition_v(H, nrhs, R, L, Z, L, s));
+    TRY(vec_copy(HMG_F64, Z, P, L * nrhs, s));
+    TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
+  }
   int it = 0;
   while (n_active > 0 && it < maxit) {
     if (it > 0) {
-      TRY(precondition_v(H, nrhs, R, L, Z, L, s));
-      TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
-      if (H->flexible) {
-        TRY(vec_dot_b(Z, V, n, L, nrhs, part, s4, s));
-        TRY(cg_update_p_b(P, Z, s4, s2, n, L, nrhs, act, true, s));
+      if (zf) {
+        TRY(vcycle_v(H, 0, nrhs, s));  // the right-hand side block holds r in FP32 (cg_update_xr_b)
+        TRY(vec_dot_zf_b(R, z32, n, L, l32, nrhs, part, s1, s));
+        TRY(cg_update_p_zf_b(P, z32, s1, s0, n, L, l32, nrhs, act, s));
       } else {
-        TRY(cg_update_p_b(P, Z, s1, s0, n, L, nrhs, act, false, s));
+        TRY(precondition_v(H, nrhs, R, L, Z, L, s));
+        TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
+        if (H->flexible) {
+          TRY(vec_dot_b(Z, V, n, L, nrhs, part, s4, s));
+          TRY(cg_update_p_b(P, Z, s4, s2, n, L, nrhs, act, true, s));
+        } else {
+          TRY(cg_update_p_b(P, Z, s1, s0, n, L, nrhs, act, false, s));
+        }
       }
     }
     TRY(launch_operator_batched(A, OP_APPLY, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s));
     TRY(vec_dot_b(P, V, n, L, nrhs, part, s2, s));
-    TRY(cg_update_xr_b(X, R, P, V, s1, s2, n, L, nrhs, part, s3, s0, act, s));
+    TRY(cg_update_xr_b(X, R, P, V, s1, s2, n, L, nrhs, part, s3, s0, act, s, r32, l32));
     HMG_HIP(hipMemcpyAsync(hs.data(), s2, nrhs * 8, hipMemcpyDeviceToHost, s));
     HMG_HIP(hipMemcpyAsync(hs.data() + nrhs, s3, nrhs * 8, hipMemcpyDeviceToHost, s));
     HMG_HIP(hipStreamSynchronize(s));

@@ -246,12 +246,14 @@ __global__ void k_reduce_b(const double* partials, int np, double* out) {
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 // omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; partials of r_r . r_r;
-// save[r] = num[r]
+// save[r] = num[r]; r32 (may be NULL): r_r rounded to FP32, vector r at r * ld32
+// (the next V-cycle's right-hand side block)
 __global__ void k_cg_xr_b(double* x, double* r, const double* p, const double* v, const double* num,
                           const double* den, int64_t n, int64_t ld, double* partials, double* save,
-                          const int* active) {
+                          const int* active, float* r32, int64_t ld32) {
   const int q = blockIdx.y;
   const int64_t o = q * ld;
+  float* const r32q = r32 ? r32 + q * ld32 : nullptr;
   double acc = 0.0;
   if (active[q]) {
     const double omega = num[q] / den[q];
@@ -259,17 +261,45 @@ __global__ void k_cg_xr_b(double* x, double* r, const double* p, const double* v
       x[o + i] += omega * p[o + i];
       const double ri = r[o + i] - omega * v[o + i];
       r[o + i] = ri;
+      if (r32q) r32q[i] = (float)ri;
       acc += ri * ri;
     }
   } else {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-      acc += r[o + i] * r[o + i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      const double ri = r[o + i];
+      if (r32q) r32q[i] = (float)ri;
+      acc += ri * ri;
+    }
   }
   double s = block_reduce(acc);
   if (threadIdx.x == 0) {
     partials[q * gridDim.x + blockIdx.x] = s;
     if (blockIdx.x == 0 && save && active[q]) save[q] = num[q];
   }
+}
+// partials[r * gridDim.x + block] of x_r . z_r with z in FP32 (vector r of z
+// at r * ldz): the FP64 products of the FP32 preconditioned residual,
+// widened exactly, without an FP64 copy of it
+__global__ void k_dot_zf_b(const double* x, const float* z, int64_t n, int64_t ld, int64_t ldz, double* partials) {
+  const double* xr = x + blockIdx.y * ld;
+  const float* zr = z + blockIdx.y * ldz;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += xr[i] * (double)zr[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+// p_r = z_r + beta_r p_r with z in FP32 (vector r at r * ldz), beta_r =
+// num[r] / den[r]; den = NULL: p_r = z_r (the first direction)
+__global__ void k_cg_p_zf_b(double* p, const float* z, const double* num, const double* den, int64_t n,
+                            int64_t ld, int64_t ldz, const int* active) {
+  const int q = blockIdx.y;
+  if (den && !active[q]) return;  // the first direction is set for every vector
+  const double beta = den ? num[q] / den[q] : 0.0;
+  double* const pq = p + q * ld;
+  const float* const zq = z + q * ldz;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    pq[i] = den ? (double)zq[i] + beta * pq[i] : (double)zq[i];
 }
 // p_r = z_r + beta_r p_r, beta_r = (+-) num[r] / den[r]
 __global__ void k_cg_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld,
@@ -315,11 +345,25 @@ int vec_dot_b(const double* x, const double* y, int64_t n, int64_t ld, int nrhs,
   hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)partials, (int)g, out);
   return check_launch("reduce_b");
 }
+int vec_dot_zf_b(const double* x, const float* z, int64_t n, int64_t ld, int64_t ldz, int nrhs, double* partials,
+                 double* out, hipStream_t s) {
+  const unsigned g = grid_for_b(n);
+  hipLaunchKernelGGL(k_dot_zf_b, dim3(g, nrhs), kBlock, 0, s, x, z, n, ld, ldz, partials);
+  TRY(check_launch("dot_zf_b"));
+  hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)partials, (int)g, out);
+  return check_launch("reduce_b");
+}
+int cg_update_p_zf_b(double* p, const float* z, const double* num, const double* den, int64_t n, int64_t ld,
+                     int64_t ldz, int nrhs, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p_zf_b, dim3(grid_for(n), nrhs), kBlock, 0, s, p, z, num, den, n, ld, ldz, active);
+  return check_launch("cg_p_zf_b");
+}
 int cg_update_xr_b(double* x, double* r, const double* p, const double* v, const double* num, const double* den,
                    int64_t n, int64_t ld, int nrhs, double* partials, double* rr, double* save, const int* active,
-                   hipStream_t s) {
+                   hipStream_t s, float* r32, int64_t ld32) {
   const unsigned g = grid_for_b(n);
-  hipLaunchKernelGGL(k_cg_xr_b, dim3(g, nrhs), kBlock, 0, s, x, r, p, v, num, den, n, ld, partials, save, active);
+  hipLaunchKernelGGL(k_cg_xr_b, dim3(g, nrhs), kBlock, 0, s, x, r, p, v, num, den, n, ld, partials, save, active,
+                     r32, ld32);
   TRY(check_launch("cg_xr_b"));
   hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)partials, (int)g, rr);
   return check_launch("reduce_b");

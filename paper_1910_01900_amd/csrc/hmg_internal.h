@@ -371,10 +371,17 @@ int vec_mul3_b(int prec, double a, const void* d, const void* b, void* z, int64_
 // out[r] = x_r . y_r (partials: nrhs * kPartialsB values)
 int vec_dot_b(const double* x, const double* y, int64_t n, int64_t ld, int nrhs, double* partials, double* out,
               hipStream_t s);
-// omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; rr[r] = r_r . r_r; save[r] = num[r]
+// omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; rr[r] = r_r . r_r; save[r] = num[r];
+// r32 (may be NULL): every r_r rounded to FP32 as well, vector r at r * ld32
 int cg_update_xr_b(double* x, double* r, const double* p, const double* v, const double* num, const double* den,
                    int64_t n, int64_t ld, int nrhs, double* partials, double* rr, double* save, const int* active,
-                   hipStream_t s);
+                   hipStream_t s, float* r32 = nullptr, int64_t ld32 = 0);
+// out[r] = x_r . z_r with z in FP32 (vector r at r * ldz), products in FP64
+int vec_dot_zf_b(const double* x, const float* z, int64_t n, int64_t ld, int64_t ldz, int nrhs, double* partials,
+                 double* out, hipStream_t s);
+// p_r = z_r + (num[r] / den[r]) p_r with z in FP32 (den NULL: p_r = z_r)
+int cg_update_p_zf_b(double* p, const float* z, const double* num, const double* den, int64_t n, int64_t ld,
+                     int64_t ldz, int nrhs, const int* active, hipStream_t s);
 // p_r = z_r + beta_r p_r, beta_r = num[r] / den[r] (negated if `negate`)
 int cg_update_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld, int nrhs,
                   const int* active, bool negate, hipStream_t s);
