@@ -1275,6 +1275,12 @@ extern "C" int hmg_vcycle(hmg_hierarchy* H, const double* b, double* x, hipStrea
 // The second half of a PCG iteration (Alg. 1): v = A p, p.Ap -> sc[2],
 // alpha = sc[1] / sc[2], x += alpha p, r -= alpha v, r.r -> sc[3], and the
 // current delta kept in sc[0] for the next beta.
+// FP32 V-cycle inside standard CG: the CG update also writes r in FP32 into
+// the V-cycle's right-hand side, and r.z and the direction update read the
+// V-cycle's FP32 result (widened exactly, as a conversion to FP64 would), so
+// z is never stored in FP64 (the same arithmetic, three passes fewer).
+static bool fp32_z(const hmg_hierarchy* H) { return !H->flexible && H->mg_prec == HMG_F32; }
+
 static int pcg_update(hmg_hierarchy* H, double* x, hipStream_t s) {
   const hmg_level* A = H->fine64;
   const int64_t n = A->n_dofs;
@@ -1282,7 +1288,8 @@ static int pcg_update(hmg_hierarchy* H, double* x, hipStream_t s) {
   int nparts = 0;
   TRY(launch_operator(A, OP_DOT, p, v, nullptr, nullptr, 0, 0, &nparts, s));
   TRY(reduce_partials(A->partials(), nparts, sc + 2, s));
-  const int g = cg_update_xr(x, r, p, v, sc + 1, sc + 2, n, part, s, sc + 0);
+  const int g = cg_update_xr(x, r, p, v, sc + 1, sc + 2, n, part, s, sc + 0,
+                             fp32_z(H) ? (float*)H->b(0) : nullptr);
   if (g < 0) return g;
   return reduce_partials(part, g, sc + 3, s);
 }
@@ -1295,6 +1302,13 @@ static int pcg_update(hmg_hierarchy* H, double* x, hipStream_t s) {
 static int pcg_iteration(hmg_hierarchy* H, double* x, hipStream_t s) {
   const int64_t n = H->fine64->n_dofs;
   double *r = H->cg(0), *p = H->cg(1), *v = H->cg(2), *z = H->cg(3), *sc = H->scal(), *part = H->part();
+  if (fp32_z(H)) {  // the right-hand side H->b(0) holds r in FP32 (pcg_update)
+    TRY(vcycle(H, 0, s));
+    const float* z32 = (const float*)H->x(0);
+    TRY(vec_dot_zf(r, z32, n, part, sc + 1, s));
+    TRY(cg_update_p_zf(p, z32, sc + 1, sc + 0, n, s));
+    return pcg_update(H, x, s);
+  }
   TRY(precondition(H, r, z, s));
   TRY(vec_dot(HMG_F64, r, z, n, part, sc + 1, s));
   if (H->flexible) {
@@ -1333,9 +1347,16 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
   if (!std::isfinite(nr)) return finish(fail(HMG_ERR_NONFINITE, "initial residual is not finite"));
   const double r0 = nr;
   if (r0 == 0.0 || nr <= atol) return finish(HMG_OK);
-  TRY(precondition(H, r, z, s));
-  TRY(vec_copy(HMG_F64, z, p, n, s));
-  TRY(vec_dot(HMG_F64, r, z, n, part, sc + 1, s));
+  if (fp32_z(H)) {
+    TRY(vec_convert(HMG_F64, r, HMG_F32, H->b(0), n, s));
+    TRY(vcycle(H, 0, s));
+    TRY(cg_update_p_zf(p, (const float*)H->x(0), nullptr, nullptr, n, s));
+    TRY(vec_dot_zf(r, (const float*)H->x(0), n, part, sc + 1, s));
+  } else {
+    TRY(precondition(H, r, z, s));
+    TRY(vec_copy(HMG_F64, z, p, n, s));
+    TRY(vec_dot(HMG_F64, r, z, n, part, sc + 1, s));
+  }
   int it = 0;
   while (nr / r0 > rtol && nr > atol && it < maxit) {
     if (it == 0) {
@@ -1370,9 +1391,9 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
 // ================================================================== several right-hand sides
 // The V-cycle and PCG on blocks of nrhs vectors: every level applies its
 // operator to all vectors in one launch (the element geometry read once per
-// element for all of them; the node sums of continuous FE levels follow
-// vector by vector); transfers and the coarse solve take the vectors one
-// after another.
+// element for all of them; the node sums of continuous FE levels follow as
+// one launch); transfers and the coarse solve take the vectors one after
+// another.
 
 // Alg. 3 on nrhs vectors (vector r at r * ld); tmp: a block like x;
 // fe: the element-local results block of a continuous FE level.
@@ -1596,12 +1617,8 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
   }
   if (n_active == 0) return finish(HMG_OK);
   TRY(upload_active());
-  // FP32 V-cycle inside standard CG: the CG update also writes the residual
-  // in FP32 straight into the V-cycle's right-hand side block, and the
-  // V-cycle's FP32 result enters r.z and the direction update directly
-  // (widened exactly, as the conversion to an FP64 z would), so z is never
-  // stored in FP64 (same arithmetic, three vector passes fewer per iteration)
-  const bool zf = !H->flexible && H->mg_prec == HMG_F32;
+  // FP32 V-cycle inside standard CG: z stays in FP32 (see fp32_z)
+  const bool zf = fp32_z(H);
   float* const r32 = zf ? (float*)H->bb(0) : nullptr;
   const float* const z32 = zf ? (const float*)H->xb(0) : nullptr;
   const int64_t l32 = H->ldl[0];

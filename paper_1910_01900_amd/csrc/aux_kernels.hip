@@ -88,7 +88,7 @@ __global__ void k_splitmix(uint64_t seed, T* x, int64_t n) {
 
 // CG (Alg. 1): omega = delta / (p^T v); x += omega p; r -= omega v; partials of r.r
 __global__ void k_cg_xr(double* x, double* r, const double* p, const double* v, const double* num,
-                        const double* den, int64_t n, double* partials, double* save) {
+                        const double* den, int64_t n, double* partials, double* save, float* r32) {
   const double omega = *num / *den;
   // keep delta = *num for the next iteration's beta (save != num, den)
   if (save && blockIdx.x == 0 && threadIdx.x == 0) *save = *num;
@@ -97,10 +97,25 @@ __global__ void k_cg_xr(double* x, double* r, const double* p, const double* v, 
     x[i] += omega * p[i];
     const double ri = r[i] - omega * v[i];
     r[i] = ri;
+    if (r32) r32[i] = (float)ri;  // the next V-cycle's FP32 right-hand side
     acc += ri * ri;
   }
   double s = block_reduce(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+// partials of x . z with z in FP32 (widened exactly), as k_dot
+__global__ void k_dot_zf(const double* x, const float* z, int64_t n, double* partials) {
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += x[i] * (double)z[i];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+// p = z + (*num / *den) p with z in FP32; den = NULL: p = z
+__global__ void k_cg_p_zf(double* p, const float* z, const double* num, const double* den, int64_t n) {
+  const double beta = den ? *num / *den : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = den ? (double)z[i] + beta * p[i] : (double)z[i];
 }
 // p = z + beta p, beta = (+-) *num / *den
 __global__ void k_cg_p(double* p, const double* z, const double* num, const double* den, int64_t n, int neg) {
@@ -192,10 +207,21 @@ int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials,
   if (rc) return rc;
   return reduce_partials(partials, (int)g, out, s);
 }
-int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
-                 const double* den, int64_t n, double* partials, hipStream_t s, double* save) {
+int vec_dot_zf(const double* x, const float* z, int64_t n, double* partials, double* out, hipStream_t s) {
   const unsigned g = dot_grid(n);
-  hipLaunchKernelGGL(k_cg_xr, g, kBlock, 0, s, x, r, p, v, num, den, n, partials, save);
+  hipLaunchKernelGGL(k_dot_zf, g, kBlock, 0, s, x, z, n, partials);
+  int rc = check_launch("dot_zf");
+  if (rc) return rc;
+  return reduce_partials(partials, (int)g, out, s);
+}
+int cg_update_p_zf(double* p, const float* z, const double* num, const double* den, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p_zf, grid_for(n), kBlock, 0, s, p, z, num, den, n);
+  return check_launch("cg_p_zf");
+}
+int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
+                 const double* den, int64_t n, double* partials, hipStream_t s, double* save, float* r32) {
+  const unsigned g = dot_grid(n);
+  hipLaunchKernelGGL(k_cg_xr, g, kBlock, 0, s, x, r, p, v, num, den, n, partials, save, r32);
   int rc = check_launch("cg_xr");
   if (rc) return rc;
   return (int)g;  // caller reduces g partials

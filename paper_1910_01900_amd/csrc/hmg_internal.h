@@ -356,7 +356,12 @@ int reduce_partials(const double* partials, int nparts, double* out, hipStream_t
 // omega = *num / *den; x += omega p; r -= omega v; *save = *num if save;
 // returns the number of partials of r.r written (>0) or an error (<0)
 int cg_update_xr(double* x, double* r, const double* p, const double* v, const double* num,
-                 const double* den, int64_t n, double* partials, hipStream_t s, double* save = nullptr);
+                 const double* den, int64_t n, double* partials, hipStream_t s, double* save = nullptr,
+                 float* r32 = nullptr);  // r32: r rounded to FP32 as well (may be NULL)
+// *out = x . z with z in FP32, products in FP64 (as vec_dot)
+int vec_dot_zf(const double* x, const float* z, int64_t n, double* partials, double* out, hipStream_t s);
+// p = z + (*num / *den) p with z in FP32 (den NULL: p = z)
+int cg_update_p_zf(double* p, const float* z, const double* num, const double* den, int64_t n, hipStream_t s);
 // p = z + beta p, beta = *num / *den (negated if `negate`)
 int cg_update_p(double* p, const double* z, const double* num, const double* den, int64_t n,
                 hipStream_t s, bool negate = false);
