@@ -22,8 +22,9 @@ def _batch(L, nrhs, seed0):
     return U
 
 
-@pytest.mark.parametrize("k,deformed,nrhs", [(1, False, 3), (2, True, 5), (3, False, 8), (4, True, 3),
-                                             (4, True, 8), (5, False, 2), (6, True, 4), (7, True, 3)])
+@pytest.mark.parametrize("k,deformed,nrhs", [(1, False, 3), (2, True, 5), (2, True, 64), (3, False, 8),
+                                             (4, True, 3), (4, True, 8), (5, False, 2), (5, True, 13),
+                                             (6, True, 4), (7, True, 3)])
 @pytest.mark.parametrize("prec", [hmg.F64, hmg.F32])
 def test_batched_apply_equals_single(k, deformed, nrhs, prec):
     print("batched k=%d deformed=%s nrhs=%d prec=%d" % (k, deformed, nrhs, prec), flush=True)

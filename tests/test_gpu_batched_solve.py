@@ -123,3 +123,21 @@ def test_batch_of_meshes_of_uneven_size_and_degree():
             res = _oracle_residual(om, k, to_np(B[q, :H.n_dofs]), to_np(X[q, :H.n_dofs]))
             print("mesh %s k=%d rhs %d: %d its, oracle residual %.2e" % (nel, k, q, st[q]["iters"], res))
             assert res <= 1.05e-10
+
+
+def test_batched_vcycle_node_sums_beyond_one_grid():
+    """A tall mesh (1 x 1 x 1200 elements, k = 7) whose FE7 level has 8,401
+    node planes: with 8 vectors the planes times vectors exceed one launch
+    grid (65,535), so that level's node sums run vector by vector while the
+    FE3 level's (3,601 planes) run as one launch; the batched V-cycle equals
+    single V-cycles."""
+    hm, _ = meshes((1, 1, 1200), 7, True, bc=(0, 1, 0, 1, 0, 0))
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=hmg.F32, max_rhs=8)
+    print("tall mesh levels:", [(l["space"], l["degree"], l["nel"]) for l in H.levels()], flush=True)
+    B = _block(H, list(range(90, 98)))
+    X = H.vcycle_batched(B)
+    for q in (0, 5, 7):
+        x1 = H.vcycle(B[q, :H.n_dofs].contiguous())
+        d = rel_inf(to_np(X[q, :H.n_dofs]), to_np(x1))
+        print("vector %d: rel diff %.2e" % (q, d))
+        assert d <= 1e-15
