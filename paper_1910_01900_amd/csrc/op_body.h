@@ -76,7 +76,7 @@ constexpr int op_wpe() {
 }
 
 // Whether the epilogue of MODE reads the input vector again (Chebyshev
-// update, u.(A u)) and the wavefront keeps its own input values in LDS
+// update, u.(A u)) and the group keeps its own input values in LDS
 // instead of reading them from memory a second time: only where the extra
 // LDS does not lower residency (workgroups per CU from 160 KB of LDS,
 // against the register limit: WPE for the FP64 curvilinear kernels, about
@@ -773,7 +773,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
     te = a.tau[I.e];
   }
 
-  // ---- own element data into LDS (coalesced per wavefront)
+  // ---- own element data into LDS (coalesced per group)
   if constexpr (early_own) {
 #pragma unroll
     for (int j = 0; j < OWN_PER_LANE; ++j) {
@@ -1051,7 +1051,7 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   if (act) write_line<N, T, 0>(A, t, v);
   group_sync<GL>();
 
-  // ---- coalesced epilogue over the wavefront's elements
+  // ---- coalesced epilogue over the group's elements
   double acc = 0.0;
   for (int idx = lane; idx < nload; idx += GL) {
     const int li = EW == 1 ? 0 : idx / N3;
@@ -1115,7 +1115,7 @@ __device__ __forceinline__ int find_mesh(cptr<MeshEntry<T>> tab, int count, int6
 }
 
 // The chunks of one tile of mesh E; the lane tables of E's degree are in
-// the wavefront's LDS.  The mesh's arguments (vector pointers resolved for
+// the group's LDS.  The mesh's arguments (vector pointers resolved for
 // this launch) are read in place from the constant table where they are
 // used, as kernel arguments are, instead of being held in registers.
 template <int N, typename T, bool CURVED, int MODE>
