@@ -882,24 +882,46 @@ __global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* o
   T acc[kMaxN];  // h-restriction: this lane's output line, summed over the children
 #pragma unroll
   for (int j = 0; j < kMaxN; ++j) acc[j] = 0;
+  // input element of output element eo (child c for the h-restriction)
+  auto in_elem = [&](int64_t eo, int c) -> int64_t {
+    if (a.kind != 1) return eo;
+    const unsigned u = (unsigned)eo;
+    if (RESTRICT) {  // coarse eo -> child c
+      const unsigned r = u / Cx, cz = r / Cy, cy = r - cz * Cy, cx = u - r * Cx;
+      return (2 * cx + (c & 1)) + (int64_t)Fx * ((2 * cy + ((c >> 1) & 1)) + (int64_t)Fy * (2 * cz + (c >> 2)));
+    }
+    // fine eo -> parent
+    const unsigned r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
+    return (ex >> 1) + (int64_t)Cx * ((ey >> 1) + (int64_t)Cy * (ez >> 1));
+  };
   for (int c = 0; c < nchild; ++c) {
     tr_sync();
-    for (int idx = lane; idx < W * ni3; idx += 64) {
-      const int le = idx / ni3, p = idx - le * ni3;
-      const int64_t eo = eb + le;
-      if (eo >= nel_out) continue;
-      int64_t ei = eo;
-      if (a.kind == 1) {
-        const unsigned u = (unsigned)eo;
-        if (RESTRICT) {  // coarse eo -> child c
-          const unsigned r = u / Cx, cz = r / Cy, cy = r - cz * Cy, cx = u - r * Cx;
-          ei = (2 * cx + (c & 1)) + (int64_t)Fx * ((2 * cy + ((c >> 1) & 1)) + (int64_t)Fy * (2 * cz + (c >> 2)));
-        } else {  // fine eo -> parent
-          const unsigned r = u / Fx, ez = r / Fy, ey = r - ez * Fy, ex = u - r * Fx;
-          ei = (ex >> 1) + (int64_t)Cx * ((ey >> 1) + (int64_t)Cy * (ez >> 1));
+    if constexpr (NF > 0 && NC > 0) {
+      // sizes at compile time: all of the lane's loads are issued before the
+      // LDS stores, one memory round trip instead of one per value (values of
+      // elements past the end are zeros whose results are not stored)
+      constexpr int KL = BUF / 64;
+      T v[KL];
+#pragma unroll
+      for (int j = 0; j < KL; ++j) {
+        const int idx = lane + 64 * j;
+        v[j] = T(0);
+        if (idx < W * ni3) {
+          const int le = idx / ni3, p = idx - le * ni3;
+          const int64_t eo = eb + le;
+          if (eo < nel_out) v[j] = in[in_elem(eo, c) * ni3 + p];
         }
       }
-      B[idx] = in[ei * ni3 + p];
+#pragma unroll
+      for (int j = 0; j < KL; ++j)
+        if (lane + 64 * j < W * ni3) B[lane + 64 * j] = v[j];
+    } else {
+      for (int idx = lane; idx < W * ni3; idx += 64) {
+        const int le = idx / ni3, p = idx - le * ni3;
+        const int64_t eo = eb + le;
+        if (eo >= nel_out) continue;
+        B[idx] = in[in_elem(eo, c) * ni3 + p];
+      }
     }
     tr_sync();
     // pass 1, x-lines: (element le, line i1 + ni i2)
