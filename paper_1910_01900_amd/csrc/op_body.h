@@ -785,19 +785,35 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       }
     }
   } else if constexpr (!FE) {
-    for (int idx = lane; idx < nload; idx += GL) {
+    // all of the lane's loads first, then the LDS stores: one memory round
+    // trip (a load-store loop waits for each load in turn)
+    T v[OWN_PER_LANE];
+#pragma unroll
+    for (int j = 0; j < OWN_PER_LANE; ++j) {
+      const int idx = lane + GL * j;
       const int li = EW == 1 ? 0 : idx / N3;
-      const T v = a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)];
-      W0[li * PER + vpos_of<N>(idx - li * N3)] = v;
-      if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = v;
+      v[j] = idx < nload ? a.u[item_offset<N>(a, it0 + li) + (idx - li * N3)] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < OWN_PER_LANE; ++j) {
+      const int idx = lane + GL * j;
+      if (idx < nload) {
+        const int li = EW == 1 ? 0 : idx / N3;
+        W0[li * PER + vpos_of<N>(idx - li * N3)] = v[j];
+        if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) LT[C::LT + idx] = v[j];
+      }
     }
   } else {
     // continuous FE levels: work item = (element, vector), vector fastest,
     // vector r of the input r * ld values after the first; element and node
-    // indices fit in 32 bits (the level's node count is checked on the host)
+    // indices fit in 32 bits (the level's node count is checked on the host).
+    // All of the lane's gathers first, then the LDS stores (one round trip).
     constexpr int k = N - 1;
     const int Mx = a.Nx * k + 1, My = a.Ny * k + 1, Mz = a.Nz * k + 1;
-    for (int idx = lane; idx < nload; idx += GL) {
+    T v[OWN_PER_LANE];
+#pragma unroll
+    for (int j = 0; j < OWN_PER_LANE; ++j) {
+      const int idx = lane + GL * j;
       const int li = EW == 1 ? 0 : idx / N3, p = idx - li * N3;
       const int64_t item = it0 + li;
       const int64_t elv = item_elem(a, item);
@@ -809,7 +825,15 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
       const int m = a.bcmask;
       const bool fixed = (gx == 0 && !(m & 1)) || (gx == Mx - 1 && !(m & 2)) || (gy == 0 && !(m & 4)) ||
                          (gy == My - 1 && !(m & 8)) || (gz == 0 && !(m & 16)) || (gz == Mz - 1 && !(m & 32));
-      W0[li * PER + vpos_of<N>(p)] = fixed ? T(0) : uv[gx + (int64_t)Mx * (gy + (int64_t)My * gz)];
+      v[j] = (idx < nload && !fixed) ? uv[gx + (int64_t)Mx * (gy + (int64_t)My * gz)] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < OWN_PER_LANE; ++j) {
+      const int idx = lane + GL * j;
+      if (idx < nload) {
+        const int li = EW == 1 ? 0 : idx / N3;
+        W0[li * PER + vpos_of<N>(idx - li * N3)] = v[j];
+      }
     }
   }
   group_sync<GL>();
