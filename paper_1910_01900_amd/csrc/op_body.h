@@ -646,6 +646,10 @@ __device__ __forceinline__ void load_lane_tables(const T* tabs, T* LT) {
   T lt[KL];
 #pragma unroll
   for (int i = 0; i < KL; ++i) lt[i] = tabs[lane + GL * i < LTN ? lane + GL * i : 0];
+  // all loads are issued before the first store (otherwise the compiler
+  // sinks the last ones past the stores: a second round trip)
+#pragma unroll
+  for (int i = 0; i < KL; ++i) pin(lt[i]);
 #pragma unroll
   for (int i = 0; i < KL; ++i)
     if (lane + GL * i < LTN) LT[lane + GL * i] = lt[i];
