@@ -470,8 +470,11 @@ __device__ __forceinline__ bool node_fixed(const FeGeo& G, int gx, int gy, int g
 // (each under its own condition), so they are in flight together; the sum
 // then takes them in that order.
 // K > 0: the degree at compile time (constant divisions); 0: G.k.
-template <typename T, int K = 0>
-__device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int gx, int gy, int gz, int* mult) {
+// NA more values (pointers also[a], NULL: none) are loaded after the
+// candidates, in flight with them, into also_v[a].
+template <typename T, int K = 0, int NA = 1>
+__device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int gx, int gy, int gz, int* mult,
+                                             const T* const (&also)[NA], T (&also_v)[NA]) {
   const int k = K ? K : G.k, n = k + 1, n3 = n * n * n;
   const Axis X = node_axis(gx, k, G.Nx), Y = node_axis(gy, k, G.Ny), Z = node_axis(gz, k, G.Nz);
   T v[8];
@@ -490,6 +493,9 @@ __device__ __forceinline__ T node_gather_sum(const FeGeo& G, const T* dg, int gx
       }
     }
   }
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+    if (also[a]) also_v[a] = *also[a];
   T s = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -530,16 +536,13 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
     dg += r * dgs;
   }
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
-  // node-vector loads first, in flight with the gather
-  T x = 0, xo = 0, di = 0, bi = 0;
-  if (MODE == OP_CHEB) {
-    x = u[i];
-    xo = xold ? xold[i] : T(0);  // NULL: x_old = 0
-    di = dinv[i];
-  }
-  if (MODE != OP_APPLY) bi = b[i];
+  // the node-vector values are loaded with the gather (in flight together)
+  const T* const ap[4] = {MODE == OP_CHEB ? u + i : nullptr, MODE == OP_CHEB && xold ? xold + i : nullptr,
+                          MODE == OP_CHEB ? dinv + i : nullptr, MODE != OP_APPLY ? b + i : nullptr};
+  T av[4] = {0, 0, 0, 0};  // x, x_old (NULL: 0), dinv, b
   int mult;
-  T v = node_gather_sum<T, K>(G, dg, gx, gy, gz, &mult);
+  T v = node_gather_sum<T, K, 4>(G, dg, gx, gy, gz, &mult, ap, av);
+  const T x = av[0], xo = av[1], di = av[2], bi = av[3];
   if (node_fixed(G, gx, gy, gz)) v = MODE == OP_CHEB ? x : u[i];
   if (MODE == OP_APPLY) {
     out[i] = v;
@@ -556,11 +559,13 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_c_sum(FeGeo G, const T* d
   const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
   if (gx >= G.Mx || gy >= G.My) return;
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
+  const T* const ap[1] = {add ? fe + i : nullptr};
+  T old[1] = {0};  // the value added to, in flight with the gather
   int mult;
-  T v = node_gather_sum<T, K>(G, dg, gx, gy, gz, &mult);
+  T v = node_gather_sum<T, K, 1>(G, dg, gx, gy, gz, &mult, ap, old);
   if (weight_mult) v /= (T)mult;
   if (node_fixed(G, gx, gy, gz)) v = 0;
-  fe[i] = add ? fe[i] + v : v;
+  fe[i] = add ? old[0] + v : v;
 }
 // dg (+)= E (free * w * fe), one thread per DG value: grid x over the
 // Nx n^3 values of one x-row of elements, y = ey, z = ez, so the element
@@ -578,6 +583,7 @@ __global__ void __launch_bounds__(kBlock) k_c_inject(FeGeo G, const T* fe, T* dg
   const int pz = p / n2, pr = p - pz * n2, py = pr / n, px = pr - py * n;
   const int gx = ex * k + px, gy = ey * k + py, gz = ez * k + pz;
   const int64_t o = (int64_t)(ez * G.Ny + ey) * G.Nx * n3 + i;
+  const T old = add ? dg[o] : T(0);  // in flight with the node value
   T v = 0;
   if (!node_fixed(G, gx, gy, gz)) {
     v = fe[gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz)];
@@ -588,7 +594,7 @@ __global__ void __launch_bounds__(kBlock) k_c_inject(FeGeo G, const T* fe, T* dg
       v /= (T)((1 + sx) * (1 + sy) * (1 + sz));
     }
   }
-  dg[o] = add ? dg[o] + v : v;
+  dg[o] = add ? old + v : v;
 }
 
 template <typename T, int K>
