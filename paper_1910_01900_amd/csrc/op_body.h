@@ -1079,30 +1079,75 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   if (act) write_line<N, T, 0>(A, t, v);
   group_sync<GL>();
 
-  // ---- coalesced epilogue over the group's elements
+  // ---- coalesced epilogue over the group's elements.  The vectors it reads
+  // (residual, Chebyshev update, u.(A u)) are loaded for all of the lane's
+  // values first, then combined and stored: one memory round trip (a
+  // load-store loop waits for each value's loads in turn)
   double acc = 0.0;
-  for (int idx = lane; idx < nload; idx += GL) {
+  constexpr bool KI = keeps_input<N, T, CURVED, FE, MODE>();
+  constexpr bool LX = !FE && (MODE == OP_CHEB || MODE == OP_DOT) && !KI;  // loads u
+  constexpr bool LB = !FE && (MODE == OP_RESID || MODE == OP_CHEB);      // loads b
+  constexpr bool LC = !FE && MODE == OP_CHEB;                            // loads x_old, dinv
+  // offsets of value idx: g in the launch's vectors, gv inside one vector
+  auto offsets = [&](int idx, int64_t& g, int64_t& gv) {
     const int li = EW == 1 ? 0 : idx / N3;
-    const T val = W0[li * PER + vpos_of<N>(idx - li * N3)];
     const int64_t item = it0 + li;
     const int64_t el = item_elem(a, item);
-    const int64_t gv = el * N3 + (idx - li * N3);  // offset inside one vector
+    gv = el * N3 + (idx - li * N3);
     // FE levels write element-local results, n_el n^3 values per vector
-    const int64_t g = gv + (a.nrhs == 1 ? 0 : (item - el * a.nrhs) * (FE ? a.nel * N3 : a.ld));
-    if constexpr (FE || MODE == OP_APPLY) {
-      a.out[g] = val;
-    } else if constexpr (MODE == OP_RESID) {
-      a.out[g] = a.b[g] - val;
-    } else if constexpr (MODE == OP_CHEB) {
-      T x;
-      if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) x = LT[C::LT + idx];  // kept in LDS
-      else x = a.u[g];
-      const T xo = a.xold ? a.xold[g] : T(0);  // NULL: x_old = 0 (second step from a zero start)
-      a.out[g] = x + a.sigma * (x - xo) + a.theta * a.dinv[gv] * (a.b[g] - val);
-    } else {
-      a.out[g] = val;
-      if constexpr (keeps_input<N, T, CURVED, FE, MODE>()) acc += (double)LT[C::LT + idx] * (double)val;
-      else acc += (double)a.u[g] * (double)val;
+    g = gv + (a.nrhs == 1 ? 0 : (item - el * a.nrhs) * (FE ? a.nel * N3 : a.ld));
+  };
+  [[maybe_unused]] T ex[LX ? OWN_PER_LANE : 1], eb[LB ? OWN_PER_LANE : 1], eo[LC ? OWN_PER_LANE : 1],
+      ed[LC ? OWN_PER_LANE : 1];
+  if constexpr (LX || LB || LC) {
+    const T* const xop = a.xold ? a.xold : a.u;  // NULL x_old: loaded from u, used as 0
+#pragma unroll
+    for (int j = 0; j < OWN_PER_LANE; ++j) {
+      const int idx = lane + GL * j;
+      if (idx < nload) {
+        int64_t g, gv;
+        offsets(idx, g, gv);
+        if constexpr (LX) ex[j] = a.u[g];
+        if constexpr (LB) eb[j] = a.b[g];
+        if constexpr (LC) {
+          eo[j] = xop[g];
+          ed[j] = a.dinv[gv];
+        }
+      }
+    }
+  }
+  if constexpr (FE || MODE == OP_APPLY) {  // stores only
+    for (int idx = lane; idx < nload; idx += GL) {
+      const int li = EW == 1 ? 0 : idx / N3;
+      int64_t g, gv;
+      offsets(idx, g, gv);
+      a.out[g] = W0[li * PER + vpos_of<N>(idx - li * N3)];
+    }
+    return acc;
+  }
+#pragma unroll
+  for (int j = 0; j < OWN_PER_LANE; ++j) {
+    const int idx = lane + GL * j;
+    if (idx < nload) {
+      const int li = EW == 1 ? 0 : idx / N3;
+      const T val = W0[li * PER + vpos_of<N>(idx - li * N3)];
+      int64_t g, gv;
+      offsets(idx, g, gv);
+      if constexpr (FE || MODE == OP_APPLY) {
+        a.out[g] = val;
+      } else if constexpr (MODE == OP_RESID) {
+        a.out[g] = eb[j] - val;
+      } else if constexpr (MODE == OP_CHEB) {
+        T x;
+        if constexpr (KI) x = LT[C::LT + idx];  // kept in LDS
+        else x = ex[j];
+        const T xo = a.xold ? eo[j] : T(0);  // NULL: x_old = 0 (second step from a zero start)
+        a.out[g] = x + a.sigma * (x - xo) + a.theta * ed[j] * (eb[j] - val);
+      } else {
+        a.out[g] = val;
+        if constexpr (KI) acc += (double)LT[C::LT + idx] * (double)val;
+        else acc += (double)ex[j] * (double)val;
+      }
     }
   }
   if constexpr (!FE && MODE == OP_DOT)
