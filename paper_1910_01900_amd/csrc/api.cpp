@@ -1392,8 +1392,8 @@ extern "C" int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, doubl
 // The V-cycle and PCG on blocks of nrhs vectors: every level applies its
 // operator to all vectors in one launch (the element geometry read once per
 // element for all of them; the node sums of continuous FE levels follow as
-// one launch); transfers and the coarse solve take the vectors one after
-// another.
+// one launch), and so do the transfers; the coarse solve takes the vectors
+// one after another.
 
 // Alg. 3 on nrhs vectors (vector r at r * ld); tmp: a block like x;
 // fe: the element-local results block of a continuous FE level.
@@ -1499,19 +1499,50 @@ static int coarse_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
   return HMG_OK;
 }
 
+// Transfers of nrhs vectors, one launch per kernel: vector q of the fine
+// block q * ldf values on, of the coarse block q * ldc values on.  sf, sc:
+// element-local blocks of the fine and coarse levels (n_dg values per
+// vector), needed by the p- and h-transfers of continuous FE levels.
+static int restrict_v(const hmg_transfer* T, int nrhs, const void* fine, int64_t ldf, void* coarse, int64_t ldc,
+                      void* sf, void* sc, hipStream_t s) {
+  const hmg_level *F = T->f, *C = T->c;
+  const int pr = F->prec;
+  if (T->kind == 'c') return tr_c_sum(pr, F->mesh, F->k, fine, coarse, 0, 0, s, nrhs, ldf, ldc);
+  const int kind = T->kind == 'h' ? 1 : 0;
+  const double* P1 = T->P1.empty() ? nullptr : T->P1.data();
+  if (!T->fe)
+    return tr_dg_restrict(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, fine, coarse, s, nrhs, ldf, ldc);
+  if (!sf || !sc) return fail(HMG_ERR_INVALID, "internal: FE transfer without element-local blocks");
+  TRY(tr_c_inject(pr, F->mesh, F->k, fine, sf, 1, 0, s, nrhs, ldf, F->n_dg));
+  TRY(tr_dg_restrict(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, sf, sc, s, nrhs, F->n_dg, C->n_dg));
+  return tr_c_sum(pr, C->mesh, C->k, sc, coarse, 0, 0, s, nrhs, C->n_dg, ldc);
+}
+static int prolongate_add_v(const hmg_transfer* T, int nrhs, const void* coarse, int64_t ldc, void* fine, int64_t ldf,
+                            void* sf, void* sc, hipStream_t s) {
+  const hmg_level *F = T->f, *C = T->c;
+  const int pr = F->prec;
+  if (T->kind == 'c') return tr_c_inject(pr, F->mesh, F->k, coarse, fine, 0, 1, s, nrhs, ldc, ldf);
+  const int kind = T->kind == 'h' ? 1 : 0;
+  const double* P1 = T->P1.empty() ? nullptr : T->P1.data();
+  if (!T->fe)
+    return tr_dg_prolongate(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, coarse, fine, 1, s, nrhs, ldc, ldf);
+  if (!sf || !sc) return fail(HMG_ERR_INVALID, "internal: FE transfer without element-local blocks");
+  TRY(tr_c_inject(pr, C->mesh, C->k, coarse, sc, 0, 0, s, nrhs, ldc, C->n_dg));
+  TRY(tr_dg_prolongate(pr, kind, F->n, C->n, F->mesh.N, T->P0.data(), P1, sc, sf, 0, s, nrhs, C->n_dg, F->n_dg));
+  return tr_c_sum(pr, F->mesh, F->k, sf, fine, 1, 1, s, nrhs, F->n_dg, ldf);
+}
+
 // Alg. 2 on level l for the blocks bb(l) -> xb(l), nrhs vectors.
 static int vcycle_v(hmg_hierarchy* H, size_t l, int nrhs, hipStream_t s) {
   hmg_level* L = H->lv[l];
   if (l + 1 == H->lv.size()) return coarse_v(H, l, nrhs, s);
   const int64_t ld = H->ldl[l], ldc = H->ldl[l + 1];
-  const size_t o = ld * L->elem_size(), oc = ldc * H->lv[l + 1]->elem_size();
   TRY(chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 1, H->sb(l), s));
   TRY(residual_v(L, nrhs, ld, H->xb(l), H->rb(l), H->bb(l), H->sb(l), s));
-  for (int q = 0; q < nrhs; ++q)
-    TRY(restrict_(H->tr[l], (const char*)H->rb(l) + q * o, (char*)H->bb(l + 1) + q * oc, s));
+  // the element-local blocks of both levels are free during the transfers
+  TRY(restrict_v(H->tr[l], nrhs, H->rb(l), ld, H->bb(l + 1), ldc, H->sb(l), H->sb(l + 1), s));
   TRY(vcycle_v(H, l + 1, nrhs, s));
-  for (int q = 0; q < nrhs; ++q)
-    TRY(prolongate_add(H->tr[l], (const char*)H->xb(l + 1) + q * oc, (char*)H->xb(l) + q * o, s));
+  TRY(prolongate_add_v(H->tr[l], nrhs, H->xb(l + 1), ldc, H->xb(l), ld, H->sb(l), H->sb(l + 1), s));
   // post-smoothing: the residual block is free again and serves as the third buffer
   return chebyshev_v(L, nrhs, ld, H->bb(l), H->xb(l), H->tb(l), H->ns, H->lmax[l], 0, H->sb(l), s, H->rb(l));
 }

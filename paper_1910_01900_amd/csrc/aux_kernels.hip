@@ -553,11 +553,17 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_fe_sum(FeGeo G, const T* 
   }
 }
 // fe (+)= free * w * E^T dg.  K > 0: the degree at compile time (constant
-// divisions); 0: G.k.
+// divisions); 0: G.k.  Grid z = vector x node plane (vector slowest): vector
+// r of fe starts r * ldf values on, of dg r * ldd values on.
 template <typename T, int K>
-__global__ void __launch_bounds__(kNodeBx * kNodeBy) k_c_sum(FeGeo G, const T* dg, T* fe, int weight_mult, int add) {
-  const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y, gz = blockIdx.z;
+__global__ void __launch_bounds__(kNodeBx * kNodeBy) k_c_sum(FeGeo G, const T* dg, T* fe, int weight_mult, int add,
+                                                             int64_t ldd, int64_t ldf) {
+  const unsigned r = blockIdx.z / (unsigned)G.Mz;
+  const int gx = blockIdx.x * kNodeBx + threadIdx.x, gy = blockIdx.y * kNodeBy + threadIdx.y,
+            gz = (int)(blockIdx.z - r * (unsigned)G.Mz);
   if (gx >= G.Mx || gy >= G.My) return;
+  dg += r * ldd;
+  fe += r * ldf;
   const int64_t i = gx + (int64_t)G.Mx * (gy + (int64_t)G.My * gz);
   const T* const ap[1] = {add ? fe + i : nullptr};
   T old[1] = {0};  // the value added to, in flight with the gather
@@ -572,13 +578,18 @@ __global__ void __launch_bounds__(kNodeBx * kNodeBy) k_c_sum(FeGeo G, const T* d
 // and local node come without run-time divisions (K > 0: the degree at
 // compile time).  A node is shared along an axis when it is the element's
 // first node and the element is not the first, or its last node and the
-// element is not the last.
+// element is not the last.  Grid z = vector x element plane (vector
+// slowest): vector r of fe starts r * ldf values on, of dg r * ldd values on.
 template <typename T, int K>
-__global__ void __launch_bounds__(kBlock) k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add) {
+__global__ void __launch_bounds__(kBlock) k_c_inject(FeGeo G, const T* fe, T* dg, int weight_mult, int add,
+                                                     int64_t ldd, int64_t ldf) {
   const int k = K ? K : G.k, n = k + 1, n2 = n * n, n3 = n2 * n;
   const int i = blockIdx.x * kBlock + threadIdx.x;  // value within the row
   if (i >= G.Nx * n3) return;
-  const int ey = blockIdx.y, ez = blockIdx.z;
+  const unsigned r = blockIdx.z / (unsigned)G.Nz;
+  const int ey = blockIdx.y, ez = (int)(blockIdx.z - r * (unsigned)G.Nz);
+  fe += r * ldf;
+  dg += r * ldd;
   const int ex = i / n3, p = i - ex * n3;
   const int pz = p / n2, pr = p - pz * n2, py = pr / n, px = pr - py * n;
   const int gx = ex * k + px, gy = ey * k + py, gz = ez * k + pz;
@@ -772,47 +783,64 @@ int set_flag(int* flag, int v, hipStream_t s) {
 }
 
 template <typename T, int K>
-static void launch_c(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add,
-                     hipStream_t s) {
+static void launch_c(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add, int nv,
+                     int64_t ldd, int64_t ldf, hipStream_t s) {
   if (inject) {
     const int n3 = (G.k + 1) * (G.k + 1) * (G.k + 1);
-    const dim3 g((unsigned)((G.Nx * n3 + kBlock - 1) / kBlock), (unsigned)G.Ny, (unsigned)G.Nz);
-    hipLaunchKernelGGL((k_c_inject<T, K>), g, dim3(kBlock), 0, s, G, (const T*)src, (T*)dst, weight_mult, add);
+    const dim3 g((unsigned)((G.Nx * n3 + kBlock - 1) / kBlock), (unsigned)G.Ny, (unsigned)(G.Nz * nv));
+    hipLaunchKernelGGL((k_c_inject<T, K>), g, dim3(kBlock), 0, s, G, (const T*)src, (T*)dst, weight_mult, add,
+                       ldd, ldf);
   } else {
-    hipLaunchKernelGGL((k_c_sum<T, K>), node_grid(G), dim3(kNodeBx, kNodeBy), 0, s, G, (const T*)src, (T*)dst,
-                       weight_mult, add);
+    dim3 g = node_grid(G);
+    g.z *= (unsigned)nv;
+    hipLaunchKernelGGL((k_c_sum<T, K>), g, dim3(kNodeBx, kNodeBy), 0, s, G, (const T*)src, (T*)dst, weight_mult,
+                       add, ldd, ldf);
   }
 }
 template <typename T>
-static void launch_c_k(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add,
-                       hipStream_t s) {
+static void launch_c_k(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add, int nv,
+                       int64_t ldd, int64_t ldf, hipStream_t s) {
   switch (G.k) {
-    case 1: launch_c<T, 1>(inject, G, src, dst, weight_mult, add, s); break;
-    case 2: launch_c<T, 2>(inject, G, src, dst, weight_mult, add, s); break;
-    case 3: launch_c<T, 3>(inject, G, src, dst, weight_mult, add, s); break;
-    case 4: launch_c<T, 4>(inject, G, src, dst, weight_mult, add, s); break;
-    case 5: launch_c<T, 5>(inject, G, src, dst, weight_mult, add, s); break;
-    case 6: launch_c<T, 6>(inject, G, src, dst, weight_mult, add, s); break;
-    case 7: launch_c<T, 7>(inject, G, src, dst, weight_mult, add, s); break;
-    default: launch_c<T, 0>(inject, G, src, dst, weight_mult, add, s);
+    case 1: launch_c<T, 1>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    case 2: launch_c<T, 2>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    case 3: launch_c<T, 3>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    case 4: launch_c<T, 4>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    case 5: launch_c<T, 5>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    case 6: launch_c<T, 6>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    case 7: launch_c<T, 7>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s); break;
+    default: launch_c<T, 0>(inject, G, src, dst, weight_mult, add, nv, ldd, ldf, s);
   }
 }
+// The vectors go on grid z (planes x vectors): as many per launch as the
+// 65535 limit of the grid allows.
+template <typename T>
+static void launch_c_v(bool inject, const FeGeo& G, const void* src, void* dst, int weight_mult, int add, int nrhs,
+                       int64_t ldd, int64_t ldf, hipStream_t s) {
+  const int64_t planes = inject ? G.Nz : G.Mz;
+  const int per = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, 65535 / planes));
+  const int64_t lds = inject ? ldf : ldd, ldt = inject ? ldd : ldf;  // source, destination strides
+  for (int r = 0; r < nrhs; r += per)
+    launch_c_k<T>(inject, G, (const T*)src + r * lds, (T*)dst + r * ldt, weight_mult, add, std::min(per, nrhs - r),
+                  ldd, ldf, s);
+}
 int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int weight_mult, int add,
-                hipStream_t s) {
+                hipStream_t s, int nrhs, int64_t ld_fe, int64_t ld_dg) {
   FeGeo G = fe_geo(m, k);
   const int64_t n3 = (int64_t)(k + 1) * (k + 1) * (k + 1);
+  if (nrhs < 1) return HMG_OK;
   if (m.n_el() * n3 >= (int64_t)1 << 31) return fail(HMG_ERR_UNSUPPORTED, "DG vector too long for the injection kernel");
   if (G.Ny > 65535 || G.Nz > 65535) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for the injection grid");
-  if (prec == HMG_F64) launch_c_k<double>(true, G, fe, dg, weight_mult, add, s);
-  else launch_c_k<float>(true, G, fe, dg, weight_mult, add, s);
+  if (prec == HMG_F64) launch_c_v<double>(true, G, fe, dg, weight_mult, add, nrhs, ld_dg, ld_fe, s);
+  else launch_c_v<float>(true, G, fe, dg, weight_mult, add, nrhs, ld_dg, ld_fe, s);
   return check_launch("c_inject");
 }
 int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
-             hipStream_t s) {
+             hipStream_t s, int nrhs, int64_t ld_dg, int64_t ld_fe) {
   FeGeo G = fe_geo(m, k);
+  if (nrhs < 1) return HMG_OK;
   if (G.Mz > 65535) return fail(HMG_ERR_UNSUPPORTED, "FE level too large for the node grid");
-  if (prec == HMG_F64) launch_c_k<double>(false, G, dg, fe, weight_mult, add, s);
-  else launch_c_k<float>(false, G, dg, fe, weight_mult, add, s);
+  if (prec == HMG_F64) launch_c_v<double>(false, G, dg, fe, weight_mult, add, nrhs, ld_dg, ld_fe, s);
+  else launch_c_v<float>(false, G, dg, fe, weight_mult, add, nrhs, ld_dg, ld_fe, s);
   return check_launch("c_sum");
 }
 
@@ -837,7 +865,8 @@ struct TrArgs {
 //   out[o0, o1, o2] = sum_i2 M2[o2, i2] T2[o0, o1, i2]   (x fastest)
 // W fills the LDS buffers (kTrBytes per buffer); the h-restriction adds the
 // 8 children in a fixed order in registers (one output line per lane).  No
-// workgroup barrier: four independent wavefronts per workgroup.
+// workgroup barrier: four independent wavefronts per workgroup.  Grid y is
+// the vector: vector r of in starts r * ldi values on, of out r * ldo.
 constexpr int kTrBytes = 4096;  // bytes per LDS buffer and wavefront
 
 __device__ __forceinline__ void tr_sync() {
@@ -849,8 +878,11 @@ __device__ __forceinline__ void tr_sync() {
 // NF, NC > 0: the node counts at compile time (unrolled 1-D products, the
 // line arrays in registers); 0: taken from the arguments.
 template <typename T, bool RESTRICT, int NF, int NC>
-__global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* out, int add) {
+__global__ void __launch_bounds__(256) k_transfer(TrArgs<T> a, const T* in, T* out, int add, int64_t ldi,
+                                                  int64_t ldo) {
   constexpr int BUF = kTrBytes / (int)sizeof(T);
+  in += blockIdx.y * ldi;
+  out += blockIdx.y * ldo;
   __shared__ T buf[4][2][BUF];
   __shared__ T Pl[4][2 * kMaxN * kMaxN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1014,51 +1046,56 @@ static TrArgs<T> tr_args(int kind, int nf, int nc, const int Nf[3], const double
 // hierarchies use (p: n -> n-1, n -> floor(k/2)+1, n -> 2; h and c: n -> n),
 // the generic kernel otherwise.
 template <typename T, bool R>
-static void launch_transfer(int nf, int nc, unsigned g, const TrArgs<T>& a, const T* in, T* out, int add,
-                            hipStream_t s) {
-#define HMG_TR(F, C)                                                                  \
-  if (nf == F && nc == C) {                                                           \
-    hipLaunchKernelGGL((k_transfer<T, R, F, C>), g, 256, 0, s, a, in, out, add); \
-    return;                                                                           \
+static void launch_transfer(int nf, int nc, unsigned g, const TrArgs<T>& a, const T* in, T* out, int add, int nrhs,
+                            int64_t ldi, int64_t ldo, hipStream_t s) {
+  const dim3 grid(g, (unsigned)nrhs);
+#define HMG_TR(F, C)                                                                                    \
+  if (nf == F && nc == C) {                                                                             \
+    hipLaunchKernelGGL((k_transfer<T, R, F, C>), grid, 256, 0, s, a, in, out, add, ldi, ldo); \
+    return;                                                                                             \
   }
   HMG_TR(2, 2) HMG_TR(3, 3) HMG_TR(4, 4) HMG_TR(5, 5) HMG_TR(6, 6) HMG_TR(7, 7) HMG_TR(8, 8)
   HMG_TR(3, 2) HMG_TR(4, 3) HMG_TR(5, 4) HMG_TR(6, 5) HMG_TR(7, 6) HMG_TR(8, 7)
   HMG_TR(4, 2) HMG_TR(5, 3) HMG_TR(6, 3) HMG_TR(7, 4) HMG_TR(8, 4)
   HMG_TR(5, 2) HMG_TR(6, 2) HMG_TR(7, 2) HMG_TR(8, 2)
 #undef HMG_TR
-  hipLaunchKernelGGL((k_transfer<T, R, 0, 0>), g, 256, 0, s, a, in, out, add);
+  hipLaunchKernelGGL((k_transfer<T, R, 0, 0>), grid, 256, 0, s, a, in, out, add, ldi, ldo);
 }
 
 int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
-                     const double* P1, const void* coarse, void* fine, int add, hipStream_t s) {
+                     const double* P1, const void* coarse, void* fine, int add, hipStream_t s, int nrhs,
+                     int64_t ld_c, int64_t ld_f) {
   const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
-  if (nel_f == 0) return HMG_OK;
+  if (nel_f == 0 || nrhs < 1) return HMG_OK;
+  if (nrhs > 65535) return fail(HMG_ERR_UNSUPPORTED, "too many vectors for one transfer launch");
   if (nel_f >= ((int64_t)1 << 31)) return fail(HMG_ERR_UNSUPPORTED, "too many elements for one transfer launch");
   if (prec == HMG_F64) {
     auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1, false);
     const unsigned g = (unsigned)((nel_f + 4 * a.W - 1) / (4 * a.W));
-    launch_transfer<double, false>(nf, nc, g, a, (const double*)coarse, (double*)fine, add, s);
+    launch_transfer<double, false>(nf, nc, g, a, (const double*)coarse, (double*)fine, add, nrhs, ld_c, ld_f, s);
   } else {
     auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1, false);
     const unsigned g = (unsigned)((nel_f + 4 * a.W - 1) / (4 * a.W));
-    launch_transfer<float, false>(nf, nc, g, a, (const float*)coarse, (float*)fine, add, s);
+    launch_transfer<float, false>(nf, nc, g, a, (const float*)coarse, (float*)fine, add, nrhs, ld_c, ld_f, s);
   }
   return check_launch("tr_prolong");
 }
 int tr_dg_restrict(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
-                   const double* P1, const void* fine, void* coarse, hipStream_t s) {
+                   const double* P1, const void* fine, void* coarse, hipStream_t s, int nrhs, int64_t ld_f,
+                   int64_t ld_c) {
   const int64_t nel_f = (int64_t)Nf[0] * Nf[1] * Nf[2];
   const int64_t nel_c = kind == 1 ? nel_f / 8 : nel_f;
-  if (nel_c == 0) return HMG_OK;
+  if (nel_c == 0 || nrhs < 1) return HMG_OK;
+  if (nrhs > 65535) return fail(HMG_ERR_UNSUPPORTED, "too many vectors for one transfer launch");
   if (nel_f >= ((int64_t)1 << 31)) return fail(HMG_ERR_UNSUPPORTED, "too many elements for one transfer launch");
   if (prec == HMG_F64) {
     auto a = tr_args<double>(kind, nf, nc, Nf, P0, P1, true);
     const unsigned g = (unsigned)((nel_c + 4 * a.W - 1) / (4 * a.W));
-    launch_transfer<double, true>(nf, nc, g, a, (const double*)fine, (double*)coarse, 0, s);
+    launch_transfer<double, true>(nf, nc, g, a, (const double*)fine, (double*)coarse, 0, nrhs, ld_f, ld_c, s);
   } else {
     auto a = tr_args<float>(kind, nf, nc, Nf, P0, P1, true);
     const unsigned g = (unsigned)((nel_c + 4 * a.W - 1) / (4 * a.W));
-    launch_transfer<float, true>(nf, nc, g, a, (const float*)fine, (float*)coarse, 0, s);
+    launch_transfer<float, true>(nf, nc, g, a, (const float*)fine, (float*)coarse, 0, nrhs, ld_f, ld_c, s);
   }
   return check_launch("tr_restrict");
 }

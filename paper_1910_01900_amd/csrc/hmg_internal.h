@@ -391,19 +391,22 @@ int cg_update_p_zf_b(double* p, const float* z, const double* num, const double*
 int cg_update_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld, int nrhs,
                   const int* active, bool negate, hipStream_t s);
 
-// transfers (element-local tensor-product kernels)
+// transfers (element-local tensor-product kernels); nrhs vectors in one
+// launch, vector r of each block r * ld_* values after the first
 // DG p / h: fine += P coarse, coarse = P^T fine
 int tr_dg_prolongate(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
-                     const double* P1, const void* coarse, void* fine, int add, hipStream_t s);
+                     const double* P1, const void* coarse, void* fine, int add, hipStream_t s, int nrhs = 1,
+                     int64_t ld_c = 0, int64_t ld_f = 0);
 int tr_dg_restrict(int prec, int kind, int nf, int nc, const int Nf[3], const double* P0,
-                   const double* P1, const void* fine, void* coarse, hipStream_t s);
+                   const double* P1, const void* fine, void* coarse, hipStream_t s, int nrhs = 1,
+                   int64_t ld_f = 0, int64_t ld_c = 0);
 // c-transfers between the FE vector and a DG-layout vector on the same mesh
 //   inject: dg = E(free * w * fe) with w = 1 or 1/mult;  add: dg += ... if add
 //   sum   : fe (+)= free * w * E^T dg
 int tr_c_inject(int prec, const Mesh& m, int k, const void* fe, void* dg, int weight_mult,
-                int add, hipStream_t s);
+                int add, hipStream_t s, int nrhs = 1, int64_t ld_fe = 0, int64_t ld_dg = 0);
 int tr_c_sum(int prec, const Mesh& m, int k, const void* dg, void* fe, int weight_mult, int add,
-             hipStream_t s);
+             hipStream_t s, int nrhs = 1, int64_t ld_dg = 0, int64_t ld_fe = 0);
 // FE operator node sum with a mode (see launch_operator) for nrhs vectors
 // in one launch: vector r of u, out, b, xold starts r * ld values after the
 // first, its element-local results r * n_dg values after the first

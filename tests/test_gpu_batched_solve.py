@@ -63,10 +63,15 @@ def test_batched_solve_of_the_k7_workload_at_reduced_size():
         assert res <= 1.05e-10 + allow
 
 
-@pytest.mark.parametrize("mg_prec", [hmg.F64, hmg.F32])
-def test_batched_vcycle_equals_single(mg_prec):
+@pytest.mark.parametrize("strategy,mg_prec", [("cph", hmg.F64), ("cph", hmg.F32), ("ph", hmg.F32),
+                                              ("hcp", hmg.F64)])
+def test_batched_vcycle_equals_single(strategy, mg_prec):
+    """The batched V-cycle (operators and transfers on all vectors in one
+    launch) against single V-cycles: c-, FE p- and FE h-transfers (cph), DG
+    p- and h-transfers (ph), DG h before c (hcp)."""
     hm, _ = meshes((4, 4, 2), 4, True)
-    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=mg_prec, max_rhs=3)
+    H = hmg.Hierarchy(hm, strategy, pseq=1, h_min=1, mg_prec=mg_prec, max_rhs=3)
+    print("levels:", [(l["space"], l["degree"], l["nel"]) for l in H.levels()], flush=True)
     B = _block(H, [65, 66, 67])
     X = H.vcycle_batched(B)
     for q in range(3):
@@ -128,8 +133,9 @@ def test_batch_of_meshes_of_uneven_size_and_degree():
 def test_batched_vcycle_node_sums_beyond_one_grid():
     """A tall mesh (1 x 1 x 1200 elements, k = 7) whose FE7 level has 8,401
     node planes: with 8 vectors the planes times vectors exceed one launch
-    grid (65,535), so that level's node sums run vector by vector while the
-    FE3 level's (3,601 planes) run as one launch; the batched V-cycle equals
+    grid (65,535), so that level's node sums run vector by vector and its
+    c-restriction sums in two launches (7 vectors, then 1), while the FE3
+    level's (3,601 planes) run as one launch; the batched V-cycle equals
     single V-cycles."""
     hm, _ = meshes((1, 1, 1200), 7, True, bc=(0, 1, 0, 1, 0, 0))
     H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=hmg.F32, max_rhs=8)
