@@ -286,8 +286,9 @@ int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, dou
  * the V-cycle as one block: every operator application of the smoothers,
  * the residuals and the outer CG takes all vectors in one launch, reading
  * the element geometry once for all of them (on continuous FE levels the
- * node sums of all vectors follow as one launch); transfers and the coarse
- * solve take the vectors one after another.  A level whose element count
+ * node sums of all vectors follow as one launch), and so does each grid
+ * transfer kernel; the coarse solve takes the vectors one after another.
+ * A level whose element count
  * times nrhs reaches 2^31 returns HMG_ERR_UNSUPPORTED.
  * set_max_rhs (1..64, default 1) reserves workspace for up to max_rhs
  * vectors and must precede hmg_hierarchy_query and _bind.
@@ -296,7 +297,8 @@ int hmg_pcg_solve(hmg_hierarchy* H, const double* b, double* x, double rtol, dou
  * hmg_pcg_solve_batched: x holds the start vectors on entry; each vector
  * stops, and is left unchanged from then on, when its own ||r||/||r_0|| <=
  * rtol or ||r|| <= atol; the call returns when all have stopped or after
- * maxit iterations (HMG_NOT_CONVERGED if any has not).  stats (nrhs
+ * maxit iterations (HMG_NOT_CONVERGED if any has not).  After
+ * HMG_ERR_NONFINITE the contents of x are unspecified.  stats (nrhs
  * entries, may be NULL) as for hmg_pcg_solve.  Blocks.  The learned coarse
  * solve is not available here (HMG_ERR_UNSUPPORTED).  nrhs must not
  * exceed max_rhs; with max_rhs = 1 (nothing reserved; nrhs up to 64) or

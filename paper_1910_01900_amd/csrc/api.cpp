@@ -1609,7 +1609,12 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
   }
   const hmg_level* A = H->fine64;
   const int64_t n = A->n_dofs, L = H->ld64;
-  double *B = H->cgb(0), *X = H->cgb(1), *R = H->cgb(2), *P = H->cgb(3), *V = H->cgb(4), *Z = H->cgb(5);
+  // the caller's blocks serve directly when their stride is the internal one
+  // (x is then updated in place); otherwise they are copied in and x out
+  const bool own = ld != L;
+  const double* const B = own ? H->cgb(0) : b;
+  double* const X = own ? H->cgb(1) : x;
+  double *R = H->cgb(2), *P = H->cgb(3), *V = H->cgb(4), *Z = H->cgb(5);
   // scalars per vector: 0 previous delta, 1 delta = r.z, 2 p.Ap, 3 r.r, 4 z.Ap
   double *s0 = H->scalb(0), *s1 = H->scalb(1), *s2 = H->scalb(2), *s3 = H->scalb(3), *s4 = H->scalb(4);
   double* part = H->partb();
@@ -1632,8 +1637,10 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
     HMG_HIP(hipStreamSynchronize(s));
     return HMG_OK;
   };
-  TRY(vec_convert_b(HMG_F64, b, ld, HMG_F64, B, L, n, nrhs, s));
-  TRY(vec_convert_b(HMG_F64, x, ld, HMG_F64, X, L, n, nrhs, s));
+  if (own) {
+    TRY(vec_convert_b(HMG_F64, b, ld, HMG_F64, H->cgb(0), L, n, nrhs, s));
+    TRY(vec_convert_b(HMG_F64, x, ld, HMG_F64, X, L, n, nrhs, s));
+  }
   TRY(launch_operator_batched(A, OP_RESID, nrhs, L, X, R, B, nullptr, 0, 0, nullptr, s));
   TRY(vec_dot_b(R, R, n, L, nrhs, part, s3, s));
   HMG_HIP(hipMemcpyAsync(hs.data(), s3, nrhs * 8, hipMemcpyDeviceToHost, s));
@@ -1695,7 +1702,7 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
       stats[q].iters = it;
       stats[q].rn = nr;
       if (!(hs[q] > 0)) {
-        TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
+        if (own) TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
         return finish(fail(HMG_ERR_BREAKDOWN, "p^T A p <= 0: operator not SPD"));
       }
       if (!std::isfinite(nr)) return finish(fail(HMG_ERR_NONFINITE, "residual is not finite"));
@@ -1707,7 +1714,7 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
     }
     if (changed && n_active > 0) TRY(upload_active());
   }
-  TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
+  if (own) TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
   HMG_HIP(hipStreamSynchronize(s));
   return finish(n_active > 0 ? HMG_NOT_CONVERGED : HMG_OK);
 }

@@ -100,6 +100,27 @@ def test_batched_solve_stops_each_vector_on_its_own():
     assert bool((X[:, H.n_dofs:] == 0).all())
 
 
+def test_batched_solve_of_blocks_with_a_wider_stride():
+    """Blocks whose row stride is the solver's own are solved in place,
+    others are copied in and out: both give the same iterates bit for bit,
+    and the wider block's padding is left alone."""
+    hm, _ = meshes((4, 4, 2), 4, True)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=hmg.F32, max_rhs=3)
+    B = _block(H, [76, 77, 78])
+    X, st = H.solve_batched(B, rtol=1e-10)
+    ld = B.shape[1] + 64
+    Bw = torch.zeros(3, ld, dtype=torch.float64, device="cuda")
+    Xw = torch.full((3, ld), 7.0, dtype=torch.float64, device="cuda")
+    Bw[:, :H.n_dofs] = B[:, :H.n_dofs]
+    Xw[:, :H.n_dofs] = 0
+    Xw, stw = H.solve_batched(Bw, Xw, rtol=1e-10)
+    for q in range(3):
+        print("vector %d: iterations %d / %d" % (q, st[q]["iters"], stw[q]["iters"]))
+        assert st[q]["iters"] == stw[q]["iters"]
+        assert torch.equal(X[q, :H.n_dofs], Xw[q, :H.n_dofs])
+    assert bool((Xw[:, H.n_dofs:] == 7.0).all())
+
+
 def test_batched_solve_argument_errors():
     hm, _ = meshes((4, 4, 4), 2, False)
     H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, max_rhs=2)
