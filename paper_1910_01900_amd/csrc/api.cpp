@@ -701,7 +701,7 @@ struct hmg_hierarchy {
   std::vector<int64_t> ldl;
   std::vector<size_t> off_bb, off_xb, off_rb, off_tb, off_sb;  // off_sb: FE element-local results
   int64_t ld64 = 0;
-  size_t off_cgb = 0, off_partb = 0, off_scalb = 0, off_actb = 0;
+  size_t off_cgb = 0, off_partb = 0, off_scalb = 0, off_actb = 0, off_dotb = 0;
   char* ws = nullptr;
   bool bound = false;
   // launch graphs (hmg_hierarchy_set_graph): one PCG iteration and one
@@ -747,6 +747,9 @@ struct hmg_hierarchy {
   double* partb() const { return (double*)(ws + off_partb); }
   double* scalb(int i) const { return (double*)(ws + off_scalb) + (size_t)i * max_rhs; }  // 0..5
   int* actb() const { return (int*)(ws + off_actb); }
+  // per-item partials of p.(A p) from the several-vector FP64 apply (degree 6
+  // and 7), n_el * max_rhs values; NULL where the apply cannot write them
+  double* dotb() const { return fine64->n >= 7 ? (double*)(ws + off_dotb) : nullptr; }
   // FP64 right-hand side and solution of the iterative coarse solve when the
   // V-cycle runs in FP32 (the coarse solve itself is an FP64 step)
   double* cb64() const { return (double*)(ws + off_c64v); }
@@ -919,6 +922,7 @@ static void hierarchy_layout(hmg_hierarchy* H) {
     H->off_partb = take(m * kPartialsB * 8);
     H->off_scalb = take(6 * m * 8);
     H->off_actb = take(m * sizeof(int));
+    H->off_dotb = take(H->fine64->n >= 7 ? m * (size_t)H->fine64->n_el * 8 : 0);
   }
   H->ws_bytes = off;
 }
@@ -1688,8 +1692,13 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
         }
       }
     }
-    TRY(launch_operator_batched(A, OP_APPLY, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s));
-    TRY(vec_dot_b(P, V, n, L, nrhs, part, s2, s));
+    if (double* const db = H->dotb()) {  // p.(A p) summed per work item by the apply
+      TRY(launch_operator_batched(A, OP_DOT, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s, db));
+      TRY(reduce_strided(db, A->n_el, nrhs, s2, s));
+    } else {
+      TRY(launch_operator_batched(A, OP_APPLY, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s));
+      TRY(vec_dot_b(P, V, n, L, nrhs, part, s2, s));
+    }
     TRY(cg_update_xr_b(X, R, P, V, s1, s2, n, L, nrhs, part, s3, s0, act, s, r32, l32));
     HMG_HIP(hipMemcpyAsync(hs.data(), s2, nrhs * 8, hipMemcpyDeviceToHost, s));
     HMG_HIP(hipMemcpyAsync(hs.data() + nrhs, s3, nrhs * 8, hipMemcpyDeviceToHost, s));

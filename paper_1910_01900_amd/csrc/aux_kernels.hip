@@ -74,6 +74,15 @@ __global__ void k_reduce(const double* partials, int np, double* out) {
   double s = block_reduce(acc);
   if (threadIdx.x == 0) *out = s;
 }
+// Block r: out[r] = sum over j < n of partials[r + nrhs * j] (per-thread
+// sums in a fixed order, then the block's fixed tree).
+__global__ void k_reduce_strided(const double* partials, int64_t n, int nrhs, double* out) {
+  const int r = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) acc += partials[r + (int64_t)nrhs * j];
+  double s = block_reduce(acc);
+  if (threadIdx.x == 0) out[r] = s;
+}
 // SplitMix64 (Steele, Lea, Flood 2014): output i = mix(seed + (i+1)*golden)
 template <typename T>
 __global__ void k_splitmix(uint64_t seed, T* x, int64_t n) {
@@ -197,6 +206,11 @@ static unsigned dot_grid(int64_t n) {
 int reduce_partials(const double* partials, int np, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, 1, 1024, 0, s, partials, np, out);
   return check_launch("reduce");
+}
+int reduce_strided(const double* partials, int64_t n, int nrhs, double* out, hipStream_t s) {
+  if (nrhs < 1) return HMG_OK;
+  hipLaunchKernelGGL(k_reduce_strided, nrhs, 1024, 0, s, partials, n, nrhs, out);
+  return check_launch("reduce_strided");
 }
 int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
             hipStream_t s) {

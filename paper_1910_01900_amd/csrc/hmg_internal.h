@@ -300,10 +300,13 @@ int fused_occupancy(int prec, int mode);
 // OP_DOT : out = A u, partials[blk] = sum u.(A u) (for p^T A p).
 int launch_operator(const hmg_level* L, int mode, const void* u, void* out, const void* b,
                     const void* xold, double sigma, double theta, int* nparts, hipStream_t s);
-// The same for nrhs vectors at once (OP_APPLY, OP_RESID, OP_CHEB): vector r
-// of u, out, b, xold starts r*ld values after the first; dinv is shared.
-// Continuous FE levels with nrhs > 1 need fe_results, a block of nrhs *
-// n_dg values of the level precision for the element-local results.
+// The same for nrhs vectors at once: vector r of u, out, b, xold starts
+// r*ld values after the first; dinv is shared.  Continuous FE levels with
+// nrhs > 1 need fe_results, a block of nrhs * n_dg values of the level
+// precision for the element-local results.  OP_DOT with nrhs > 1 (DG levels
+// of degree 6 and 7: a group is one wavefront holding one element) writes
+// one partial of u.(A u) per work item (element e, vector r) at e * nrhs + r
+// of fe_results, a block of n_el * nrhs doubles (reduce_strided sums them).
 int launch_operator_batched(const hmg_level* L, int mode, int nrhs, int64_t ld, const void* u, void* out,
                             const void* b, const void* xold, double sigma, double theta, int* nparts,
                             hipStream_t s, void* fe_results = nullptr);
@@ -352,6 +355,8 @@ int vec_convert_gated(int from, const void* x, int to, void* y, int64_t n, const
 int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
             hipStream_t s);
 int reduce_partials(const double* partials, int nparts, double* out, hipStream_t s);
+// out[r] = sum over j < n of partials[r + nrhs * j], r < nrhs (fixed order)
+int reduce_strided(const double* partials, int64_t n, int nrhs, double* out, hipStream_t s);
 // CG updates with device scalars (all FP64): see kernels for formulas
 // omega = *num / *den; x += omega p; r -= omega v; *save = *num if save;
 // returns the number of partials of r.r written (>0) or an error (<0)

@@ -25,7 +25,12 @@ op_kernel(const OpArgs<T> a) {
   load_lane_tables<T, C::LT, C::GL>(a.tabs, W0 + C::EW * C::PER);
   const double acc = op_items<N, T, CURVED, FE, MODE>(a, it0, count - grp * C::EW, W0);
   if constexpr (!FE && MODE == OP_DOT)
-    if ((threadIdx.x & 63) == 0) a.partials[(int64_t)blockIdx.x * C::WAVES + (threadIdx.x >> 6)] = acc;
+    if ((threadIdx.x & 63) == 0) {
+      if (a.nrhs == 1)  // one partial per wavefront
+        a.partials[(int64_t)blockIdx.x * C::WAVES + (threadIdx.x >> 6)] = acc;
+      else if (it0 < a.nel * a.nrhs)  // one element per group: one partial per work item
+        a.partials[it0] = acc;
+    }
 }
 
 // ------------------------------------------------------------------ multi mesh
@@ -101,8 +106,15 @@ static int run_op(const hmg_level* L, int mode, const void* u, void* out, const 
     return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: at most 64, and fewer than 2^31 element-vectors");
   const int64_t nb = nrhs == 1 ? (int64_t)a.rowchunks * a.Ny * a.Nz : (L->n_el * nrhs + C::EB - 1) / C::EB;
   if (nb > INT32_MAX / C::WAVES) return fail(HMG_ERR_UNSUPPORTED, "mesh too large for one launch");
-  // one partial per wavefront, within the level's partials buffer
-  if (nparts) {
+  if (!FE && mode == OP_DOT && nrhs > 1) {
+    // one partial per work item (element, vector), item e * nrhs + r, into
+    // the caller's block (scratch) of n_el * nrhs values: needs groups of one
+    // wavefront holding one element
+    if (C::EW != 1 || C::GL != 64 || !scratch)
+      return fail(HMG_ERR_UNSUPPORTED, "several vectors with u.(A u): degree 6 or 7 and a partials block");
+    a.partials = (double*)scratch;
+    if (nparts) *nparts = (int)(L->n_el * nrhs);
+  } else if (nparts) {  // one partial per wavefront, within the level's partials buffer
     if (nb * C::WAVES > op_partials_capacity(a.Nx, a.Ny, a.Nz))
       return fail(HMG_ERR_WORKSPACE, "operator partial sums exceed their buffer");
     *nparts = (int)nb * C::WAVES;
@@ -246,7 +258,8 @@ static int launch_any(const hmg_level* L, int mode, int nrhs, int64_t ld, const 
                       const void* xold, double sigma, double theta, int* nparts, const int* skip, void* sc,
                       hipStream_t s) {
   if (L->n_el == 0 || nrhs == 0) return HMG_OK;
-  if (nrhs > 1 && mode == OP_DOT) return fail(HMG_ERR_UNSUPPORTED, "several vectors at once: apply/residual/Chebyshev only");
+  if (nrhs > 1 && mode == OP_DOT && (L->space != HMG_DG || !sc))
+    return fail(HMG_ERR_UNSUPPORTED, "several vectors with u.(A u): DG levels and a partials block only");
   if (nrhs > 1 && L->space != HMG_DG && !sc)
     return fail(HMG_ERR_UNSUPPORTED, "several vectors at once on a continuous FE level need a results block");
   switch (L->n) {
