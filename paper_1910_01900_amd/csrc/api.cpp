@@ -1619,8 +1619,9 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
   const double* const B = own ? H->cgb(0) : b;
   double* const X = own ? H->cgb(1) : x;
   double *R = H->cgb(2), *P = H->cgb(3), *V = H->cgb(4), *Z = H->cgb(5);
-  // scalars per vector: 0 previous delta, 1 delta = r.z, 2 p.Ap, 3 r.r, 4 z.Ap
+  // scalars per vector: 0 previous delta, 1 delta = r.z, 2 p.Ap, 3 r.r, 4 z.Ap, 5 omega
   double *s0 = H->scalb(0), *s1 = H->scalb(1), *s2 = H->scalb(2), *s3 = H->scalb(3), *s4 = H->scalb(4);
+  double* const alpha = H->scalb(5);  // omega of each vector's deferred x step
   double* part = H->partb();
   int* act = H->actb();
   std::vector<hmg_solve_stats> stats(nrhs, hmg_solve_stats{0, 0, 0, 0, 0});
@@ -1680,7 +1681,8 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
       if (zf) {
         TRY(vcycle_v(H, 0, nrhs, s));  // the right-hand side block holds r in FP32 (cg_update_xr_b)
         TRY(vec_dot_zf_b(R, z32, n, L, l32, nrhs, part, s1, s));
-        TRY(cg_update_p_zf_b(P, z32, s1, s0, n, L, l32, nrhs, act, s));
+        // also takes the last update's deferred step x += alpha p
+        TRY(cg_update_p_zf_b(P, z32, s1, s0, n, L, l32, nrhs, act, s, X, alpha));
       } else {
         TRY(precondition_v(H, nrhs, R, L, Z, L, s));
         TRY(vec_dot_b(R, Z, n, L, nrhs, part, s1, s));
@@ -1699,18 +1701,24 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
       TRY(launch_operator_batched(A, OP_APPLY, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s));
       TRY(vec_dot_b(P, V, n, L, nrhs, part, s2, s));
     }
-    TRY(cg_update_xr_b(X, R, P, V, s1, s2, n, L, nrhs, part, s3, s0, act, s, r32, l32));
+    // with the FP32 z the step x += alpha p waits for the next direction
+    // update, which reads p anyway (one pass over p fewer)
+    TRY(cg_update_xr_b(zf ? nullptr : X, R, P, V, s1, s2, n, L, nrhs, part, s3, s0, act, s, r32, l32, alpha));
     HMG_HIP(hipMemcpyAsync(hs.data(), s2, nrhs * 8, hipMemcpyDeviceToHost, s));
     HMG_HIP(hipMemcpyAsync(hs.data() + nrhs, s3, nrhs * 8, hipMemcpyDeviceToHost, s));
     HMG_HIP(hipStreamSynchronize(s));
     ++it;
     bool changed = false;
+    uint64_t live = 0, done = 0;  // vectors of this update; those that stop now
+    for (int q = 0; q < nrhs; ++q)
+      if (active[q]) live |= 1ull << q;
     for (int q = 0; q < nrhs; ++q) {
       if (!active[q]) continue;
       const double nr = std::sqrt(hs[nrhs + q]);
       stats[q].iters = it;
       stats[q].rn = nr;
       if (!(hs[q] > 0)) {
+        if (zf) TRY(cg_step_x_b(X, P, alpha, n, L, nrhs, live, s));
         if (own) TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
         return finish(fail(HMG_ERR_BREAKDOWN, "p^T A p <= 0: operator not SPD"));
       }
@@ -1719,9 +1727,17 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
         active[q] = 0;
         --n_active;
         changed = true;
+        done |= 1ull << q;
       }
     }
+    if (zf) TRY(cg_step_x_b(X, P, alpha, n, L, nrhs, done, s));  // their last step
     if (changed && n_active > 0) TRY(upload_active());
+  }
+  if (zf && it > 0) {  // the last step of the vectors still running (maxit reached)
+    uint64_t live = 0;
+    for (int q = 0; q < nrhs; ++q)
+      if (active[q]) live |= 1ull << q;
+    TRY(cg_step_x_b(X, P, alpha, n, L, nrhs, live, s));
   }
   if (own) TRY(vec_convert_b(HMG_F64, X, L, HMG_F64, x, ld, n, nrhs, s));
   HMG_HIP(hipStreamSynchronize(s));

@@ -288,17 +288,20 @@ __global__ void k_reduce_b(const double* partials, int np, double* out) {
 // omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; partials of r_r . r_r;
 // save[r] = num[r]; r32 (may be NULL): r_r rounded to FP32, vector r at r * ld32
 // (the next V-cycle's right-hand side block)
+// x = NULL: the step x += omega p is left to the next direction update
+// (k_cg_p_zf_b) or k_cg_x_step, and omega is stored in alpha[q] instead.
 __global__ void k_cg_xr_b(double* x, double* r, const double* p, const double* v, const double* num,
                           const double* den, int64_t n, int64_t ld, double* partials, double* save,
-                          const int* active, float* r32, int64_t ld32) {
+                          const int* active, float* r32, int64_t ld32, double* alpha) {
   const int q = blockIdx.y;
   const int64_t o = q * ld;
   float* const r32q = r32 ? r32 + q * ld32 : nullptr;
   double acc = 0.0;
   if (active[q]) {
     const double omega = num[q] / den[q];
+    if (!x && blockIdx.x == 0 && threadIdx.x == 0) alpha[q] = omega;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-      x[o + i] += omega * p[o + i];
+      if (x) x[o + i] += omega * p[o + i];
       const double ri = r[o + i] - omega * v[o + i];
       r[o + i] = ri;
       if (r32q) r32q[i] = (float)ri;
@@ -330,16 +333,38 @@ __global__ void k_dot_zf_b(const double* x, const float* z, int64_t n, int64_t l
   if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 // p_r = z_r + beta_r p_r with z in FP32 (vector r at r * ldz), beta_r =
-// num[r] / den[r]; den = NULL: p_r = z_r (the first direction)
+// num[r] / den[r]; den = NULL: p_r = z_r (the first direction).  x != NULL:
+// first the previous iteration's step x_r += alpha[r] p_r (deferred by
+// k_cg_xr_b), with the same p_r values.
 __global__ void k_cg_p_zf_b(double* p, const float* z, const double* num, const double* den, int64_t n,
-                            int64_t ld, int64_t ldz, const int* active) {
+                            int64_t ld, int64_t ldz, const int* active, double* x, const double* alpha) {
   const int q = blockIdx.y;
   if (den && !active[q]) return;  // the first direction is set for every vector
   const double beta = den ? num[q] / den[q] : 0.0;
   double* const pq = p + q * ld;
   const float* const zq = z + q * ldz;
+  if (x) {
+    const double a = alpha[q];
+    double* const xq = x + q * ld;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      const double pi = pq[i];
+      xq[i] += a * pi;
+      pq[i] = den ? (double)zq[i] + beta * pi : (double)zq[i];
+    }
+    return;
+  }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     pq[i] = den ? (double)zq[i] + beta * pq[i] : (double)zq[i];
+}
+// x_r += alpha[r] p_r for the vectors r in mask (their deferred last step)
+__global__ void k_cg_x_step(double* x, const double* p, const double* alpha, int64_t n, int64_t ld, uint64_t mask) {
+  const int q = blockIdx.y;
+  if (!((mask >> q) & 1)) return;
+  const double a = alpha[q];
+  double* const xq = x + q * ld;
+  const double* const pq = p + q * ld;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    xq[i] += a * pq[i];
 }
 // p_r = z_r + beta_r p_r, beta_r = (+-) num[r] / den[r]
 __global__ void k_cg_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld,
@@ -394,16 +419,24 @@ int vec_dot_zf_b(const double* x, const float* z, int64_t n, int64_t ld, int64_t
   return check_launch("reduce_b");
 }
 int cg_update_p_zf_b(double* p, const float* z, const double* num, const double* den, int64_t n, int64_t ld,
-                     int64_t ldz, int nrhs, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_p_zf_b, dim3(grid_for(n), nrhs), kBlock, 0, s, p, z, num, den, n, ld, ldz, active);
+                     int64_t ldz, int nrhs, const int* active, hipStream_t s, double* x, const double* alpha) {
+  hipLaunchKernelGGL(k_cg_p_zf_b, dim3(grid_for(n), nrhs), kBlock, 0, s, p, z, num, den, n, ld, ldz, active, x,
+                     alpha);
   return check_launch("cg_p_zf_b");
+}
+int cg_step_x_b(double* x, const double* p, const double* alpha, int64_t n, int64_t ld, int nrhs, uint64_t mask,
+                hipStream_t s) {
+  if (!mask || nrhs < 1) return HMG_OK;
+  hipLaunchKernelGGL(k_cg_x_step, dim3(grid_for(n), nrhs), kBlock, 0, s, x, p, alpha, n, ld, mask);
+  return check_launch("cg_x_step");
 }
 int cg_update_xr_b(double* x, double* r, const double* p, const double* v, const double* num, const double* den,
                    int64_t n, int64_t ld, int nrhs, double* partials, double* rr, double* save, const int* active,
-                   hipStream_t s, float* r32, int64_t ld32) {
+                   hipStream_t s, float* r32, int64_t ld32, double* alpha) {
+  if (!x && !alpha) return fail(HMG_ERR_INVALID, "internal: deferred CG step without alpha");
   const unsigned g = grid_for_b(n);
   hipLaunchKernelGGL(k_cg_xr_b, dim3(g, nrhs), kBlock, 0, s, x, r, p, v, num, den, n, ld, partials, save, active,
-                     r32, ld32);
+                     r32, ld32, alpha);
   TRY(check_launch("cg_xr_b"));
   hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)partials, (int)g, rr);
   return check_launch("reduce_b");

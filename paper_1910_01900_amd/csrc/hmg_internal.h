@@ -382,16 +382,23 @@ int vec_mul3_b(int prec, double a, const void* d, const void* b, void* z, int64_
 int vec_dot_b(const double* x, const double* y, int64_t n, int64_t ld, int nrhs, double* partials, double* out,
               hipStream_t s);
 // omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; rr[r] = r_r . r_r; save[r] = num[r];
-// r32 (may be NULL): every r_r rounded to FP32 as well, vector r at r * ld32
+// r32 (may be NULL): every r_r rounded to FP32 as well, vector r at r * ld32;
+// x = NULL: the x step is deferred, omega_r stored in alpha[r] (cg_update_p_zf_b
+// or cg_step_x_b take it)
 int cg_update_xr_b(double* x, double* r, const double* p, const double* v, const double* num, const double* den,
                    int64_t n, int64_t ld, int nrhs, double* partials, double* rr, double* save, const int* active,
-                   hipStream_t s, float* r32 = nullptr, int64_t ld32 = 0);
+                   hipStream_t s, float* r32 = nullptr, int64_t ld32 = 0, double* alpha = nullptr);
 // out[r] = x_r . z_r with z in FP32 (vector r at r * ldz), products in FP64
 int vec_dot_zf_b(const double* x, const float* z, int64_t n, int64_t ld, int64_t ldz, int nrhs, double* partials,
                  double* out, hipStream_t s);
-// p_r = z_r + (num[r] / den[r]) p_r with z in FP32 (den NULL: p_r = z_r)
+// p_r = z_r + (num[r] / den[r]) p_r with z in FP32 (den NULL: p_r = z_r);
+// x != NULL: first x_r += alpha[r] p_r (the deferred step of the last update)
 int cg_update_p_zf_b(double* p, const float* z, const double* num, const double* den, int64_t n, int64_t ld,
-                     int64_t ldz, int nrhs, const int* active, hipStream_t s);
+                     int64_t ldz, int nrhs, const int* active, hipStream_t s, double* x = nullptr,
+                     const double* alpha = nullptr);
+// x_r += alpha[r] p_r for the vectors r set in mask (deferred steps)
+int cg_step_x_b(double* x, const double* p, const double* alpha, int64_t n, int64_t ld, int nrhs, uint64_t mask,
+                hipStream_t s);
 // p_r = z_r + beta_r p_r, beta_r = num[r] / den[r] (negated if `negate`)
 int cg_update_p_b(double* p, const double* z, const double* num, const double* den, int64_t n, int64_t ld, int nrhs,
                   const int* active, bool negate, hipStream_t s);

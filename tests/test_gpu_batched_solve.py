@@ -106,6 +106,26 @@ def test_batched_solve_stops_each_vector_on_its_own():
     assert bool((X[:, H.n_dofs:] == 0).all())
 
 
+@pytest.mark.parametrize("mg_prec", [hmg.F64, hmg.F32])
+def test_batched_solve_stopped_by_maxit_returns_its_last_iterate(mg_prec):
+    """After maxit iterations (HMG_NOT_CONVERGED) every vector holds the
+    iterate whose recursive residual the stats report: b - A x recomputed by
+    the oracle agrees with rn (with the FP32 V-cycle the x step of an update
+    waits for the next direction update, so the last one is applied at the
+    end)."""
+    hm, om = meshes((4, 4, 2), 3, True)
+    H = hmg.Hierarchy(hm, "cph", pseq=1, h_min=1, mg_prec=mg_prec, max_rhs=3)
+    B = _block(H, [86, 87, 88])
+    for maxit in (1, 3):
+        X, st = H.solve_batched(B, rtol=1e-14, maxit=maxit, allow_not_converged=True)
+        for q in range(3):
+            b, x = to_np(B[q, :H.n_dofs]), to_np(X[q, :H.n_dofs])
+            true = np.linalg.norm(b - sipg.apply(om, 3, x).ravel())
+            print("maxit %d vector %d: %s, true residual %.6e" % (maxit, q, st[q], true))
+            assert st[q]["status"] == "HMG_NOT_CONVERGED" and st[q]["iters"] == maxit
+            assert abs(true - st[q]["rn"]) <= 1e-9 * st[q]["r0"]
+
+
 def test_batched_solve_of_blocks_with_a_wider_stride():
     """Blocks whose row stride is the solver's own are solved in place,
     others are copied in and out: both give the same iterates bit for bit,
