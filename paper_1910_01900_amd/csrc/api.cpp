@@ -1696,7 +1696,7 @@ extern "C" int hmg_pcg_solve_batched(hmg_hierarchy* H, int nrhs, const double* b
     }
     if (double* const db = H->dotb()) {  // p.(A p) summed per work item by the apply
       TRY(launch_operator_batched(A, OP_DOT, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s, db));
-      TRY(reduce_strided(db, A->n_el, nrhs, s2, s));
+      TRY(reduce_strided(db, A->n_el, nrhs, s2, part, s));
     } else {
       TRY(launch_operator_batched(A, OP_APPLY, nrhs, L, P, V, nullptr, nullptr, 0, 0, nullptr, s));
       TRY(vec_dot_b(P, V, n, L, nrhs, part, s2, s));

@@ -74,14 +74,17 @@ __global__ void k_reduce(const double* partials, int np, double* out) {
   double s = block_reduce(acc);
   if (threadIdx.x == 0) *out = s;
 }
-// Block r: out[r] = sum over j < n of partials[r + nrhs * j] (per-thread
-// sums in a fixed order, then the block's fixed tree).
-__global__ void k_reduce_strided(const double* partials, int64_t n, int nrhs, double* out) {
-  const int r = blockIdx.x;
+// Block (b, r): tmp[r * gridDim.x + b] = sum over j = b * blockDim.x + t
+// + k * gridDim.x * blockDim.x < n of partials[r + nrhs * j] (per-thread
+// sums in a fixed order, then the block's fixed tree); k_reduce_b then sums
+// each vector's gridDim.x values.
+__global__ void k_reduce_strided(const double* partials, int64_t n, int nrhs, double* tmp) {
+  const int r = blockIdx.y;
   double acc = 0.0;
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) acc += partials[r + (int64_t)nrhs * j];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    acc += partials[r + (int64_t)nrhs * j];
   double s = block_reduce(acc);
-  if (threadIdx.x == 0) out[r] = s;
+  if (threadIdx.x == 0) tmp[r * gridDim.x + blockIdx.x] = s;
 }
 // SplitMix64 (Steele, Lea, Flood 2014): output i = mix(seed + (i+1)*golden)
 template <typename T>
@@ -207,11 +210,6 @@ int reduce_partials(const double* partials, int np, double* out, hipStream_t s) 
   hipLaunchKernelGGL(k_reduce, 1, 1024, 0, s, partials, np, out);
   return check_launch("reduce");
 }
-int reduce_strided(const double* partials, int64_t n, int nrhs, double* out, hipStream_t s) {
-  if (nrhs < 1) return HMG_OK;
-  hipLaunchKernelGGL(k_reduce_strided, nrhs, 1024, 0, s, partials, n, nrhs, out);
-  return check_launch("reduce_strided");
-}
 int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
             hipStream_t s) {
   const unsigned g = dot_grid(n);
@@ -284,6 +282,15 @@ __global__ void k_reduce_b(const double* partials, int np, double* out) {
   for (int i = threadIdx.x; i < np; i += blockDim.x) acc += pr[i];
   double s = block_reduce(acc);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+int reduce_strided(const double* partials, int64_t n, int nrhs, double* out, double* tmp, hipStream_t s) {
+  if (nrhs < 1) return HMG_OK;
+  const int64_t want = (n + kBlock - 1) / kBlock;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kPartialsB));
+  hipLaunchKernelGGL(k_reduce_strided, dim3(g, nrhs), kBlock, 0, s, partials, n, nrhs, tmp);
+  TRY(check_launch("reduce_strided"));
+  hipLaunchKernelGGL(k_reduce_b, nrhs, 1024, 0, s, (const double*)tmp, (int)g, out);
+  return check_launch("reduce_b");
 }
 // omega_r = num[r] / den[r]; x_r += omega_r p_r; r_r -= omega_r v_r; partials of r_r . r_r;
 // save[r] = num[r]; r32 (may be NULL): r_r rounded to FP32, vector r at r * ld32

@@ -355,8 +355,9 @@ int vec_convert_gated(int from, const void* x, int to, void* y, int64_t n, const
 int vec_dot(int prec, const void* x, const void* y, int64_t n, double* partials, double* out,
             hipStream_t s);
 int reduce_partials(const double* partials, int nparts, double* out, hipStream_t s);
-// out[r] = sum over j < n of partials[r + nrhs * j], r < nrhs (fixed order)
-int reduce_strided(const double* partials, int64_t n, int nrhs, double* out, hipStream_t s);
+// out[r] = sum over j < n of partials[r + nrhs * j], r < nrhs (fixed order;
+// tmp: nrhs * kPartialsB values)
+int reduce_strided(const double* partials, int64_t n, int nrhs, double* out, double* tmp, hipStream_t s);
 // CG updates with device scalars (all FP64): see kernels for formulas
 // omega = *num / *den; x += omega p; r -= omega v; *save = *num if save;
 // returns the number of partials of r.r written (>0) or an error (<0)
