@@ -32,6 +32,10 @@ WORKLOADS = {
     "curved_k4_64": dict(nel=(64, 64, 64), degree=4, deformed=True, amp=0.05, tau_scale_seed=None, nrhs=1),
     "curved_k7_48": dict(nel=(48, 48, 48), degree=7, deformed=True, amp=0.05, tau_scale_seed=5, nrhs=8),
     "curved_k5_48": dict(nel=(48, 48, 48), degree=5, deformed=True, amp=0.05, tau_scale_seed=None, nrhs=1),
+    # Cartesian meshes of the same sizes (no stored geometry): the affine
+    # kernels that the batches of unit cubes run
+    "cartesian_k4_64": dict(nel=(64, 64, 64), degree=4, deformed=False, amp=0.0, tau_scale_seed=None, nrhs=1),
+    "cartesian_k7_48": dict(nel=(48, 48, 48), degree=7, deformed=False, amp=0.0, tau_scale_seed=None, nrhs=1),
 }
 
 
