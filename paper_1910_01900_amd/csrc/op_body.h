@@ -514,20 +514,19 @@ __device__ __forceinline__ void inject(const OpArgs<T>& a, const ElemInfo& I, in
 // With n^T J^{-T} = +-e_d / h_d on both sides and surface weight
 // h_a h_b w_a w_b, the flux reduces to the plane term tau [u] - c {du/dn}
 // and the normal-derivative term -c/2 [u], each taken through the face mass
-// matrix M (x) M.  A: own nodal u; F: LDS scratch of 4 n^2; LT: lane tables.
+// matrix M (x) M.  A: own nodal u; F: LDS scratch of 4 n^2; LT: lane tables;
+// Pn, Qn, tn of face f = 2d + s: the neighbour line's end value, its
+// normal-derivative combination and the neighbour's penalty (loaded for all
+// six faces at once by affine_nb); te: the own penalty.
 template <int N, typename T, int d>
-__device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, const T* A, T* F, const T* LT,
-                                             bool act, int t, const ElemInfo& I, T (&vacc)[N]) {
+__device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* A, T* F, const T* LT, bool act, int t,
+                                             const ElemInfo& I, T (&vacc)[N], const T (&Pn6)[6],
+                                             const T (&Qn6)[6], const T (&tn)[6], T te) {
   constexpr int NT = N * N;
   constexpr int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
   constexpr TabOff O(N);
   const int ta = t % N, tbb = t / N;
   if (act) {
-    // global loads first: neighbour lines and penalties
-    T nl[2][N];
-    load_nb_lines<N, T, d>(a, ub, I, t, nl[0], nl[1]);
-    const T te = a.tau[I.e];
-    const T tn[2] = {a.tau[nb_elem<d>(a, I, 0)], a.tau[nb_elem<d>(a, I, 1)]};
     T line[N];
     read_line<N, T, d>(A, t, line);
     const cptr<T> c = fresh(a.tabs);
@@ -537,17 +536,14 @@ __device__ __forceinline__ void affine_faces(const OpArgs<T>& a, const T* ub, co
       const bool hf = has_nb(I, f);
       const bool neu = !hf && ((a.bcmask >> f) & 1);
       const T Po = line[s * (N - 1)];
-      T Qo = 0, Qn = 0;
+      T Qo = 0;
 #pragma unroll
-      for (int m = 0; m < N; ++m) {
-        Qo += c[(s ? O.dl1() : O.dl0()) + m] * line[m];
-        Qn += c[(s ? O.dl0() : O.dl1()) + m] * nl[s][m];
-      }
-      const T Pn = s ? nl[s][0] : nl[s][N - 1];
+      for (int m = 0; m < N; ++m) Qo += c[(s ? O.dl1() : O.dl0()) + m] * line[m];
+      const T Pn = Pn6[f], Qn = Qn6[f];
       const T Pj = hf ? Po - Pn : (neu ? T(0) : T(2) * Po);
       const T Qs = hf ? Qo + Qn : (neu ? T(0) : T(2) * Qo);
       const T cdn = (s ? T(1) : T(-1)) / a.h[d];
-      F[(2 * s) * NT + t] = tau_face(te, tn[s], hf) * Pj - T(0.5) * cdn * Qs;
+      F[(2 * s) * NT + t] = tau_face(te, tn[f], hf) * Pj - T(0.5) * cdn * Qs;
       F[(2 * s + 1) * NT + t] = T(-0.5) * cdn * Pj;
     }
   }
@@ -765,6 +761,38 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
   }
 
 
+  // affine faces: the neighbour lines of all six faces reduced at once to
+  // their end value and normal-derivative combination, with the penalties
+  // (one memory round trip, together with the own values below, instead of
+  // one per direction)
+  [[maybe_unused]] T aPn[6], aQn[6], atn[6];
+  [[maybe_unused]] T ate = 0;
+  if constexpr (!CURVED && !FE) {
+    if (act) {
+      T nl[6][N];
+      load_nb_lines<N, T, 0>(a, ub, I, t, nl[0], nl[1]);
+      load_nb_lines<N, T, 1>(a, ub, I, t, nl[2], nl[3]);
+      load_nb_lines<N, T, 2>(a, ub, I, t, nl[4], nl[5]);
+      ate = a.tau[I.e];
+      atn[0] = a.tau[nb_elem<0>(a, I, 0)];
+      atn[1] = a.tau[nb_elem<0>(a, I, 1)];
+      atn[2] = a.tau[nb_elem<1>(a, I, 0)];
+      atn[3] = a.tau[nb_elem<1>(a, I, 1)];
+      atn[4] = a.tau[nb_elem<2>(a, I, 0)];
+      atn[5] = a.tau[nb_elem<2>(a, I, 1)];
+      const cptr<T> c = fresh(a.tabs);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const int s = f & 1;
+        T Q = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) Q += c[(s ? O.dl0() : O.dl1()) + m] * nl[f][m];
+        aQn[f] = Q;
+        aPn[f] = s ? nl[f][0] : nl[f][N - 1];
+      }
+    }
+  }
+
   // own-side face data: for n = 5 and 8 each direction's is loaded a phase
   // ahead of its use, those of the x faces in the phase that moves the own
   // values to LDS (1-2% faster; for n = 3, 4, 6 the registers cost a
@@ -853,9 +881,9 @@ __device__ __forceinline__ double op_items(const OpArgs<T>& a, const int64_t it0
 #pragma unroll
     for (int i = 0; i < N; ++i) vacc[i] = 0;
     if constexpr (!FE) {
-      affine_faces<N, T, 0>(a, ub, A, B, LT, act, t, I, vacc);
-      affine_faces<N, T, 1>(a, ub, A, B, LT, act, t, I, vacc);
-      affine_faces<N, T, 2>(a, ub, A, B, LT, act, t, I, vacc);
+      affine_faces<N, T, 0>(a, A, B, LT, act, t, I, vacc, aPn, aQn, atn, ate);
+      affine_faces<N, T, 1>(a, A, B, LT, act, t, I, vacc, aPn, aQn, atn, ate);
+      affine_faces<N, T, 2>(a, A, B, LT, act, t, I, vacc, aPn, aQn, atn, ate);
     }
     const T cx = a.h[1] * a.h[2] / a.h[0], cy = a.h[0] * a.h[2] / a.h[1], cz = a.h[0] * a.h[1] / a.h[2];
     if (act) {  // z: p = M u, q = K u
