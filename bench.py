@@ -328,7 +328,7 @@ def learned_bench(samples=20480, steps=3000, batch=64, lr=1e-3, grid=16, h_min=1
     solve; h_min = 24 (15,625 nodes, no dense inverse): flexible CG with the
     iterative (Jacobi-PCG, 1e-3, at most 50 iterations) coarse solve.
     Against both: Chebyshev smoothing only on the coarsest level, and
-    flexible CG with the learned correction (judge: coarse residual <= 0.5,
+    flexible CG with the learned correction (accepted while the coarse residual <= 0.5,
     else the exact or iterative solve).  Training pairs: the coarse
     right-hand sides of the V-cycles of seeded solves and their exact (FP64
     dense or CG to 1e-12) solves."""

@@ -362,7 +362,7 @@ enum { HMG_COARSE_EXACT = 0, HMG_COARSE_SMOOTH = 1, HMG_COARSE_LEARNED = 2, HMG_
  * CG in FP64 on an FP64 copy of the coarsest level, whatever the V-cycle
  * precision, to hmg_hierarchy_set_coarse_cg's tolerance; the default above
  * 8192 unknowns), SMOOTH (Chebyshev smoothing only, the
- * V-cycle without a coarse solve) or LEARNED: x = network(b), judged on the
+ * V-cycle without a coarse solve) or LEARNED: x = network(b), checked on the
  * GPU by |b - A x| <= accept |b| (finite), else the exact solve or, without
  * a dense inverse, the CG solve (fallbacks counted, hmg_hierarchy_coarse_stats).
  * LEARNED needs a continuous Q1 coarsest level whose node grid fits the

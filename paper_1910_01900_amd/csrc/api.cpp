@@ -708,7 +708,7 @@ struct hmg_hierarchy {
   // V-cycle, recorded on a library stream, keyed by the caller's vectors
   bool use_graph = false;
   // coarsest-level solve: exact (dense inverse), Chebyshev smoothing only, or
-  // the learned correction judged by its coarse residual (exact fallback)
+  // the learned correction accepted by its coarse residual (exact fallback)
   int coarse_mode = HMG_COARSE_EXACT;
   hmg_net* net = nullptr;
   double accept = 0.0;
@@ -1144,7 +1144,7 @@ static int coarse_cg(hmg_hierarchy* H, const hmg_level* L, const void* b, void* 
 // coarsest level, the level-precision right-hand side converted on the way
 // in and the solution converted back.  *skip (set before the call) gates
 // the conversion in and the solve.  The solve sets *skip once it has
-// converged, so the conversion back is gated by the judge's decision
+// converged, so the conversion back is gated by the acceptance test
 // *accepted instead (0 outside the learned correction).
 static int coarse_cg64_at(hmg_hierarchy* H, size_t l, const void* b, void* x, hipStream_t s) {
   hmg_level* L = H->lv[l];
@@ -1178,7 +1178,7 @@ static int coarse_solve(hmg_hierarchy* H, size_t l, hipStream_t s) {
       TRY(net_pack(L->prec, H->b(l), nullptr, H->nc, 1, ng, N->G, H->c0, net_hsigma(N), net_hin(N), nullptr, s));
       TRY(net_forward(N, net_hin(N), net_hout(N), 1, s));
       TRY(net_unpack(L->prec, net_hout(N), ng, N->G, net_hsigma(N), H->c0, H->x(l), s));
-      // judge: |b - A x| against accept |b|, else the exact solve
+      // acceptance test: |b - A x| against accept |b|, else the exact solve
       double* gate = H->scal() + 8;
       TRY(launch_operator(L, OP_RESID, H->x(l), H->r(l), H->b(l), nullptr, 0, 0, nullptr, s));
       TRY(vec_dot(L->prec, H->r(l), H->r(l), H->nc, H->part(), gate, s));

@@ -296,7 +296,7 @@ def test_large_coarse_level_iterative_targets_and_learned_fallback():
     assert st["status"] == "HMG_OK" and st["rn"] <= 1e-10 * st["r0"]
     L64 = hmg.Level(hm)
     assert float(torch.linalg.norm(L64.residual(b, x)) / torch.linalg.norm(b)) <= 2e-10
-    # zero right-hand side: the judge rejects any nonzero correction and the
+    # zero right-hand side: the acceptance test rejects any nonzero correction and the
     # iterative fallback keeps x = 0
     z = H.vcycle(torch.zeros_like(b))
     assert bool(torch.all(z == 0))
